@@ -1,0 +1,343 @@
+"""Seeded synthetic inputs for the elasticity solve: problem descriptions only.
+
+This module builds the input data of a solve (grid, stiffness field,
+eigenstrain, boundary data) for the workloads of the paper's examples and for
+tests.  It holds none of the solver's arithmetic: no finite difference, no
+operator, no transfer.  Both the CPU oracle and the GPU library consume what it
+produces, so it must stay free of either's code.
+
+Layout conventions (shared input format):
+  * ``n``: nodes per axis including both ends, ``n[2] == 1`` in 2D.
+  * A periodic axis stores ``n - 1`` unique nodes (node ``n-1`` is node 0).
+  * Fields are float64 arrays ``[comp][z][y][x]`` over the stored nodes.
+  * Isotropic moduli: 2 components (lambda, mu).  Anisotropic moduli: the
+    upper triangle, row-major, of the symmetric Voigt matrix (21 in 3D with
+    Voigt order 11,22,33,23,31,12; 6 in 2D with order 11,22,12) -- the layout
+    of Sec. 4.3 (eq. for the cubic Voigt modulus and the Voigt vectors).
+  * Eigenstrain: tensor components (not engineering shears) in Voigt order,
+    6 in 3D, 3 in 2D.
+  * Face data (face ``2*axis + side``): ``d`` components over the face's
+    nodes, shaped like a field with the face's normal axis of extent 1;
+    prescribed displacement on Dirichlet faces, prescribed traction on
+    traction faces.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+DIRICHLET = "dirichlet"
+TRACTION = "traction"
+PERIODIC = "periodic"
+
+
+@dataclasses.dataclass
+class Problem:
+    dim: int
+    n: Tuple[int, int, int]
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    bc: Tuple[str, str, str, str, str, str]
+    kind: str                      # "iso" or "aniso"
+    C: np.ndarray                  # [nc][mz][my][mx]
+    eps0: Optional[np.ndarray] = None
+    b: Optional[np.ndarray] = None
+    face: Dict[int, np.ndarray] = dataclasses.field(default_factory=dict)
+    name: str = ""
+
+    @property
+    def periodic(self) -> Tuple[bool, bool, bool]:
+        return tuple(a < self.dim and self.bc[2 * a] == PERIODIC for a in range(3))
+
+    @property
+    def m(self) -> Tuple[int, int, int]:
+        """Stored (unique) nodes per axis."""
+        return tuple((self.n[a] - 1 if self.periodic[a] else self.n[a]) if a < self.dim else 1
+                     for a in range(3))
+
+    @property
+    def h(self) -> Tuple[float, float, float]:
+        return tuple((self.hi[a] - self.lo[a]) / (self.n[a] - 1) if a < self.dim else 1.0 for a in range(3))
+
+    @property
+    def nodes(self) -> int:
+        m = self.m
+        return m[0] * m[1] * m[2]
+
+    def coords(self):
+        """Node coordinates (x, y, z) broadcastable to [mz][my][mx]."""
+        m, h = self.m, self.h
+        x = self.lo[0] + h[0] * np.arange(m[0])
+        y = self.lo[1] + h[1] * np.arange(m[1])
+        z = self.lo[2] + h[2] * np.arange(m[2]) if self.dim == 3 else np.zeros(1)
+        return x[None, None, :], y[None, :, None], z[:, None, None]
+
+    def face_shape(self, f: int) -> Tuple[int, int, int]:
+        m = list(self.m)[::-1]          # [mz, my, mx]
+        m[2 - f // 2] = 1
+        return tuple(m)
+
+    def dirichlet_count(self) -> int:
+        """Stored nodes on at least one Dirichlet face."""
+        m = self.m
+        mask = np.zeros(m[::-1], dtype=bool)
+        for f in range(2 * self.dim):
+            if self.bc[f] != DIRICHLET:
+                continue
+            a = f // 2
+            sl = [slice(None)] * 3
+            sl[2 - a] = 0 if f % 2 == 0 else m[a] - 1
+            mask[tuple(sl)] = True
+        return int(mask.sum())
+
+    def dofs(self) -> int:
+        """Unknowns: d x stored nodes not on a Dirichlet face."""
+        return self.dim * (self.nodes - self.dirichlet_count())
+
+
+# --------------------------------------------------------------------------
+# stiffness tensors (input construction only)
+# --------------------------------------------------------------------------
+
+_V3 = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (1, 2): 3, (2, 1): 3, (0, 2): 4, (2, 0): 4, (0, 1): 5, (1, 0): 5}
+
+
+def cubic_voigt(c11: float, c12: float, c44: float) -> np.ndarray:
+    """6x6 Voigt matrix of a cubic crystal in its own frame (Sec. 4.3)."""
+    V = np.zeros((6, 6))
+    V[:3, :3] = c12
+    np.fill_diagonal(V[:3, :3], c11)
+    V[3, 3] = V[4, 4] = V[5, 5] = c44
+    return V
+
+
+def voigt_to_tensor(V: np.ndarray) -> np.ndarray:
+    T = np.zeros((3, 3, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                for l in range(3):
+                    T[i, j, k, l] = V[_V3[i, j], _V3[k, l]]
+    return T
+
+
+def tensor_to_voigt(T: np.ndarray) -> np.ndarray:
+    V = np.zeros((6, 6))
+    for (i, j), I in _V3.items():
+        for (k, l), J in _V3.items():
+            V[I, J] = T[i, j, k, l]
+    return V
+
+
+def rotate_voigt(V: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """C'_pqst = R_pi R_qj C_ijkl R_sk R_tl (Sec. 4.3, rotated modulus)."""
+    T = voigt_to_tensor(V)
+    return tensor_to_voigt(np.einsum("pi,qj,sk,tl,ijkl->pqst", R, R, R, R, T, optimize=True))
+
+
+def upper21(V: np.ndarray) -> np.ndarray:
+    n = V.shape[0]
+    return np.array([V[I, J] for I in range(n) for J in range(I, n)])
+
+
+def shoemake_rotation(u: Sequence[float]) -> np.ndarray:
+    """Uniform random rotation from three U[0,1) numbers (Shoemake, Graphics Gems III, 1992)."""
+    u1, u2, u3 = u
+    a, b = math.sqrt(1.0 - u1), math.sqrt(u1)
+    x, y = a * math.sin(2 * math.pi * u2), a * math.cos(2 * math.pi * u2)
+    z, w = b * math.sin(2 * math.pi * u3), b * math.cos(2 * math.pi * u3)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+CUBIC = (1.68, 1.21, 0.75)   # C11, C12, C44 of the polycrystal example (Sec. 4.3)
+
+
+def _tanh_step(s):
+    return 0.5 * (1.0 - np.tanh(s))
+
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+def inclusion_2d(n: int = 65, width: float = 0.02, radius: float = 0.25, eigen: float = 1e-3) -> Problem:
+    """2D plane strain, [0,1]^2: isotropic matrix (mu=1, lambda=1.5) with a
+    circular inclusion (mu=2, lambda=3) blended by a tanh of the given width,
+    isotropic in-plane eigenstrain inside, u=0 on the bottom face, the other
+    faces traction-free."""
+    p = Problem(dim=2, n=(n, n, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+                bc=(TRACTION, TRACTION, DIRICHLET, TRACTION, TRACTION, TRACTION),
+                kind="iso", C=np.zeros(0), name=f"inclusion2d_{n}")
+    x, y, _ = p.coords()
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    eta = _tanh_step((r - radius) / width)               # [1][my][mx]
+    lam = 1.5 + (3.0 - 1.5) * eta
+    mu = 1.0 + (2.0 - 1.0) * eta
+    p.C = np.stack([lam, mu]).astype(np.float64)
+    p.eps0 = np.stack([eigen * eta, eigen * eta, np.zeros_like(eta)]).astype(np.float64)
+    return p
+
+
+def _voronoi_moduli(p: Problem, centers: np.ndarray, rots: Sequence[np.ndarray], width_cells: float,
+                    base: np.ndarray, scale=None) -> np.ndarray:
+    """Voronoi polycrystal, per-grain rotated moduli, grain boundaries
+    smoothed by tanh of the distance to the bisector plane (transition about
+    two cells), mixture rule C = sum g_n C_n / sum g_n (Sec. 4.3)."""
+    G = len(centers)
+    grainC = np.stack([upper21(rotate_voigt(base, R)) for R in rots])      # [G][21]
+    m = p.m
+    x, y, _ = p.coords()
+    hmin = min(p.h[:p.dim])
+    Lper = [p.hi[a] - p.lo[a] for a in range(3)]
+    out = np.empty((21, m[2], m[1], m[0]))
+    zs = p.lo[2] + p.h[2] * np.arange(m[2])
+    chunk = max(1, int(2 ** 22 // (m[0] * m[1] * max(G, 1))))
+    for z0 in range(0, m[2], chunk):
+        z = zs[z0:z0 + chunk][:, None, None]
+        pos = [np.broadcast_to(x, (len(z), m[1], m[0])), np.broadcast_to(y, (len(z), m[1], m[0])),
+               np.broadcast_to(z, (len(z), m[1], m[0]))]
+        # per-seed displacement vectors with the minimum image on periodic axes
+        dvec = []
+        for a in range(3):
+            dv = pos[a][None] - centers[:, a][:, None, None, None]
+            if p.periodic[a]:
+                dv = dv - Lper[a] * np.round(dv / Lper[a])
+            dvec.append(dv)
+        d2 = dvec[0] ** 2 + dvec[1] ** 2 + dvec[2] ** 2                       # [G][...]
+        a_idx = np.argmin(d2, axis=0)
+        d2a = np.take_along_axis(d2, a_idx[None], 0)[0]
+        # image positions of the seeds relative to the node: x - dvec
+        sep2 = np.zeros_like(d2)
+        for a in range(3):
+            pa = np.take_along_axis(dvec[a], a_idx[None], 0)[0]
+            sep2 += (dvec[a] - pa[None]) ** 2
+        sep = np.sqrt(np.maximum(sep2, 1e-300))
+        delta = np.where(sep2 > 0, (d2 - d2a[None]) / (2.0 * sep), 0.0)
+        g = _tanh_step(delta / (0.5 * width_cells * hmin))
+        g = g / g.sum(axis=0, keepdims=True)
+        blk = np.einsum("g...,gc->c...", g, grainC, optimize=True)
+        if scale is not None:
+            blk = blk * scale[z0:z0 + chunk][None]
+        out[:, z0:z0 + chunk] = blk
+    return out
+
+
+def polycrystal_3d(n: int = 129, grains: int = 16, seed: int = 2002, strain: float = 1e-3,
+                   inclusion: Optional[Tuple[float, float]] = None) -> Problem:
+    """3D Voronoi polycrystal on [0,1]^3 with cubic grains (C11=1.68,
+    C12=1.21, C44=0.75) rotated uniformly at random, periodic x and y faces,
+    u = 0 on z = 0 and u = (0, 0, strain) on z = 1.
+
+    ``inclusion=(stiffening, eigenstrain)`` adds a sphere of radius 0.25 at
+    the centre: C = (1 + (stiffening-1) eta) C_poly and isotropic eigenstrain
+    ``eigenstrain * eta`` with eta a tanh step of width 2 cells."""
+    rng = np.random.default_rng(seed)
+    centers = rng.random((grains, 3))
+    rots = [shoemake_rotation(rng.random(3)) for _ in range(grains)]
+    p = Problem(dim=3, n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, DIRICHLET, DIRICHLET),
+                kind="aniso", C=np.zeros(0), name=f"polycrystal_{n}_{grains}g")
+    scale = None
+    eta = None
+    if inclusion is not None:
+        x, y, z = p.coords()
+        r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2)
+        eta = _tanh_step((r - 0.25) / (2.0 * p.h[0]))
+        scale = 1.0 + (inclusion[0] - 1.0) * eta
+        p.name += "_sphere"
+    p.C = _voronoi_moduli(p, centers, rots, 2.0, cubic_voigt(*CUBIC), scale)
+    if eta is not None:
+        e = inclusion[1] * eta
+        z0 = np.zeros_like(e)
+        p.eps0 = np.stack([e, e, e, z0, z0, z0])
+    top = np.zeros((3,) + p.face_shape(5))
+    top[2] = strain
+    p.face[5] = top
+    return p
+
+
+def iso_from_lame(lam: np.ndarray, mu: np.ndarray) -> np.ndarray:
+    return np.stack([lam, mu]).astype(np.float64)
+
+
+def random_problem(dim: int, n: Sequence[int], bc: Sequence[str], kind: str, seed: int,
+                   with_eps0: bool = True, with_body: bool = False, with_face_data: bool = True,
+                   smooth: bool = True, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Problem:
+    """Random but well-posed test problem: smooth positive-definite moduli
+    (rotated cubic plus isotropic background, modulated by low-order
+    trigonometric fields, or independent per node when ``smooth`` is false),
+    random smooth eigenstrain, body force and face data."""
+    rng = np.random.default_rng(seed)
+    n3 = tuple(n) + (1,) * (3 - len(n))
+    hi3 = tuple(hi[a] if a < dim else lo[a] for a in range(3))
+    p = Problem(dim=dim, n=n3, lo=tuple(lo), hi=hi3, bc=tuple(bc), kind=kind, C=np.zeros(0),
+                name=f"random{dim}d_{kind}_{seed}")
+    x, y, z = p.coords()
+    m = p.m
+    shape = (m[2], m[1], m[0])
+
+    def field(amp):
+        if not smooth:
+            return amp * rng.uniform(-1, 1, size=shape)
+        k = rng.uniform(0.5, 2.5, size=3)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        f = np.sin(2 * np.pi * k[0] * x + ph[0]) * np.cos(2 * np.pi * k[1] * y + ph[1])
+        if dim == 3:
+            f = f * np.cos(2 * np.pi * k[2] * z + ph[2])
+        return amp * np.broadcast_to(f, shape)
+
+    if kind == "iso":
+        mu = 1.0 + 0.5 * (1 + field(1.0))
+        lam = 1.5 + 0.7 * field(1.0)
+        p.C = iso_from_lame(lam, mu)
+    else:
+        R = shoemake_rotation(rng.random(3))
+        if dim == 3:
+            V = rotate_voigt(cubic_voigt(*CUBIC), R)
+            comps = upper21(V)
+        else:
+            c = rng.uniform(-0.2, 0.2)
+            V2 = np.array([[1.8, 1.1, c], [1.1, 1.6, -0.5 * c], [c, -0.5 * c, 0.7]])
+            comps = np.array([V2[I, J] for I in range(3) for J in range(I, 3)])
+        s = 1.0 + 0.4 * field(1.0)               # positive scale keeps it SPD
+        p.C = np.stack([comps[c] * s for c in range(len(comps))]).astype(np.float64)
+        # add a small SPD isotropic part with its own variation
+        lam_mu = (0.2 + 0.1 * field(1.0), 0.3 + 0.1 * field(1.0))
+        if dim == 3:
+            iso = [(0, lam_mu[0] + 2 * lam_mu[1]), (1, lam_mu[0]), (2, lam_mu[0]), (6, lam_mu[0] + 2 * lam_mu[1]),
+                   (7, lam_mu[0]), (11, lam_mu[0] + 2 * lam_mu[1]), (15, lam_mu[1]), (18, lam_mu[1]), (20, lam_mu[1])]
+        else:
+            iso = [(0, lam_mu[0] + 2 * lam_mu[1]), (1, lam_mu[0]), (3, lam_mu[0] + 2 * lam_mu[1]), (5, lam_mu[1])]
+        for c, v in iso:
+            p.C[c] = p.C[c] + v
+    ne = 6 if dim == 3 else 3
+    if with_eps0:
+        p.eps0 = np.stack([field(1e-3) for _ in range(ne)]).astype(np.float64)
+    if with_body:
+        p.b = np.stack([field(1e-2) for _ in range(dim)]).astype(np.float64)
+    if with_face_data:
+        for f in range(2 * dim):
+            if bc[f] == PERIODIC:
+                continue
+            shp = (dim,) + p.face_shape(f)
+            p.face[f] = (1e-3 * rng.uniform(-1, 1, size=shp)).astype(np.float64)
+    return p
+
+
+def plane_strain_voigt(V6: np.ndarray) -> np.ndarray:
+    """3x3 Voigt matrix (order 11, 22, 12) of the in-plane restriction of a 3D
+    stiffness given as its 6x6 Voigt matrix."""
+    sel = [0, 1, 5]
+    return V6[np.ix_(sel, sel)]
+
+
+def upper_tri(V: np.ndarray) -> np.ndarray:
+    """Row-major upper triangle of a symmetric matrix (the stored moduli layout)."""
+    return upper21(V)
