@@ -1,0 +1,181 @@
+/*
+ * emg.h -- C ABI of the MI355X (gfx950) geometric-multigrid solver for the
+ * node-based finite-difference elasticity operator of Runnels, Agrawal,
+ * Zhang and Almgren, "Massively parallel finite difference elasticity using
+ * block-structured adaptive mesh refinement with a geometric multigrid
+ * solver" (arXiv 2001.04789).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an emg_status; EMG_OK (0) on success.  On error
+ *     emg_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this boundary.
+ *   - Grids are node based.  Axis a has n[a] nodes including both ends,
+ *     spacing h[a] = (hi[a] - lo[a]) / (n[a] - 1).  A periodic axis stores
+ *     n[a] - 1 unique nodes (node n[a]-1 is node 0); every other axis stores
+ *     n[a].  m[a] below is that stored count (m[2] = 1 in 2D).
+ *   - Fields are dense structure-of-arrays, component-major:
+ *     field[comp][z][y][x] over the stored nodes, x fastest, no padding.
+ *   - A pointer argument is a host pointer unless the call's `on_device`
+ *     flag is set (then it is a device pointer on the problem's GPU, e.g. a
+ *     torch tensor's data_ptr()).  The library copies what it is given; the
+ *     caller keeps ownership of every buffer it passes.
+ *   - Each problem owns its device memory and one HIP stream (created at
+ *     default priority); all of its work runs on that stream.  Calls on one
+ *     problem must not overlap; different problems may be used from
+ *     different threads.
+ */
+#ifndef EMG_H
+#define EMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EMG_OK = 0,
+  EMG_EINVAL = -1,     /* bad argument, size, layout or boundary-condition combination */
+  EMG_ENOMEM = -2,     /* device allocation failed or HBM budget exceeded */
+  EMG_EDEVICE = -3,    /* a HIP call failed */
+  EMG_ENOTCONV = -4,   /* cycle cap reached; the last iterate and stats are still returned */
+  EMG_EDIVERGED = -5,  /* residual norm became NaN or Inf */
+  EMG_ESTATE = -6      /* call order, e.g. solve before the moduli are set */
+} emg_status;
+
+/* Face boundary types (Sec. 2.1, eqs. elastic_b1 and elastic_b2; periodic
+ * faces of representative volume elements, Sec. 1).  Face f = 2*axis + side
+ * (side 0 = low end, 1 = high end).  Both faces of an axis are periodic or
+ * neither is.  A node on a Dirichlet face has the Dirichlet row; a node on
+ * traction faces only has the sum over those faces of the traction rows. */
+typedef enum { EMG_BC_DIRICHLET = 0, EMG_BC_TRACTION = 1, EMG_BC_PERIODIC = 2 } emg_bc_type;
+
+/* Stored moduli per node (Sec. 2.1.1 reduced constants; Sec. 4.3 Voigt form):
+ *   EMG_MOD_ISO:   2 components, lambda then mu.
+ *   EMG_MOD_ANISO: upper triangle, row-major, of the symmetric Voigt matrix:
+ *                  21 components in 3D (Voigt order 11,22,33,23,31,12),
+ *                  6 in 2D plane strain (order 11,22,12). */
+typedef enum { EMG_MOD_ISO = 0, EMG_MOD_ANISO = 1 } emg_moduli_kind;
+
+typedef enum { EMG_FP64 = 0, EMG_MIXED = 1 } emg_precision;
+
+typedef struct emg_ctx emg_ctx;
+typedef struct emg_problem emg_problem;
+
+typedef struct {
+  int dim;          /* 2 (plane strain) or 3 */
+  int64_t n[3];     /* nodes per axis including both ends; n[2] = 1 in 2D */
+  double lo[3], hi[3];
+  int bc[6];        /* emg_bc_type per face; faces 4,5 are ignored in 2D */
+  int kind;         /* emg_moduli_kind */
+} emg_domain;
+
+typedef struct {
+  double rtol;       /* stop when ||r||_2 / ||r_0||_2 <= rtol (default 1e-10); the norm runs over
+                        non-Dirichlet rows, r_0 is the residual of the Dirichlet lift */
+  int max_cycles;    /* cap on V-cycles (FP64) or refinement iterations (mixed); default 200 */
+  int precision;     /* EMG_FP64: V-cycles in FP64.  EMG_MIXED: FP64 residual and update around
+                        one FP32 V-cycle per iteration, FP64 coarsest solve */
+  int nu1, nu2;      /* damped-Jacobi sweeps before / after the coarse correction (default 2, 2) */
+  double omega;      /* Jacobi damping (default 2/3) */
+  int warm_start;    /* 1: start from the current displacement instead of the Dirichlet lift */
+  int check_every;   /* cycles per device-side launch between host convergence reads (default 4);
+                        cycles after convergence inside a launch are skipped on the device */
+  int use_graph;     /* 1 (default): replay captured HIP graphs; 0: launch kernels eagerly */
+} emg_solve_opts;
+
+typedef struct {
+  int cycles;          /* V-cycles (or refinement iterations) applied to the returned solution */
+  int converged;       /* 1 if rel_res <= rtol */
+  double rel_res;      /* final ||r|| / ||r_0|| (FP64 residual) */
+  double conv_factor;  /* geometric mean reduction per cycle */
+  double solve_seconds;/* wall time of the cycle loop (lift to tolerance) */
+  double setup_seconds;/* wall time of hierarchy setup and right-hand-side assembly in this call */
+  int64_t dofs;        /* d x stored nodes not on a Dirichlet face */
+} emg_solve_stats;
+
+const char *emg_last_error(void);
+void emg_default_opts(emg_solve_opts *opts);
+
+/* Context: binds a HIP device and an HBM budget (0 = no limit) checked at
+ * problem creation against the problem's device footprint. */
+emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out);
+emg_status emg_ctx_destroy(emg_ctx *ctx);
+
+/* Problem on one node grid.  Builds the multigrid hierarchy (levels 0, -1,
+ * -2, ... of Sec. 3.1): all axes halve together while every non-periodic
+ * axis has an even cell count >= 8 and every periodic axis an even stored
+ * node count >= 8; the coarsest level is solved exactly in FP64.
+ * EMG_EINVAL for: dim not 2/3, an axis with fewer than 5 nodes, mismatched
+ * periodic faces, no Dirichlet face (rigid-body null space), fewer than two
+ * levels, or a coarsest level with more than 1536 unknowns.  The device
+ * footprint is allocated here (EMG_ENOMEM if it exceeds the budget). */
+emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem **out);
+emg_status emg_problem_destroy(emg_problem *p);
+/* Replace the problem's stream (a hipStream_t, e.g. torch's current stream
+ * on ROCm).  NULL restores the problem's own stream. */
+emg_status emg_set_stream(emg_problem *p, void *hip_stream);
+/* Bytes of device memory the problem holds. */
+emg_status emg_footprint(const emg_problem *p, size_t *bytes);
+
+/* Inputs of Sec. 2.1 eq. elastic_int: moduli C (layout per emg_moduli_kind),
+ * eigenstrain eps0 (tensor components, not engineering shears, Voigt order,
+ * 6 in 3D / 3 in 2D; NULL = 0), body force b (d components; NULL = 0). */
+emg_status emg_set_moduli(emg_problem *p, const double *C, int on_device);
+emg_status emg_set_eigenstrain(emg_problem *p, const double *eps0, int on_device);
+emg_status emg_set_body_force(emg_problem *p, const double *b, int on_device);
+/* Face data: d components over the face's stored nodes, laid out like a
+ * field whose normal axis has extent 1.  Prescribed displacement u0 on a
+ * Dirichlet face (eq. elastic_b1), prescribed traction t0 on a traction face
+ * (eq. elastic_b2).  NULL = 0.  At a node on several Dirichlet faces the
+ * lowest-numbered face supplies u0. */
+emg_status emg_set_face(emg_problem *p, int face, const double *values, int on_device);
+
+/* Solve D_H(u) = -(D(0) + b) with the boundary operators (Sec. 2.1.1) by
+ * correction-scheme V-cycles (Sec. 3.1) to opts->rtol.  Blocking.
+ * EMG_ENOTCONV / EMG_EDIVERGED still leave the last iterate readable. */
+emg_status emg_solve(emg_problem *p, const emg_solve_opts *opts, emg_solve_stats *stats);
+
+/* Outputs on level 0: displacement (d components) and stress
+ * sigma = C (grad u - eps0) in Voigt order (6 in 3D: 11,22,33,23,31,12;
+ * 3 in 2D: 11,22,12); central differences inside, 3-point one-sided on
+ * non-periodic faces.  Also the assembled right-hand side (d components). */
+emg_status emg_get_displacement(emg_problem *p, double *u, int on_device);
+emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device);
+emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device);
+emg_status emg_get_rhs(emg_problem *p, double *f, int on_device);
+
+/* ---- level-wise steps of the cycle, for verification and timing ----
+ * Level 0 is the input grid, level l the l-th coarsening.  All vector
+ * arguments are DEVICE pointers with d components in the level's layout;
+ * `precision` selects double (EMG_FP64) or float (EMG_MIXED) vectors and
+ * moduli.  Setup (coarsened moduli, coarsest inverse) runs on first use. */
+emg_status emg_num_levels(emg_problem *p, int *levels);
+emg_status emg_level_shape(emg_problem *p, int level, int64_t m[3], double h[3]);
+/* moduli of a level (FP64, layout of emg_set_moduli), device pointer out */
+emg_status emg_level_moduli(emg_problem *p, int level, double *C_dev);
+/* out = D_H u on every row (interior, traction, Dirichlet rows u) */
+emg_status emg_level_apply(emg_problem *p, int level, int precision, const void *u, void *out);
+/* out = f - D_H u */
+emg_status emg_level_residual(emg_problem *p, int level, int precision, const void *u, const void *f, void *out);
+/* one damped Jacobi sweep: out = u + omega (f - D_H u) / diag; Dirichlet rows out = f */
+emg_status emg_level_jacobi(emg_problem *p, int level, int precision, double omega, const void *u,
+                            const void *f, void *out);
+/* full-weighting restriction of a fine residual on `level` to level+1 */
+emg_status emg_level_restrict(emg_problem *p, int level, int precision, const void *r_fine, void *f_coarse);
+/* u_fine (on `level`) += interpolation of e_coarse (on level+1); Dirichlet rows untouched */
+emg_status emg_level_prolong_add(emg_problem *p, int level, int precision, const void *e_coarse, void *u_fine);
+/* exact FP64 solve on the coarsest level: e = A^-1 f */
+emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, void *e);
+
+/* Average duration in milliseconds of one launch of a cycle kernel on the
+ * problem's stream, measured with HIP events around `reps` back-to-back
+ * launches in the launch configuration the solve uses.  kernel: 0 = Jacobi
+ * sweep, 1 = residual with full-weighting restriction, 2 = interpolation. */
+emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMG_H */

@@ -1,0 +1,887 @@
+// Host runtime and C ABI of the gfx950 multigrid elasticity solver.
+//
+// A problem owns its multigrid hierarchy in HBM (levels 0, -1, -2, ... of
+// Sec. 3.1), one HIP stream, and HIP graphs of whole cycles.  The solve loop
+// replays a graph of `check_every` cycles; the first Jacobi sweep of each
+// cycle also produces the residual norm of the incoming iterate, and a
+// one-block check kernel decides convergence on the device, so cycles queued
+// after convergence return at once and the host reads a 64-byte control
+// block once per replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "../../include/emg.h"
+#include "emg_kernels.hpp"
+
+using namespace emg;
+
+namespace {
+
+thread_local std::string g_err;
+
+emg_status fail(emg_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCK(call)                                                                                  \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      return fail(EMG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+constexpr int kMaxBottom = 1536;
+
+template <class F>
+void dispatch(int D, int K, F &&f) {
+  if (D == 2 && K == MOD_ISO) f(std::integral_constant<int, 2>{}, std::integral_constant<int, MOD_ISO>{});
+  else if (D == 2) f(std::integral_constant<int, 2>{}, std::integral_constant<int, MOD_ANISO>{});
+  else if (K == MOD_ISO) f(std::integral_constant<int, 3>{}, std::integral_constant<int, MOD_ISO>{});
+  else f(std::integral_constant<int, 3>{}, std::integral_constant<int, MOD_ANISO>{});
+}
+
+dim3 grid_of(const Geom &g) { return dim3((g.m[0] + BX - 1) / BX, (g.m[1] + BY - 1) / BY, g.m[2]); }
+const dim3 kBlock(BX, BY, 1);
+
+struct Level {
+  Geom g{};
+  double *C64 = nullptr;
+  float *C32 = nullptr;
+  double *u64[2] = {nullptr, nullptr};
+  double *f64 = nullptr, *r64 = nullptr;
+  float *u32[2] = {nullptr, nullptr};
+  float *f32 = nullptr, *r32 = nullptr;
+};
+
+}  // namespace
+
+struct emg_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  std::mutex mu;
+};
+
+struct emg_problem {
+  emg_ctx *ctx = nullptr;
+  emg_domain dom{};
+  int D = 3, K = MOD_ISO, nc = 2, ne = 6;
+  std::vector<Level> lv;
+  double *eps = nullptr, *body = nullptr, *face[6] = {nullptr};
+  double *Ainv = nullptr;
+  int nbot = 0;
+  double *partial = nullptr;
+  long long npartial = 0;
+  Ctl *ctl = nullptr;
+  Ctl *ctl_host = nullptr;
+  int *status = nullptr;
+  double *sig = nullptr;
+  hipStream_t own = nullptr, stream = nullptr;
+  bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  // graph cache: key = (precision, cycles per replay, nu1, nu2, omega)
+  struct GraphEntry {
+    int prec, k, nu1, nu2;
+    double omega;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+template <typename T>
+emg_status dalloc(emg_problem *p, T **out, size_t count) {
+  void *ptr = nullptr;
+  const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, b);
+  if (e != hipSuccess) return fail(EMG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  p->allocs.push_back(ptr);
+  p->bytes += b;
+  *out = static_cast<T *>(ptr);
+  return EMG_OK;
+}
+
+#define TRY(x)                    \
+  do {                            \
+    emg_status s_ = (x);          \
+    if (s_ != EMG_OK) return s_;  \
+  } while (0)
+
+bool can_coarsen(const Geom &g) {
+  for (int a = 0; a < g.dim; a++) {
+    if (g.per[a]) {
+      if (g.m[a] % 2 || g.m[a] < 8) return false;
+    } else {
+      const int cells = g.m[a] - 1;
+      if (cells % 2 || cells < 8) return false;
+    }
+  }
+  return true;
+}
+
+Geom coarse_of(const Geom &g) {
+  Geom c = g;
+  for (int a = 0; a < g.dim; a++) {
+    c.m[a] = g.per[a] ? g.m[a] / 2 : (g.m[a] - 1) / 2 + 1;
+    c.h[a] = 2.0 * g.h[a];
+  }
+  c.N = (long long)c.m[0] * c.m[1] * c.m[2];
+  return c;
+}
+
+long long nblocks(const Geom &g) {
+  dim3 gr = grid_of(g);
+  return (long long)gr.x * gr.y * gr.z;
+}
+
+// ---- kernel launch helpers (all on the problem's stream) ----
+
+template <typename R>
+const R *moduli(const Level &L) {
+  if constexpr (std::is_same<R, double>::value) return L.C64;
+  else return L.C32;
+}
+
+template <typename R, int MODE, typename TO>
+void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *out, R omega, double *partial,
+                    const Ctl *ctl) {
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), grid_of(L.g), kBlock, 0, p->stream, L.g, moduli<R>(L), u, f,
+                       out, omega, partial, ctl);
+  });
+}
+
+template <typename R>
+void launch_jacobi_zero(emg_problem *p, const Level &L, const R *f, R *out, R omega, const Ctl *ctl) {
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_jacobi_zero<D, K, R>), grid_of(L.g), kBlock, 0, p->stream, L.g, moduli<R>(L), f, out, omega,
+                       ctl);
+  });
+}
+
+template <typename RI, typename RO>
+void launch_restrict(emg_problem *p, const Level &Lf, const Level &Lc, const RI *rf, RO *fc, const Ctl *ctl) {
+  if (p->D == 2)
+    hipLaunchKernelGGL((k_restrict<2, RI, RO>), grid_of(Lc.g), kBlock, 0, p->stream, Lf.g, Lc.g, rf, fc, ctl);
+  else
+    hipLaunchKernelGGL((k_restrict<3, RI, RO>), grid_of(Lc.g), kBlock, 0, p->stream, Lf.g, Lc.g, rf, fc, ctl);
+}
+
+template <typename RC, typename RF>
+void launch_prolong(emg_problem *p, const Level &Lc, const Level &Lf, const RC *ec, RF *uf, const Ctl *ctl) {
+  if (p->D == 2)
+    hipLaunchKernelGGL((k_prolong_add<2, RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
+  else
+    hipLaunchKernelGGL((k_prolong_add<3, RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
+}
+
+template <typename RI, typename RO>
+void launch_bottom(emg_problem *p, const RI *f, RO *e, const Ctl *ctl) {
+  hipLaunchKernelGGL((k_bottom_solve<RI, RO>), dim3((p->nbot + 3) / 4), dim3(256), 0, p->stream, p->Ainv, p->nbot, f,
+                     e, ctl);
+}
+
+template <typename A, typename B>
+void launch_cast(emg_problem *p, long long n, const A *in, B *out, const Ctl *ctl) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_cast<A, B>), dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, p->stream, n, in,
+                     out, ctl);
+}
+
+template <typename T>
+void launch_fill(emg_problem *p, long long n, T *out, T v) {
+  const long long blocks = std::min<long long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, p->stream, n, out, v);
+}
+
+void launch_check(emg_problem *p, long long nparts, int ans) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, p->stream, p->partial, nparts, p->ctl, ans);
+}
+
+// ---- setup: coarse moduli, coarsest inverse, right-hand side ----
+
+emg_status setup(emg_problem *p) {
+  if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
+  if (p->setup_done) return EMG_OK;
+  const int L = (int)p->lv.size();
+  for (int l = 1; l < L; l++)
+    hipLaunchKernelGGL((k_coarsen<double>), grid_of(p->lv[l].g), kBlock, 0, p->stream, p->lv[l - 1].g, p->lv[l].g,
+                       p->nc, p->lv[l - 1].C64, p->lv[l].C64);
+  HIPCK(hipGetLastError());
+  // coarsest operator: assemble [A | I], invert by Gauss-Jordan with partial pivoting
+  const Level &B = p->lv[L - 1];
+  const int n = p->nbot;
+  double *M = nullptr;
+  HIPCK(hipMallocAsync((void **)&M, sizeof(double) * 2 * (size_t)n * n, p->stream));
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_bottom_assemble<D, K>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, B.g, B.C64, M, n);
+  });
+  hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, p->stream, 1LL, p->status, 0);
+  for (int k = 0; k < n; k++) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, p->stream, M, n, k, p->status);
+    const long long cols = 2LL * n - k - 1;
+    if (cols > 0)
+      hipLaunchKernelGGL(k_gj_elim, dim3((unsigned)((cols + 255) / 256), n), dim3(256), 0, p->stream, M, n, k);
+  }
+  hipLaunchKernelGGL(k_gj_extract, dim3((unsigned)(((long long)n * n + 255) / 256)), dim3(256), 0, p->stream, M, n,
+                     p->Ainv);
+  HIPCK(hipGetLastError());
+  int st = 0;
+  HIPCK(hipMemcpyAsync(&st, p->status, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPCK(hipFreeAsync(M, p->stream));
+  HIPCK(hipStreamSynchronize(p->stream));
+  if (st) return fail(EMG_EINVAL, "coarsest-level operator is singular");
+  p->setup_done = true;
+  return EMG_OK;
+}
+
+emg_status ensure_mixed(emg_problem *p) {
+  if (p->mixed_ready) return EMG_OK;
+  for (auto &L : p->lv) {
+    const long long nd = (long long)p->D * L.g.N;
+    if (!L.C32) {
+      TRY(dalloc(p, &L.C32, (size_t)p->nc * L.g.N));
+      TRY(dalloc(p, &L.u32[0], nd));
+      TRY(dalloc(p, &L.u32[1], nd));
+      TRY(dalloc(p, &L.f32, nd));
+      TRY(dalloc(p, &L.r32, nd));
+    }
+    launch_cast<double, float>(p, (long long)p->nc * L.g.N, L.C64, L.C32, nullptr);
+  }
+  HIPCK(hipGetLastError());
+  p->mixed_ready = true;
+  return EMG_OK;
+}
+
+emg_status assemble_rhs(emg_problem *p) {
+  if (p->rhs_ready) return EMG_OK;
+  const Level &L0 = p->lv[0];
+  Faces F;
+  for (int f = 0; f < 6; f++) F.p[f] = p->face[f];
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_rhs<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, p->body, F, L0.f64);
+  });
+  HIPCK(hipGetLastError());
+  p->rhs_ready = true;
+  return EMG_OK;
+}
+
+// ---- cycles ----
+
+// V-cycle on coarse level l >= 1 for the correction, starting from zero;
+// returns the ping-pong buffer holding the result.
+template <typename R>
+R *vbuf(Level &L, int b) {
+  if constexpr (std::is_same<R, double>::value) return L.u64[b];
+  else return L.u32[b];
+}
+template <typename R>
+R *fbuf(Level &L) {
+  if constexpr (std::is_same<R, double>::value) return L.f64;
+  else return L.f32;
+}
+template <typename R>
+R *rbuf(Level &L) {
+  if constexpr (std::is_same<R, double>::value) return L.r64;
+  else return L.r32;
+}
+
+template <typename R>
+int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega) {
+  const int L = (int)p->lv.size();
+  Level &Lv = p->lv[l];
+  if (l == L - 1) {
+    launch_bottom<R, R>(p, fbuf<R>(Lv), vbuf<R>(Lv, 0), p->ctl);
+    return 0;
+  }
+  int cur = 0;
+  launch_jacobi_zero<R>(p, Lv, fbuf<R>(Lv), vbuf<R>(Lv, 0), omega, p->ctl);
+  for (int s = 1; s < nu1; s++) {
+    launch_stencil<R, MODE_JACOBI, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1), omega, nullptr, p->ctl);
+    cur ^= 1;
+  }
+  launch_stencil<R, MODE_RESID, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), rbuf<R>(Lv), omega, nullptr, p->ctl);
+  launch_restrict<R, R>(p, Lv, p->lv[l + 1], rbuf<R>(Lv), fbuf<R>(p->lv[l + 1]), p->ctl);
+  const int cb = coarse_cycle<R>(p, l + 1, nu1, nu2, omega);
+  launch_prolong<R, R>(p, p->lv[l + 1], Lv, vbuf<R>(p->lv[l + 1], cb), vbuf<R>(Lv, cur), p->ctl);
+  for (int s = 0; s < nu2; s++) {
+    launch_stencil<R, MODE_JACOBI, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1), omega, nullptr, p->ctl);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+// One FP64 V-cycle on level 0 for u (buffer 0 in and out).  The first sweep
+// also sums the squared residual of the incoming iterate; the check kernel
+// stops the solve before the cycle changes anything if it has converged.
+void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
+  Level &L0 = p->lv[0];
+  int cur = 0;
+  launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[0], L0.f64, L0.u64[1], omega, p->partial, p->ctl);
+  launch_check(p, nblocks(L0.g), 0);
+  cur = 1;
+  for (int s = 1; s < nu1; s++) {
+    launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
+    cur ^= 1;
+  }
+  launch_stencil<double, MODE_RESID, double>(p, L0, L0.u64[cur], L0.f64, L0.r64, omega, nullptr, p->ctl);
+  launch_restrict<double, double>(p, L0, p->lv[1], L0.r64, p->lv[1].f64, p->ctl);
+  const int cb = coarse_cycle<double>(p, 1, nu1, nu2, omega);
+  launch_prolong<double, double>(p, p->lv[1], L0, p->lv[1].u64[cb], L0.u64[cur], p->ctl);
+  for (int s = 0; s < nu2; s++) {
+    launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
+    cur ^= 1;
+  }
+  if (cur != 0) launch_cast<double, double>(p, (long long)p->D * L0.g.N, L0.u64[cur], L0.u64[0], p->ctl);
+}
+
+// One mixed-precision refinement step: FP64 residual of u_a + e written to
+// u_b and (as FP32) to the level-0 FP32 right-hand side, convergence check,
+// then one FP32 V-cycle for the new correction e (left in u32[0] of level 0).
+void record_mixed_iter(emg_problem *p, int a, int nu1, int nu2, float omega) {
+  Level &L0 = p->lv[0];
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_resid_update<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, L0.u64[a],
+                       L0.u32[0], L0.f64, L0.u64[a ^ 1], L0.f32, p->partial, p->ctl);
+  });
+  launch_check(p, nblocks(L0.g), a ^ 1);
+  const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega);
+  if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
+}
+
+void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double omega) {
+  if (prec == EMG_FP64) {
+    for (int c = 0; c < k; c++) record_fp64_cycle(p, nu1, nu2, omega);
+  } else {
+    for (int c = 0; c < k; c++) record_mixed_iter(p, c & 1, nu1, nu2, (float)omega);
+  }
+}
+
+emg_status get_graph(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, hipGraphExec_t *out) {
+  for (auto &g : p->graphs)
+    if (g.prec == prec && g.k == k && g.nu1 == nu1 && g.nu2 == nu2 && g.omega == omega) {
+      *out = g.exec;
+      return EMG_OK;
+    }
+  hipGraph_t graph;
+  HIPCK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  record_cycles(p, prec, k, nu1, nu2, omega);
+  HIPCK(hipStreamEndCapture(p->stream, &graph));
+  hipGraphExec_t exec;
+  HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  HIPCK(hipGraphDestroy(graph));
+  p->graphs.push_back({prec, k, nu1, nu2, omega, exec});
+  *out = exec;
+  return EMG_OK;
+}
+
+emg_status validate_level(emg_problem *p, int level) {
+  if (level < 0 || level >= (int)p->lv.size()) return fail(EMG_EINVAL, "level out of range");
+  return EMG_OK;
+}
+
+emg_status copy_in(emg_problem *p, double *dst, const double *src, size_t count, int on_device) {
+  HIPCK(hipMemcpyAsync(dst, src, count * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                       p->stream));
+  HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+emg_status copy_out(emg_problem *p, double *dst, const double *src, size_t count, int on_device) {
+  HIPCK(hipMemcpyAsync(dst, src, count * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       p->stream));
+  HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+void destroy_graphs(emg_problem *p) {
+  for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+
+}  // namespace
+
+// ============================== C ABI ==============================
+
+extern "C" {
+
+const char *emg_last_error(void) { return g_err.c_str(); }
+
+void emg_default_opts(emg_solve_opts *o) {
+  o->rtol = 1e-10;
+  o->max_cycles = 200;
+  o->precision = EMG_FP64;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->omega = 2.0 / 3.0;
+  o->warm_start = 0;
+  o->check_every = 4;
+  o->use_graph = 1;
+}
+
+emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out) {
+  if (!out) return fail(EMG_EINVAL, "null output pointer");
+  int count = 0;
+  HIPCK(hipGetDeviceCount(&count));
+  if (hip_device < 0 || hip_device >= count) return fail(EMG_EINVAL, "no such HIP device");
+  HIPCK(hipSetDevice(hip_device));
+  emg_ctx *c = new emg_ctx;
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return EMG_OK;
+}
+
+emg_status emg_ctx_destroy(emg_ctx *ctx) {
+  delete ctx;
+  return EMG_OK;
+}
+
+emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem **out) {
+  if (!ctx || !dom || !out) return fail(EMG_EINVAL, "null argument");
+  if (dom->dim != 2 && dom->dim != 3) return fail(EMG_EINVAL, "dim must be 2 or 3");
+  if (dom->kind != EMG_MOD_ISO && dom->kind != EMG_MOD_ANISO) return fail(EMG_EINVAL, "bad moduli kind");
+  Geom g{};
+  g.dim = dom->dim;
+  bool any_dir = false;
+  for (int a = 0; a < 3; a++) {
+    if (a < dom->dim) {
+      const int b0 = dom->bc[2 * a], b1 = dom->bc[2 * a + 1];
+      for (int b : {b0, b1})
+        if (b != EMG_BC_DIRICHLET && b != EMG_BC_TRACTION && b != EMG_BC_PERIODIC)
+          return fail(EMG_EINVAL, "bad boundary type");
+      if ((b0 == EMG_BC_PERIODIC) != (b1 == EMG_BC_PERIODIC))
+        return fail(EMG_EINVAL, "both faces of a periodic axis must be periodic");
+      any_dir = any_dir || b0 == EMG_BC_DIRICHLET || b1 == EMG_BC_DIRICHLET;
+      if (dom->n[a] < 5 || dom->n[a] > (1 << 20)) return fail(EMG_EINVAL, "every axis needs 5..2^20 nodes");
+      if (!(dom->hi[a] > dom->lo[a])) return fail(EMG_EINVAL, "empty domain extent");
+      g.per[a] = b0 == EMG_BC_PERIODIC;
+      g.m[a] = (int)(g.per[a] ? dom->n[a] - 1 : dom->n[a]);
+      g.h[a] = (dom->hi[a] - dom->lo[a]) / double(dom->n[a] - 1);
+      g.bc[2 * a] = b0;
+      g.bc[2 * a + 1] = b1;
+    } else {
+      if (dom->n[a] != 1) return fail(EMG_EINVAL, "n[2] must be 1 in 2D");
+      g.m[a] = 1;
+      g.per[a] = 1;
+      g.h[a] = 1.0;
+      g.bc[2 * a] = g.bc[2 * a + 1] = EMG_BC_PERIODIC;
+    }
+  }
+  if (!any_dir) return fail(EMG_EINVAL, "at least one Dirichlet face is required (rigid-body null space)");
+  g.N = (long long)g.m[0] * g.m[1] * g.m[2];
+  std::vector<Geom> gs{g};
+  while (can_coarsen(gs.back())) gs.push_back(coarse_of(gs.back()));
+  if (gs.size() < 2) return fail(EMG_EINVAL, "grid does not coarsen (need even cell counts >= 8)");
+  const long long nbot = (long long)dom->dim * gs.back().N;
+  if (nbot > kMaxBottom) return fail(EMG_EINVAL, "coarsest level too large (" + std::to_string(nbot) + " unknowns)");
+
+  emg_problem *p = new emg_problem;
+  p->ctx = ctx;
+  p->dom = *dom;
+  p->D = dom->dim;
+  p->K = dom->kind;
+  p->nc = p->K == MOD_ISO ? 2 : (p->D == 3 ? 21 : 6);
+  p->ne = p->D == 3 ? 6 : 3;
+  p->nbot = (int)nbot;
+  auto bail = [&](emg_status s) {
+    std::string keep = g_err;
+    emg_problem_destroy(p);
+    g_err = keep;
+    return s;
+  };
+  if (hipSetDevice(ctx->device) != hipSuccess) return bail(fail(EMG_EDEVICE, "hipSetDevice failed"));
+  if (hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(EMG_EDEVICE, "hipStreamCreate failed"));
+  p->stream = p->own;
+  // footprint check before allocating
+  size_t need = 0;
+  for (size_t l = 0; l < gs.size(); l++) need += gs[l].N * (p->nc + 4 * p->D) * sizeof(double);
+  need += gs[0].N * (p->ne + p->D) * sizeof(double) + sizeof(double) * (size_t)nbot * nbot;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->in_use + need > ctx->budget) {
+      delete p;
+      return fail(EMG_ENOMEM, "HBM budget exceeded");
+    }
+    ctx->in_use += need;
+  }
+  p->lv.resize(gs.size());
+  for (size_t l = 0; l < gs.size(); l++) {
+    Level &L = p->lv[l];
+    L.g = gs[l];
+    const size_t nd = (size_t)p->D * L.g.N;
+    emg_status s;
+    if ((s = dalloc(p, &L.C64, (size_t)p->nc * L.g.N)) != EMG_OK) return bail(s);
+    if ((s = dalloc(p, &L.u64[0], nd)) != EMG_OK) return bail(s);
+    if ((s = dalloc(p, &L.u64[1], nd)) != EMG_OK) return bail(s);
+    if ((s = dalloc(p, &L.f64, nd)) != EMG_OK) return bail(s);
+    if ((s = dalloc(p, &L.r64, nd)) != EMG_OK) return bail(s);
+  }
+  emg_status s;
+  if ((s = dalloc(p, &p->Ainv, (size_t)nbot * nbot)) != EMG_OK) return bail(s);
+  p->npartial = nblocks(gs[0]);
+  if ((s = dalloc(p, &p->partial, (size_t)p->npartial)) != EMG_OK) return bail(s);
+  if ((s = dalloc(p, &p->ctl, 1)) != EMG_OK) return bail(s);
+  if ((s = dalloc(p, &p->status, 4)) != EMG_OK) return bail(s);
+  if (hipHostMalloc((void **)&p->ctl_host, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(EMG_ENOMEM, "hipHostMalloc failed"));
+  const size_t nd0 = (size_t)p->D * gs[0].N;
+  launch_fill<double>(p, (long long)nd0, p->lv[0].u64[0], 0.0);
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return bail(fail(EMG_EDEVICE, "initial fill failed"));
+  *out = p;
+  return EMG_OK;
+}
+
+emg_status emg_problem_destroy(emg_problem *p) {
+  if (!p) return EMG_OK;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  destroy_graphs(p);
+  for (void *a : p->allocs) (void)hipFree(a);
+  if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+  if (p->own) (void)hipStreamDestroy(p->own);
+  if (p->ctx) {
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    size_t need = 0;
+    for (auto &L : p->lv) need += L.g.N * (p->nc + 4 * p->D) * sizeof(double);
+    if (!p->lv.empty()) need += p->lv[0].g.N * (p->ne + p->D) * sizeof(double) + sizeof(double) * (size_t)p->nbot * p->nbot;
+    p->ctx->in_use -= std::min(p->ctx->in_use, need);
+  }
+  delete p;
+  return EMG_OK;
+}
+
+emg_status emg_set_stream(emg_problem *p, void *s) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  HIPCK(hipStreamSynchronize(p->stream));
+  destroy_graphs(p);
+  p->stream = s ? (hipStream_t)s : p->own;
+  return EMG_OK;
+}
+
+emg_status emg_footprint(const emg_problem *p, size_t *bytes) {
+  if (!p || !bytes) return fail(EMG_EINVAL, "null argument");
+  *bytes = p->bytes;
+  return EMG_OK;
+}
+
+emg_status emg_set_moduli(emg_problem *p, const double *C, int on_device) {
+  if (!p || !C) return fail(EMG_EINVAL, "null argument");
+  TRY(copy_in(p, p->lv[0].C64, C, (size_t)p->nc * p->lv[0].g.N, on_device));
+  p->moduli_set = true;
+  p->setup_done = p->mixed_ready = p->rhs_ready = false;
+  return EMG_OK;
+}
+
+emg_status emg_set_eigenstrain(emg_problem *p, const double *e, int on_device) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  p->rhs_ready = false;
+  if (!e) {
+    p->eps = nullptr;
+    return EMG_OK;
+  }
+  static_assert(sizeof(double) == 8, "");
+  if (!p->eps) TRY(dalloc(p, &p->eps, (size_t)p->ne * p->lv[0].g.N));
+  return copy_in(p, p->eps, e, (size_t)p->ne * p->lv[0].g.N, on_device);
+}
+
+emg_status emg_set_body_force(emg_problem *p, const double *b, int on_device) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  p->rhs_ready = false;
+  if (!b) {
+    p->body = nullptr;
+    return EMG_OK;
+  }
+  if (!p->body) TRY(dalloc(p, &p->body, (size_t)p->D * p->lv[0].g.N));
+  return copy_in(p, p->body, b, (size_t)p->D * p->lv[0].g.N, on_device);
+}
+
+emg_status emg_set_face(emg_problem *p, int f, const double *v, int on_device) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  if (f < 0 || f >= 2 * p->D) return fail(EMG_EINVAL, "face out of range");
+  if (p->lv[0].g.per[f / 2]) return fail(EMG_EINVAL, "periodic faces carry no data");
+  p->rhs_ready = false;
+  if (!v) {
+    p->face[f] = nullptr;
+    return EMG_OK;
+  }
+  const Geom &g = p->lv[0].g;
+  const size_t fn = (size_t)g.N / g.m[f / 2];
+  if (!p->face[f]) TRY(dalloc(p, &p->face[f], (size_t)p->D * fn));
+  return copy_in(p, p->face[f], v, (size_t)p->D * fn, on_device);
+}
+
+emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *st) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  emg_solve_opts opt;
+  emg_default_opts(&opt);
+  if (o) opt = *o;
+  if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
+  if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
+  if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
+  int k = std::max(1, opt.check_every);
+  if (opt.precision == EMG_MIXED && (k & 1)) k += 1;
+  const auto t0 = std::chrono::steady_clock::now();
+  TRY(setup(p));
+  if (opt.precision == EMG_MIXED) TRY(ensure_mixed(p));
+  TRY(assemble_rhs(p));
+  Level &L0 = p->lv[0];
+  const long long nd0 = (long long)p->D * L0.g.N;
+  Ctl c0{};
+  c0.r0sq = -1.0;
+  c0.tol2 = opt.rtol * opt.rtol;
+  c0.max_cycles = opt.max_cycles;
+  *p->ctl_host = c0;
+  HIPCK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, p->stream));
+  // the Dirichlet lift; with a warm start it goes to a scratch buffer and
+  // only its residual norm is kept as the reference
+  double *lift = opt.warm_start ? L0.u64[1] : L0.u64[0];
+  if (p->D == 2)
+    hipLaunchKernelGGL((k_lift<2>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
+  else
+    hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
+  if (opt.warm_start) {
+    launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
+    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(256), 0, p->stream, p->partial, nblocks(L0.g), p->ctl);
+  }
+  if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[0], 0.0f);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(p->stream));
+  const auto t1 = std::chrono::steady_clock::now();
+  hipGraphExec_t exec = nullptr;
+  if (opt.use_graph) TRY(get_graph(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, &exec));
+  const auto t2 = std::chrono::steady_clock::now();
+  for (;;) {
+    if (exec)
+      HIPCK(hipGraphLaunch(exec, p->stream));
+    else
+      record_cycles(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega);
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+    if (p->ctl_host->done) break;
+  }
+  const auto t3 = std::chrono::steady_clock::now();
+  const Ctl c = *p->ctl_host;
+  // the answer lives in buffer c.ans of level 0; keep it in buffer 0
+  if (c.ans != 0) {
+    HIPCK(hipMemcpyAsync(L0.u64[0], L0.u64[c.ans], sizeof(double) * nd0, hipMemcpyDeviceToDevice, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+  }
+  emg_solve_stats s{};
+  s.cycles = c.cycles;
+  s.rel_res = c.r0sq > 0 ? std::sqrt(c.rsq / c.r0sq) : 0.0;
+  s.converged = c.done == 1;
+  s.conv_factor = (c.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / c.cycles) : 0.0;
+  s.solve_seconds = std::chrono::duration<double>(t3 - t2).count();
+  s.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
+  long long dir_nodes = 0;
+  {
+    const Geom &g = L0.g;
+    // count nodes on a Dirichlet face (inclusion-exclusion over the box)
+    long long inner = 1;
+    for (int a = 0; a < g.dim; a++) {
+      int cut = 0;
+      if (!g.per[a]) cut = (g.bc[2 * a] == EMG_BC_DIRICHLET) + (g.bc[2 * a + 1] == EMG_BC_DIRICHLET);
+      inner *= (g.m[a] - cut);
+    }
+    dir_nodes = g.N - inner;
+  }
+  s.dofs = (long long)p->D * (L0.g.N - dir_nodes);
+  if (st) *st = s;
+  if (c.done == 2) return fail(EMG_EDIVERGED, "residual norm is not finite");
+  if (c.done == 3) return fail(EMG_ENOTCONV, "cycle cap reached before the tolerance");
+  return EMG_OK;
+}
+
+emg_status emg_get_displacement(emg_problem *p, double *u, int on_device) {
+  if (!p || !u) return fail(EMG_EINVAL, "null argument");
+  return copy_out(p, u, p->lv[0].u64[0], (size_t)p->D * p->lv[0].g.N, on_device);
+}
+
+emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device) {
+  if (!p || !u) return fail(EMG_EINVAL, "null argument");
+  return copy_in(p, p->lv[0].u64[0], u, (size_t)p->D * p->lv[0].g.N, on_device);
+}
+
+emg_status emg_get_rhs(emg_problem *p, double *f, int on_device) {
+  if (!p || !f) return fail(EMG_EINVAL, "null argument");
+  if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
+  TRY(assemble_rhs(p));
+  return copy_out(p, f, p->lv[0].f64, (size_t)p->D * p->lv[0].g.N, on_device);
+}
+
+emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device) {
+  if (!p || !sigma) return fail(EMG_EINVAL, "null argument");
+  if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
+  const Level &L0 = p->lv[0];
+  if (!p->sig) TRY(dalloc(p, &p->sig, (size_t)p->ne * L0.g.N));
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, L0.u64[0], p->sig);
+  });
+  HIPCK(hipGetLastError());
+  return copy_out(p, sigma, p->sig, (size_t)p->ne * L0.g.N, on_device);
+}
+
+emg_status emg_num_levels(emg_problem *p, int *levels) {
+  if (!p || !levels) return fail(EMG_EINVAL, "null argument");
+  *levels = (int)p->lv.size();
+  return EMG_OK;
+}
+
+emg_status emg_level_shape(emg_problem *p, int level, int64_t m[3], double h[3]) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  TRY(validate_level(p, level));
+  for (int a = 0; a < 3; a++) {
+    if (m) m[a] = p->lv[level].g.m[a];
+    if (h) h[a] = p->lv[level].g.h[a];
+  }
+  return EMG_OK;
+}
+
+emg_status emg_level_moduli(emg_problem *p, int level, double *C_dev) {
+  if (!p || !C_dev) return fail(EMG_EINVAL, "null argument");
+  TRY(validate_level(p, level));
+  TRY(setup(p));
+  return copy_out(p, C_dev, p->lv[level].C64, (size_t)p->nc * p->lv[level].g.N, 1);
+}
+
+static emg_status level_prep(emg_problem *p, int level, int precision) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  TRY(validate_level(p, level));
+  if (precision != EMG_FP64 && precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  TRY(setup(p));
+  if (precision == EMG_MIXED) TRY(ensure_mixed(p));
+  return EMG_OK;
+}
+
+static emg_status finish(emg_problem *p) {
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+emg_status emg_level_apply(emg_problem *p, int level, int precision, const void *u, void *out) {
+  TRY(level_prep(p, level, precision));
+  const Level &L = p->lv[level];
+  if (precision == EMG_FP64)
+    launch_stencil<double, MODE_APPLY, double>(p, L, (const double *)u, nullptr, (double *)out, 0.0, nullptr, nullptr);
+  else
+    launch_stencil<float, MODE_APPLY, float>(p, L, (const float *)u, nullptr, (float *)out, 0.0f, nullptr, nullptr);
+  return finish(p);
+}
+
+emg_status emg_level_residual(emg_problem *p, int level, int precision, const void *u, const void *f, void *out) {
+  TRY(level_prep(p, level, precision));
+  const Level &L = p->lv[level];
+  if (precision == EMG_FP64)
+    launch_stencil<double, MODE_RESID, double>(p, L, (const double *)u, (const double *)f, (double *)out, 0.0, nullptr,
+                                               nullptr);
+  else
+    launch_stencil<float, MODE_RESID, float>(p, L, (const float *)u, (const float *)f, (float *)out, 0.0f, nullptr,
+                                             nullptr);
+  return finish(p);
+}
+
+emg_status emg_level_jacobi(emg_problem *p, int level, int precision, double omega, const void *u, const void *f,
+                            void *out) {
+  TRY(level_prep(p, level, precision));
+  const Level &L = p->lv[level];
+  if (precision == EMG_FP64)
+    launch_stencil<double, MODE_JACOBI, double>(p, L, (const double *)u, (const double *)f, (double *)out, omega,
+                                                nullptr, nullptr);
+  else
+    launch_stencil<float, MODE_JACOBI, float>(p, L, (const float *)u, (const float *)f, (float *)out, (float)omega,
+                                              nullptr, nullptr);
+  return finish(p);
+}
+
+emg_status emg_level_restrict(emg_problem *p, int level, int precision, const void *r, void *fc) {
+  TRY(level_prep(p, level, precision));
+  if (level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
+  if (precision == EMG_FP64)
+    launch_restrict<double, double>(p, p->lv[level], p->lv[level + 1], (const double *)r, (double *)fc, nullptr);
+  else
+    launch_restrict<float, float>(p, p->lv[level], p->lv[level + 1], (const float *)r, (float *)fc, nullptr);
+  return finish(p);
+}
+
+emg_status emg_level_prolong_add(emg_problem *p, int level, int precision, const void *ec, void *uf) {
+  TRY(level_prep(p, level, precision));
+  if (level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
+  if (precision == EMG_FP64)
+    launch_prolong<double, double>(p, p->lv[level + 1], p->lv[level], (const double *)ec, (double *)uf, nullptr);
+  else
+    launch_prolong<float, float>(p, p->lv[level + 1], p->lv[level], (const float *)ec, (float *)uf, nullptr);
+  return finish(p);
+}
+
+emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, void *e) {
+  TRY(level_prep(p, (int)p->lv.size() - 1, precision));
+  if (precision == EMG_FP64)
+    launch_bottom<double, double>(p, (const double *)f, (double *)e, nullptr);
+  else
+    launch_bottom<float, float>(p, (const float *)f, (float *)e, nullptr);
+  return finish(p);
+}
+
+emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms) {
+  TRY(level_prep(p, level, precision));
+  if (reps < 1 || !avg_ms) return fail(EMG_EINVAL, "bad reps or output");
+  if ((kernel == 1 || kernel == 2) && level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
+  if (kernel < 0 || kernel > 2) return fail(EMG_EINVAL, "unknown kernel id");
+  Level &L = p->lv[level];
+  auto one = [&]() {
+    if (precision == EMG_FP64) {
+      if (kernel == 0)
+        launch_stencil<double, MODE_JACOBI, double>(p, L, L.u64[0], L.f64, L.u64[1], 2.0 / 3.0, nullptr, nullptr);
+      else if (kernel == 1)
+        launch_stencil<double, MODE_RESID, double>(p, L, L.u64[0], L.f64, L.r64, 0.0, nullptr, nullptr);
+      else
+        launch_prolong<double, double>(p, p->lv[level + 1], L, p->lv[level + 1].u64[0], L.u64[1], nullptr);
+    } else {
+      if (kernel == 0)
+        launch_stencil<float, MODE_JACOBI, float>(p, L, L.u32[0], L.f32, L.u32[1], 2.0f / 3.0f, nullptr, nullptr);
+      else if (kernel == 1)
+        launch_stencil<float, MODE_RESID, float>(p, L, L.u32[0], L.f32, L.r32, 0.0f, nullptr, nullptr);
+      else
+        launch_prolong<float, float>(p, p->lv[level + 1], L, p->lv[level + 1].u32[0], L.u32[1], nullptr);
+    }
+  };
+  one();  // warm
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  HIPCK(hipEventRecord(e0, p->stream));
+  for (int r = 0; r < reps; r++) one();
+  HIPCK(hipEventRecord(e1, p->stream));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return finish(p);
+}
+
+}  // extern "C"

@@ -1,0 +1,339 @@
+// Device-side building blocks of the gfx950 multigrid elasticity solver:
+// grid geometry, row classification, the finite-difference rows of the
+// operator D_H (product-rule interior rows, traction boundary rows,
+// Dirichlet rows) and wavefront reductions.
+//
+// Operator (Sec. 2.1, Sec. 2.1.1 product rule):
+//   interior row i:  sum_jkl d_j(C_ijkl) d_l(u_k) + C_ijkl d_jl(u_k)
+//   traction row i:  sum over the node's faces of  n_a sum_kl C_iakl dhat_l(u_k)
+//   Dirichlet row i: u_i
+// The interior rows are evaluated in "flux form": with e the engineering
+// strain of the centre gradient, sum_kl C_ijkl(q) d_l u_k = (C(q) e)_{V(i,j)},
+// so the modulus-derivative term is a difference of two neighbour
+// stress-like rows and never materialises C_,j.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emg {
+
+enum { BC_DIR = 0, BC_TRAC = 1, BC_PER = 2 };
+enum { ROW_INT = 0, ROW_TRAC = 1, ROW_DIR = 2 };
+enum { MOD_ISO = 0, MOD_ANISO = 1 };
+
+// Geometry of one level, passed by value to every kernel.
+struct Geom {
+  int m[3];        // stored nodes per axis (periodic: n-1); m[2] = 1 in 2D
+  int dim;
+  int per[3];      // periodic flag per axis
+  int bc[6];       // face types
+  double h[3];     // spacing
+  long long N;     // stored nodes
+};
+
+// Convergence control block living in device memory.  Cycle kernels read
+// `done` first and return at once when it is set, so launches queued after
+// convergence cost only their launch.
+struct Ctl {
+  double r0sq;     // squared norm of the first residual (negative until set)
+  double rsq;      // squared norm of the latest residual
+  double tol2;     // rtol^2
+  int done;        // 0 running, 1 converged, 2 diverged (NaN/Inf), 3 cycle cap
+  int cycles;      // cycles applied to the iterate being tested
+  int ans;         // buffer index holding the answer when done
+  int max_cycles;
+  int pad[2];
+};
+
+template <int D> __host__ __device__ constexpr int nvoigt() { return D == 3 ? 6 : 3; }
+template <int D, int K> __host__ __device__ constexpr int nmod() { return K == MOD_ISO ? 2 : (D == 3 ? 21 : 6); }
+// Voigt slot of the pair (i,j): 3D 11,22,33,23,31,12 -> 0..5, 2D 11,22,12 -> 0..2
+template <int D> __host__ __device__ constexpr int vslot(int i, int j) { return i == j ? i : (D == 2 ? 2 : 6 - i - j); }
+// slot of (I,J) in the row-major upper triangle of an n x n symmetric matrix
+__host__ __device__ constexpr int utri(int n, int I, int J) {
+  return I <= J ? I * n - I * (I - 1) / 2 + (J - I) : J * n - J * (J - 1) / 2 + (I - J);
+}
+
+// Full tensor component C_ijkl from the stored constants c[] of one node.
+template <int D, int K, typename R>
+__device__ __forceinline__ R cfull(const R *c, int i, int j, int k, int l) {
+  if constexpr (K == MOD_ISO)
+    return c[0] * R((i == j) && (k == l)) + c[1] * (R((i == k) && (j == l)) + R((i == l) && (j == k)));
+  else
+    return c[utri(nvoigt<D>(), vslot<D>(i, j), vslot<D>(k, l))];
+}
+
+// -1 if the node sits on the low end of non-periodic axis a, +1 on the high
+// end, 0 otherwise.  Equals the outward normal component of that face.
+__device__ __forceinline__ int end_of(const Geom &g, int a, int c) {
+  if (g.per[a]) return 0;
+  if (c == 0) return -1;
+  if (c == g.m[a] - 1) return 1;
+  return 0;
+}
+
+__device__ __forceinline__ int row_class(const Geom &g, const int p[3]) {
+  int on = 0;
+  for (int a = 0; a < g.dim; a++) {
+    int e = end_of(g, a, p[a]);
+    if (e) {
+      on = 1;
+      if (g.bc[2 * a + (e > 0)] == BC_DIR) return ROW_DIR;
+    }
+  }
+  return on ? ROW_TRAC : ROW_INT;
+}
+
+__device__ __forceinline__ long long stride_of(const Geom &g, int a) {
+  return a == 0 ? 1LL : (a == 1 ? (long long)g.m[0] : (long long)g.m[0] * g.m[1]);
+}
+
+// Linear-index offset of moving by o along axis a from coordinate c
+// (periodic axes wrap).
+__device__ __forceinline__ long long shift(const Geom &g, int a, int c, int o) {
+  int t = c + o;
+  if (g.per[a]) {
+    if (t < 0) t += g.m[a];
+    else if (t >= g.m[a]) t -= g.m[a];
+  }
+  return (long long)(t - c) * stride_of(g, a);
+}
+
+// Accessors for the displacement-like vector the rows act on.
+template <typename R> struct PtrU {
+  const R *__restrict__ p;
+  long long N;
+  __device__ __forceinline__ R operator()(int k, long long i) const { return p[k * N + i]; }
+};
+template <typename R> struct UnitU {   // unit vector e_q
+  long long q, N;
+  __device__ __forceinline__ R operator()(int k, long long i) const { return (k * N + i == q) ? R(1) : R(0); }
+};
+
+// ---- interior rows: product-rule operator with central differences ----
+template <int D, int K, typename R, class U>
+__device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long N, U u, long long n,
+                                              const long long om[3], const long long op[3], const R i2h[3],
+                                              const R ih2[3], R acc[D], R dg[D]) {
+  R G[D][D], H[D][D][D];
+#pragma unroll
+  for (int k = 0; k < D; k++) {
+    R c0 = u(k, n);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      R up = u(k, n + op[j]), um = u(k, n + om[j]);
+      G[k][j] = (up - um) * i2h[j];
+      H[k][j][j] = (up - R(2) * c0 + um) * ih2[j];
+    }
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+      for (int l = j + 1; l < D; l++) {
+        R v = ((u(k, n + op[j] + op[l]) - u(k, n + op[j] + om[l])) -
+               (u(k, n + om[j] + op[l]) - u(k, n + om[j] + om[l]))) *
+              (i2h[j] * i2h[l]);
+        H[k][j][l] = v;
+        H[k][l][j] = v;
+      }
+  }
+  if constexpr (K == MOD_ISO) {
+    const R lam = C[n], mu = C[N + n];
+    R divu = R(0);
+#pragma unroll
+    for (int k = 0; k < D; k++) divu += G[k][k];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      R gd = R(0), lap = R(0), s2 = R(0);
+#pragma unroll
+      for (int k = 0; k < D; k++) gd += H[k][i][k];
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+        lap += H[i][j][j];
+        s2 += (j == i ? R(0) : ih2[j]);
+      }
+      R dlam = (C[n + op[i]] - C[n + om[i]]) * i2h[i];
+      R t1 = dlam * divu;
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+        R dmu = (C[N + n + op[j]] - C[N + n + om[j]]) * i2h[j];
+        t1 += dmu * (G[i][j] + G[j][i]);
+      }
+      acc[i] = (lam + mu) * gd + mu * lap + t1;
+      dg[i] = R(-2) * ((lam + R(2) * mu) * ih2[i] + mu * s2);
+    }
+  } else {
+    constexpr int NV = nvoigt<D>(), NC = nmod<D, K>();
+    R cc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) cc[c] = C[c * N + n];
+    R e[NV];
+#pragma unroll
+    for (int a = 0; a < D; a++) e[a] = G[a][a];
+    if constexpr (D == 3) {
+      e[3] = G[1][2] + G[2][1];
+      e[4] = G[0][2] + G[2][0];
+      e[5] = G[0][1] + G[1][0];
+    } else {
+      e[2] = G[0][1] + G[1][0];
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      R a2 = R(0), d2 = R(0);
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+#pragma unroll
+        for (int k = 0; k < D; k++)
+#pragma unroll
+          for (int l = 0; l < D; l++) a2 += cc[utri(NV, vslot<D>(i, j), vslot<D>(k, l))] * H[k][j][l];
+        d2 += cc[utri(NV, vslot<D>(i, j), vslot<D>(i, j))] * ih2[j];
+      }
+      acc[i] = a2;
+      dg[i] = R(-2) * d2;
+    }
+    // modulus-derivative term: sum_j [ (C(n+e_j) e)_{V(i,j)} - (C(n-e_j) e)_{V(i,j)} ] / (2 h_j)
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const long long q = n + (s == 0 ? op[j] : om[j]);
+        R cq[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) cq[c] = C[c * N + q];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          const int I = vslot<D>(i, j);
+          R sg = R(0);
+#pragma unroll
+          for (int J = 0; J < NV; J++) sg += cq[utri(NV, I, J)] * e[J];
+          acc[i] += (s == 0 ? sg : -sg) * i2h[j];
+        }
+      }
+    }
+  }
+}
+
+// ---- boundary rows on traction faces (3-point one-sided normal derivatives) ----
+template <int D, int K, typename R, class U>
+__device__ void traction_rows(const Geom &g, const R *__restrict__ C, U u, long long n, const int p[3], R acc[D],
+                              R dg[D]) {
+  constexpr int NC = nmod<D, K>();
+  R cc[NC];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  R Gh[D][D], c0[D];
+  int en[D];
+  for (int l = 0; l < D; l++) {
+    const R hl = R(g.h[l]);
+    en[l] = end_of(g, l, p[l]);
+    if (en[l] != 0) {
+      const int s = -en[l];   // inward direction
+      const long long s1 = shift(g, l, p[l], s), s2 = shift(g, l, p[l], 2 * s);
+      c0[l] = R(-3 * s) / (R(2) * hl);
+      for (int k = 0; k < D; k++)
+        Gh[k][l] = R(s) * (R(-3) * u(k, n) + R(4) * u(k, n + s1) - u(k, n + s2)) / (R(2) * hl);
+    } else {
+      c0[l] = R(0);
+      const long long sp = shift(g, l, p[l], 1), sm = shift(g, l, p[l], -1);
+      for (int k = 0; k < D; k++) Gh[k][l] = (u(k, n + sp) - u(k, n + sm)) / (R(2) * hl);
+    }
+  }
+  for (int i = 0; i < D; i++) { acc[i] = R(0); dg[i] = R(0); }
+  for (int a = 0; a < D; a++) {
+    if (en[a] == 0) continue;
+    const R na = R(en[a]);
+    for (int i = 0; i < D; i++) {
+      R s = R(0), sd = R(0);
+      for (int k = 0; k < D; k++)
+        for (int l = 0; l < D; l++) s += cfull<D, K, R>(cc, i, a, k, l) * Gh[k][l];
+      for (int l = 0; l < D; l++) sd += cfull<D, K, R>(cc, i, a, i, l) * c0[l];
+      acc[i] += na * s;
+      dg[i] += na * sd;
+    }
+  }
+}
+
+// Neighbour offsets (with periodic wrap) of node p for the interior rows.
+__device__ __forceinline__ void neighbour_offsets(const Geom &g, const int p[3], long long om[3], long long op[3]) {
+  for (int a = 0; a < 3; a++) {
+    if (a < g.dim) {
+      om[a] = shift(g, a, p[a], -1);
+      op[a] = shift(g, a, p[a], 1);
+    } else {
+      om[a] = op[a] = 0;
+    }
+  }
+}
+
+// All d rows of D_H at node n (class cls) and their diagonal coefficients.
+template <int D, int K, typename R, class U>
+__device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, U u, long long n, const int p[3], int cls,
+                                        R acc[D], R dg[D]) {
+  if (cls == ROW_INT) {
+    long long om[3], op[3];
+    neighbour_offsets(g, p, om, op);
+    R i2h[3], ih2[3];
+    for (int a = 0; a < 3; a++) {
+      i2h[a] = R(0.5 / g.h[a]);
+      ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
+    }
+    interior_rows<D, K, R, U>(C, g.N, u, n, om, op, i2h, ih2, acc, dg);
+  } else if (cls == ROW_TRAC) {
+    traction_rows<D, K, R, U>(g, C, u, n, p, acc, dg);
+  } else {
+    for (int i = 0; i < D; i++) {
+      acc[i] = u(i, n);
+      dg[i] = R(1);
+    }
+  }
+}
+
+// Diagonal coefficients only (no displacement needed).
+template <int D, int K, typename R>
+__device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, long long n, const int p[3], int cls,
+                                        R dg[D]) {
+  if (cls == ROW_DIR) {
+    for (int i = 0; i < D; i++) dg[i] = R(1);
+    return;
+  }
+  constexpr int NC = nmod<D, K>();
+  R cc[NC];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  if (cls == ROW_INT) {
+    for (int i = 0; i < D; i++) {
+      R s = R(0);
+      for (int j = 0; j < D; j++) s += cfull<D, K, R>(cc, i, j, i, j) * R(1.0 / (g.h[j] * g.h[j]));
+      dg[i] = R(-2) * s;
+    }
+    return;
+  }
+  for (int i = 0; i < D; i++) dg[i] = R(0);
+  for (int a = 0; a < D; a++) {
+    int ea = end_of(g, a, p[a]);
+    if (!ea) continue;
+    for (int i = 0; i < D; i++)
+      for (int l = 0; l < D; l++) {
+        int el = end_of(g, l, p[l]);
+        if (!el) continue;
+        R c0 = R(3 * el) / R(2.0 * g.h[l]);
+        dg[i] += R(ea) * cfull<D, K, R>(cc, i, a, i, l) * c0;
+      }
+  }
+}
+
+// ---- reductions ----
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of v over a 256-thread block, written by thread 0 to *dst.
+__device__ __forceinline__ void block_sum_256(double v, double *dst) {
+  __shared__ double ws[4];
+  const int t = threadIdx.x + threadIdx.y * blockDim.x;
+  v = wave_sum(v);
+  if ((t & 63) == 0) ws[t >> 6] = v;
+  __syncthreads();
+  if (t == 0) *dst = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+}  // namespace emg

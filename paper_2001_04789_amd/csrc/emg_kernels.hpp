@@ -1,0 +1,498 @@
+// gfx950 kernels of the multigrid elasticity solver.  One thread per node,
+// 64 x 4 thread blocks (one wavefront per x-row of a tile), x fastest so
+// every load of a field component is a coalesced row of 64 nodes.
+#pragma once
+#include "emg_device.hpp"
+
+namespace emg {
+
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
+
+constexpr int BX = 64, BY = 4;
+
+__device__ __forceinline__ bool skip(const Ctl *ctl) { return ctl != nullptr && ctl->done != 0; }
+
+__device__ __forceinline__ long long block_linear() {
+  return ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+// Operator application / residual / damped Jacobi sweep on one level.
+//   APPLY : out = D_H u
+//   RESID : out = f - D_H u                (norm partials if `partial`)
+//   JACOBI: out = u + omega (f - D_H u)/diag, Dirichlet rows out = f
+//           (norm partials of f - D_H u, i.e. of the input's residual, if `partial`)
+// Norm partials sum squares over non-Dirichlet rows, one value per block.
+template <int D, int K, typename R, int MODE, typename TO>
+__global__ __launch_bounds__(256) void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
+                                                 const R *__restrict__ f, TO *__restrict__ out, R omega,
+                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  double nrm = 0.0;
+  if (x < g.m[0] && y < g.m[1]) {
+    const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+    const int p[3] = {x, y, z};
+    const int cls = row_class(g, p);
+    R acc[D], dg[D];
+    rows_at<D, K, R>(g, C, PtrU<R>{u, g.N}, n, p, cls, acc, dg);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const long long q = i * g.N + n;
+      if constexpr (MODE == MODE_APPLY) {
+        out[q] = TO(acc[i]);
+      } else if constexpr (MODE == MODE_RESID) {
+        const R r = f[q] - acc[i];
+        out[q] = TO(r);
+        if (cls != ROW_DIR) nrm += double(r) * double(r);
+      } else {
+        const R r = f[q] - acc[i];
+        if (cls == ROW_DIR) {
+          out[q] = TO(f[q]);
+        } else {
+          out[q] = TO(u[q] + omega * r / dg[i]);
+          nrm += double(r) * double(r);
+        }
+      }
+    }
+  }
+  if (partial) block_sum_256(nrm, partial + block_linear());
+}
+
+// FP64 residual of the refined iterate for mixed-precision refinement:
+// uo = ui + e (e: FP32 correction), r = f - D_H uo written as FP32, norm partials.
+template <int D, int K>
+struct SumU {
+  const double *__restrict__ u;
+  const float *__restrict__ e;
+  long long N;
+  __device__ __forceinline__ double operator()(int k, long long i) const { return u[k * N + i] + double(e[k * N + i]); }
+};
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_resid_update(Geom g, const double *__restrict__ C, const double *__restrict__ ui,
+                                                      const float *__restrict__ e, const double *__restrict__ f,
+                                                      double *__restrict__ uo, float *__restrict__ r32,
+                                                      double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  double nrm = 0.0;
+  if (x < g.m[0] && y < g.m[1]) {
+    const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+    const int p[3] = {x, y, z};
+    const int cls = row_class(g, p);
+    double acc[D], dg[D];
+    rows_at<D, K, double>(g, C, SumU<D, K>{ui, e, g.N}, n, p, cls, acc, dg);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const long long q = i * g.N + n;
+      const double v = ui[q] + double(e[q]);
+      const double r = f[q] - acc[i];
+      uo[q] = v;
+      r32[q] = float(r);
+      if (cls != ROW_DIR) nrm += r * r;
+    }
+  }
+  block_sum_256(nrm, partial + block_linear());
+}
+
+// First sweep from a zero initial guess: out = omega f / diag (Dirichlet: f).
+template <int D, int K, typename R>
+__global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
+                                                     R *__restrict__ out, R omega, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= g.m[0] || y >= g.m[1]) return;
+  const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+  const int p[3] = {x, y, z};
+  const int cls = row_class(g, p);
+  R dg[D];
+  diag_at<D, K, R>(g, C, n, p, cls, dg);
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const long long q = i * g.N + n;
+    out[q] = (cls == ROW_DIR) ? f[q] : omega * f[q] / dg[i];
+  }
+}
+
+// Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
+// axis on whose end the coarse node sits only the coincident fine node
+// enters; Dirichlet coarse rows get 0.
+template <int D, typename RI, typename RO>
+__global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf, RO *__restrict__ fc,
+                                                  const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= gc.m[0] || y >= gc.m[1]) return;
+  const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
+  const int P[3] = {x, y, z};
+  const int cls = row_class(gc, P);
+  if (cls == ROW_DIR) {
+    for (int i = 0; i < D; i++) fc[i * gc.N + nc] = RO(0);
+    return;
+  }
+  const int pf[3] = {2 * x, 2 * y, 2 * z};
+  const long long nf = ((long long)pf[2] * gf.m[1] + pf[1]) * gf.m[0] + pf[0];
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  long long off[3][3];
+  for (int a = 0; a < 3; a++) {
+    off[a][0] = off[a][1] = off[a][2] = 0;
+    if (a < D && end_of(gc, a, P[a]) == 0) {
+      lo[a] = -1;
+      hi[a] = 1;
+      off[a][0] = shift(gf, a, pf[a], -1);
+      off[a][2] = shift(gf, a, pf[a], 1);
+    }
+  }
+  RI acc[D];
+  for (int i = 0; i < D; i++) acc[i] = RI(0);
+  for (int oz = lo[2]; oz <= hi[2]; oz++)
+    for (int oy = lo[1]; oy <= hi[1]; oy++)
+      for (int ox = lo[0]; ox <= hi[0]; ox++) {
+        RI w = RI(1);
+        if (hi[0]) w *= (ox == 0) ? RI(0.5) : RI(0.25);
+        if (hi[1]) w *= (oy == 0) ? RI(0.5) : RI(0.25);
+        if (hi[2]) w *= (oz == 0) ? RI(0.5) : RI(0.25);
+        const long long q = nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1];
+        for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + q];
+      }
+  for (int i = 0; i < D; i++) fc[i * gc.N + nc] = RO(acc[i]);
+}
+
+// u_fine += bilinear/trilinear interpolation of the coarse correction;
+// Dirichlet fine rows untouched.
+template <int D, typename RC, typename RF>
+__global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
+                                                     const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= gf.m[0] || y >= gf.m[1]) return;
+  const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
+  const int p[3] = {x, y, z};
+  if (row_class(gf, p) == ROW_DIR) return;
+  const int b[3] = {x >> 1, y >> 1, z >> 1};
+  const long long nb = ((long long)b[2] * gc.m[1] + b[1]) * gc.m[0] + b[0];
+  int cnt[3];
+  long long o1[3];
+  for (int a = 0; a < 3; a++) {
+    cnt[a] = (a < D && (p[a] & 1)) ? 2 : 1;
+    o1[a] = cnt[a] == 2 ? shift(gc, a, b[a], 1) : 0;
+  }
+  RC acc[D];
+  for (int i = 0; i < D; i++) acc[i] = RC(0);
+  for (int cz = 0; cz < cnt[2]; cz++)
+    for (int cy = 0; cy < cnt[1]; cy++)
+      for (int cx = 0; cx < cnt[0]; cx++) {
+        RC w = RC(1);
+        if (cnt[0] == 2) w *= RC(0.5);
+        if (cnt[1] == 2) w *= RC(0.5);
+        if (cnt[2] == 2) w *= RC(0.5);
+        const long long q = nb + (cx ? o1[0] : 0) + (cy ? o1[1] : 0) + (cz ? o1[2] : 0);
+        for (int i = 0; i < D; i++) acc[i] += w * ec[i * gc.N + q];
+      }
+  for (int i = 0; i < D; i++) uf[i * gf.N + n] += RF(acc[i]);
+}
+
+// Coarse-level moduli: full weighting of each stored component, injection
+// along an axis on whose end the coarse node sits.
+template <typename R>
+__global__ __launch_bounds__(256) void k_coarsen(Geom gf, Geom gc, int nc, const R *__restrict__ Cf, R *__restrict__ Cc) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= gc.m[0] || y >= gc.m[1]) return;
+  const long long n = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
+  const int P[3] = {x, y, z};
+  const int pf[3] = {2 * x, 2 * y, 2 * z};
+  const long long nf = ((long long)pf[2] * gf.m[1] + pf[1]) * gf.m[0] + pf[0];
+  int hi[3] = {0, 0, 0};
+  long long off[3][3];
+  for (int a = 0; a < 3; a++) {
+    off[a][0] = off[a][1] = off[a][2] = 0;
+    if (a < gc.dim && end_of(gc, a, P[a]) == 0) {
+      hi[a] = 1;
+      off[a][0] = shift(gf, a, pf[a], -1);
+      off[a][2] = shift(gf, a, pf[a], 1);
+    }
+  }
+  for (int c = 0; c < nc; c++) {
+    R acc = R(0);
+    for (int oz = -hi[2]; oz <= hi[2]; oz++)
+      for (int oy = -hi[1]; oy <= hi[1]; oy++)
+        for (int ox = -hi[0]; ox <= hi[0]; ox++) {
+          R w = R(1);
+          if (hi[0]) w *= (ox == 0) ? R(0.5) : R(0.25);
+          if (hi[1]) w *= (oy == 0) ? R(0.5) : R(0.25);
+          if (hi[2]) w *= (oz == 0) ? R(0.5) : R(0.25);
+          acc += w * Cf[c * gf.N + nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1]];
+        }
+    Cc[c * gc.N + n] = acc;
+  }
+}
+
+// Face data of all faces (d components per face node, normal axis extent 1).
+struct Faces {
+  const double *p[6];
+};
+
+__device__ __forceinline__ double face_val(const Geom &g, const Faces &F, int f, const int p[3], int i) {
+  const double *a = F.p[f];
+  if (!a) return 0.0;
+  const int ax = f / 2;
+  int q[3] = {p[0], p[1], p[2]}, fm[3] = {g.m[0], g.m[1], g.m[2]};
+  q[ax] = 0;
+  fm[ax] = 1;
+  const long long fn = (long long)fm[0] * fm[1] * fm[2];
+  return a[i * fn + ((long long)q[2] * fm[1] + q[1]) * fm[0] + q[0]];
+}
+
+// C:E contracted on the last pair: sum_kl C_ijkl E_kl for node moduli c[]
+// and symmetric tensor E given by its Voigt-ordered tensor components.
+template <int D, int K>
+__device__ __forceinline__ double c_dot_e(const double *c, const double *E, int i, int j) {
+  double s = 0.0;
+  for (int k = 0; k < D; k++)
+    for (int l = 0; l < D; l++) s += cfull<D, K, double>(c, i, j, k, l) * E[vslot<D>(k, l)];
+  return s;
+}
+
+// Right-hand side: interior -b + d_j(C_ijkl eps0_kl) by the product rule
+// (= -(D(0) + b), Sec. 2.1.1); traction rows sum_f t0_f + C eps0 n_f;
+// Dirichlet rows u0 of the lowest-numbered Dirichlet face.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ C, const double *__restrict__ eps,
+                                             const double *__restrict__ b, Faces F, double *__restrict__ f) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= g.m[0] || y >= g.m[1]) return;
+  constexpr int NC = nmod<D, K>(), NE = nvoigt<D>();
+  const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+  const int p[3] = {x, y, z};
+  const int cls = row_class(g, p);
+  double cc[NC], ec[NE];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  for (int c = 0; c < NE; c++) ec[c] = eps ? eps[c * g.N + n] : 0.0;
+  for (int i = 0; i < D; i++) {
+    double acc = 0.0;
+    if (cls == ROW_DIR) {
+      for (int fc = 0; fc < 2 * D; fc++) {
+        const int e = end_of(g, fc / 2, p[fc / 2]);
+        if (((fc & 1) ? e > 0 : e < 0) && g.bc[fc] == BC_DIR) {
+          acc = face_val(g, F, fc, p, i);
+          break;
+        }
+      }
+    } else if (cls == ROW_INT) {
+      if (b) acc -= b[i * g.N + n];
+      if (eps) {
+        for (int j = 0; j < D; j++) {
+          const long long sp = shift(g, j, p[j], 1), sm = shift(g, j, p[j], -1);
+          double cp[NC], cm[NC], ep[NE], em[NE];
+          for (int c = 0; c < NC; c++) {
+            cp[c] = C[c * g.N + n + sp];
+            cm[c] = C[c * g.N + n + sm];
+          }
+          for (int c = 0; c < NE; c++) {
+            ep[c] = eps[c * g.N + n + sp];
+            em[c] = eps[c * g.N + n + sm];
+          }
+          const double inv2h = 0.5 / g.h[j];
+          acc += (c_dot_e<D, K>(cp, ec, i, j) - c_dot_e<D, K>(cm, ec, i, j)) * inv2h;
+          acc += (c_dot_e<D, K>(cc, ep, i, j) - c_dot_e<D, K>(cc, em, i, j)) * inv2h;
+        }
+      }
+    } else {
+      for (int fc = 0; fc < 2 * D; fc++) {
+        const int a = fc / 2;
+        const int e = end_of(g, a, p[a]);
+        if (!((fc & 1) ? e > 0 : e < 0)) continue;
+        acc += face_val(g, F, fc, p, i);
+        if (eps) acc += double(e) * c_dot_e<D, K>(cc, ec, i, a);
+      }
+    }
+    f[i * g.N + n] = acc;
+  }
+}
+
+// Stress sigma_ij = C_ijkl (du_k/dx_l - eps0_kl): central differences, 3-point
+// one-sided on non-periodic ends; Voigt output.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_stress(Geom g, const double *__restrict__ C, const double *__restrict__ eps,
+                                                const double *__restrict__ u, double *__restrict__ sig) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= g.m[0] || y >= g.m[1]) return;
+  constexpr int NC = nmod<D, K>(), NE = nvoigt<D>();
+  const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+  const int p[3] = {x, y, z};
+  double cc[NC];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  double E[NE];   // strain minus eigenstrain, tensor components in Voigt order
+  double Gd[D][D];
+  for (int l = 0; l < D; l++) {
+    const int en = end_of(g, l, p[l]);
+    const double h = g.h[l];
+    for (int k = 0; k < D; k++) {
+      const double *uk = u + k * g.N;
+      if (en != 0) {
+        const int s = -en;
+        const long long s1 = shift(g, l, p[l], s), s2 = shift(g, l, p[l], 2 * s);
+        Gd[k][l] = s * (-3.0 * uk[n] + 4.0 * uk[n + s1] - uk[n + s2]) / (2.0 * h);
+      } else {
+        Gd[k][l] = (uk[n + shift(g, l, p[l], 1)] - uk[n + shift(g, l, p[l], -1)]) / (2.0 * h);
+      }
+    }
+  }
+  for (int k = 0; k < D; k++)
+    for (int l = k; l < D; l++) {
+      const int v = vslot<D>(k, l);
+      E[v] = 0.5 * (Gd[k][l] + Gd[l][k]) - (eps ? eps[v * g.N + n] : 0.0);
+    }
+  for (int i = 0; i < D; i++)
+    for (int j = i; j < D; j++) sig[vslot<D>(i, j) * g.N + n] = c_dot_e<D, K>(cc, E, i, j);
+}
+
+// Dirichlet lift: u = f on Dirichlet rows, 0 elsewhere.
+template <int D>
+__global__ __launch_bounds__(256) void k_lift(Geom g, const double *__restrict__ f, double *__restrict__ u) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= g.m[0] || y >= g.m[1]) return;
+  const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
+  const int p[3] = {x, y, z};
+  const bool dir = row_class(g, p) == ROW_DIR;
+  for (int i = 0; i < D; i++) u[i * g.N + n] = dir ? f[i * g.N + n] : 0.0;
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(256) void k_cast(long long n, const A *__restrict__ in, B *__restrict__ out,
+                                              const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) out[i] = B(in[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(long long n, T *__restrict__ out, T v) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) out[i] = v;
+}
+
+// Sum the norm partials in a fixed order and update the control block.
+// `ans` is the buffer index of the iterate whose residual was measured.
+__global__ __launch_bounds__(256) void k_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans) {
+  if (ctl->done) return;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+  __shared__ double tot;
+  block_sum_256(s, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v = tot;
+    ctl->ans = ans;
+    if (!(v == v) || v > 1.0e300) {
+      ctl->done = 2;
+      return;
+    }
+    if (ctl->r0sq < 0.0) ctl->r0sq = v;
+    ctl->rsq = v;
+    if (v <= ctl->tol2 * ctl->r0sq) ctl->done = 1;
+    else if (ctl->cycles >= ctl->max_cycles) ctl->done = 3;
+    else ctl->cycles += 1;
+  }
+}
+
+// Store the summed partials as the reference norm (warm starts measure
+// convergence relative to the Dirichlet lift's residual).
+__global__ __launch_bounds__(256) void k_set_r0(const double *__restrict__ partial, long long nparts, Ctl *ctl) {
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+  __shared__ double tot;
+  block_sum_256(s, &tot);
+  __syncthreads();
+  if (threadIdx.x == 0) ctl->r0sq = tot;
+}
+
+// ---- coarsest level: dense matrix by unit vectors, Gauss-Jordan inverse ----
+
+// M (n x 2n, row-major) = [A | I] with A the level's D_H.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_bottom_assemble(Geom g, const double *__restrict__ C, double *__restrict__ M,
+                                                         int nunk) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;
+  if (r >= nunk) return;
+  const int i = r / (int)g.N;
+  const long long n = r % g.N;
+  const int p[3] = {int(n % g.m[0]), int((n / g.m[0]) % g.m[1]), int(n / ((long long)g.m[0] * g.m[1]))};
+  const int cls = row_class(g, p);
+  double acc[D], dg[D];
+  rows_at<D, K, double>(g, C, UnitU<double>{q, g.N}, n, p, cls, acc, dg);
+  const long long w = 2LL * nunk;
+  M[r * w + q] = acc[i];
+  M[r * w + nunk + q] = (r == q) ? 1.0 : 0.0;
+}
+
+// Pivot step k: choose the largest |M[i][k]|, i >= k, swap it into row k,
+// scale row k to a unit pivot.  status[0] = 1 if the pivot is zero.
+__global__ __launch_bounds__(256) void k_gj_pivot(double *__restrict__ M, int n, int k, int *status) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  const long long w = 2LL * n;
+  double best = -1.0;
+  int arg = k;
+  for (int i = k + t; i < n; i += 256) {
+    const double v = fabs(M[i * w + k]);
+    if (v > best) { best = v; arg = i; }
+  }
+  bv[t] = best;
+  bi[t] = arg;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      if (bv[t + s] > bv[t] || (bv[t + s] == bv[t] && bi[t + s] < bi[t])) { bv[t] = bv[t + s]; bi[t] = bi[t + s]; }
+    }
+    __syncthreads();
+  }
+  const int pr = bi[0];
+  if (pr != k)
+    for (long long j = t; j < w; j += 256) {
+      const double a = M[k * w + j];
+      M[k * w + j] = M[pr * w + j];
+      M[pr * w + j] = a;
+    }
+  __syncthreads();
+  if (t == 0) {
+    piv = M[k * w + k];
+    if (piv == 0.0) status[0] = 1;
+  }
+  __syncthreads();
+  const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+  for (long long j = k + t; j < w; j += 256) M[k * w + j] *= inv;
+}
+
+// Elimination step k: M[i][j] -= M[i][k] M[k][j] for i != k, j > k.
+__global__ __launch_bounds__(256) void k_gj_elim(double *__restrict__ M, int n, int k) {
+  const long long w = 2LL * n;
+  const long long j = (long long)k + 1 + (long long)blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= w || i == k) return;
+  M[i * w + j] -= M[i * w + k] * M[k * w + j];
+}
+
+__global__ __launch_bounds__(256) void k_gj_extract(const double *__restrict__ M, int n, double *__restrict__ Ainv) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const long long i = idx / n, j = idx % n;
+  Ainv[idx] = M[i * 2LL * n + n + j];
+}
+
+// e = A^-1 f in FP64, one wavefront per row.
+template <typename RI, typename RO>
+__global__ __launch_bounds__(256) void k_bottom_solve(const double *__restrict__ Ainv, int n, const RI *__restrict__ f,
+                                                      RO *__restrict__ e, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += Ainv[(long long)row * n + j] * double(f[j]);
+  s = wave_sum(s);
+  if (lane == 0) e[row] = RO(s);
+}
+
+}  // namespace emg

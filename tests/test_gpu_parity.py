@@ -1,0 +1,254 @@
+"""GPU parity: every step of the HIP path, called through the C ABI, against
+the CPU oracle on the same seeded inputs.
+
+Per-step checks (operator, residual, Jacobi sweep, restriction,
+interpolation, coarse moduli, coarsest solve, right-hand side, stress) use
+grids that span several 64 x 4 tiles with ragged tails in x and y.  FP64
+steps must agree to 1e-12 of the output's magnitude (different summation
+order and fused multiply-adds only); FP32 steps to 2e-5.  Whole solves must
+reach relative residual 1e-10 and agree with the oracle's solution (iterated
+to 1e-13) to 1e-8 in relative 2-norm.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def emg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_04789_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(emg):
+    c = emg.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype=dtype)
+
+
+def host(t):
+    return t.detach().to("cpu", dtype=torch.float64).numpy()
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = {
+    "3d_aniso_mixed_bc": dict(dim=3, n=(65, 65, 33), bc=("dirichlet", "traction", "traction", "traction", "traction", "dirichlet"),
+                              kind="aniso"),
+    "3d_iso_traction": dict(dim=3, n=(65, 65, 33), bc=("traction", "traction", "traction", "traction", "dirichlet", "traction"),
+                            kind="iso"),
+    "3d_aniso_periodic": dict(dim=3, n=(81, 81, 33), bc=("periodic", "periodic", "periodic", "periodic", "dirichlet", "dirichlet"),
+                              kind="aniso"),
+    "2d_iso": dict(dim=2, n=(129, 97), bc=("traction", "traction", "dirichlet", "traction", "periodic", "periodic"), kind="iso"),
+    "2d_aniso_periodic": dict(dim=2, n=(129, 97), bc=("periodic", "periodic", "dirichlet", "traction", "periodic", "periodic"),
+                              kind="aniso"),
+}
+
+
+def make_case(name, seed=7):
+    c = CASES[name]
+    return synth.random_problem(c["dim"], c["n"], c["bc"], c["kind"], seed=seed, with_body=True,
+                                lo=(0.0, -0.2, 0.1), hi=(1.0, 0.7, 0.6))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_level_steps_match_oracle(emg, ctx, name):
+    spec = make_case(name)
+    print(f"[gpu] level steps {name} m={spec.m}", flush=True)
+    prob = emg.Problem.from_spec(ctx, spec)
+    g0 = oracle.Grid.of(spec)
+    grids = oracle.hierarchy(g0)
+    assert prob.num_levels() == len(grids)
+    for l, g in enumerate(grids):
+        m, h = prob.level_shape(l)
+        assert m == g.m and np.allclose(h, g.h, rtol=1e-15)
+    # coarse moduli
+    Cs = [spec.C]
+    for l in range(1, len(grids)):
+        Cs.append(oracle.coarsen_moduli(grids[l - 1], grids[l], Cs[-1]))
+    for l, g in enumerate(grids):
+        out = torch.empty(g.shape(g.ncomp_moduli), dtype=torch.float64, device=DEV)
+        prob.level_moduli(l, out)
+        assert rel_err(host(out), Cs[l]) <= 1e-14, l
+    rng = np.random.default_rng(3)
+    d = spec.dim
+    for l in (0, 1):
+        g = grids[l]
+        u = rng.standard_normal(g.shape(d))
+        f = rng.standard_normal(g.shape(d))
+        ref_apply = oracle.apply(g, Cs[l], u)
+        ref_res = oracle.residual(g, Cs[l], u, f)
+        ref_jac = oracle.jacobi(g, Cs[l], u, f, 2.0 / 3.0)
+        for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("mixed", torch.float32, 2e-5)):
+            ud, fd = dev(u, dt), dev(f, dt)
+            out = torch.empty_like(ud)
+            prob.level_apply(l, ud, out, precision=prec)
+            assert rel_err(host(out), ref_apply) <= tol, (l, prec, "apply")
+            prob.level_residual(l, ud, fd, out, precision=prec)
+            assert rel_err(host(out), ref_res) <= tol, (l, prec, "residual")
+            prob.level_jacobi(l, ud, fd, out, precision=prec)
+            assert rel_err(host(out), ref_jac) <= tol, (l, prec, "jacobi")
+        # transfers between l and l+1
+        gc = grids[l + 1]
+        fc_ref = oracle.restrict(g, gc, f)
+        ec = rng.standard_normal(gc.shape(d))
+        up_ref = oracle.prolong_add(gc, g, ec, u)
+        for prec, dt, tol in (("fp64", torch.float64, 1e-14), ("mixed", torch.float32, 1e-6)):
+            fc = torch.empty(gc.shape(d), dtype=dt, device=DEV)
+            prob.level_restrict(l, dev(f, dt), fc, precision=prec)
+            assert rel_err(host(fc), fc_ref) <= tol, (l, prec, "restrict")
+            ud = dev(u, dt)
+            prob.level_prolong_add(l, dev(ec, dt), ud, precision=prec)
+            assert rel_err(host(ud), up_ref) <= tol, (l, prec, "prolong")
+    # coarsest exact solve
+    gb = grids[-1]
+    fb = rng.standard_normal(gb.shape(d))
+    A = oracle.dense_matrix(gb, Cs[-1])
+    eb_ref = np.linalg.solve(A, fb.ravel()).reshape(fb.shape)
+    eb = torch.empty(gb.shape(d), dtype=torch.float64, device=DEV)
+    prob.level_bottom_solve(dev(fb), eb)
+    assert rel_err(host(eb), eb_ref) <= 1e-10
+    # right-hand side and stress
+    f_ref = oracle.rhs(g0, spec.C, spec.eps0, spec.b, spec.face)
+    assert rel_err(prob.rhs(), f_ref) <= 1e-12
+    u = rng.standard_normal(g0.shape(d)) * 1e-3
+    prob.set_displacement(u)
+    s_ref = oracle.stress(g0, spec.C, spec.eps0, u)
+    assert rel_err(prob.stress(), s_ref) <= 1e-12
+    prob.close()
+
+
+SOLVES = {
+    "inclusion2d_65": lambda: synth.inclusion_2d(n=65),
+    "polycrystal_17": lambda: synth.polycrystal_3d(n=17, grains=8, seed=2002),
+    "polycrystal_33_sphere": lambda: synth.polycrystal_3d(n=33, grains=16, seed=2003, inclusion=(3.0, 2e-3)),
+    "random3d_iso_traction": lambda: synth.random_problem(3, (17, 17, 17), ("dirichlet", "traction", "traction", "traction",
+                                                                            "traction", "traction"), "iso", seed=9),
+    "random2d_aniso": lambda: synth.random_problem(2, (65, 33), ("dirichlet", "dirichlet", "traction", "traction",
+                                                                 "periodic", "periodic"), "aniso", seed=10, with_body=True),
+}
+
+_ORACLE_CACHE = {}
+
+
+def oracle_solution(name):
+    if name not in _ORACLE_CACHE:
+        spec = SOLVES[name]()
+        _ORACLE_CACHE[name] = (spec, oracle.solve(spec, tol=1e-13, max_cycles=400))
+    return _ORACLE_CACHE[name]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(SOLVES))
+def test_solve_matches_oracle(emg, ctx, name, precision):
+    spec, ref = oracle_solution(name)
+    print(f"[gpu] solve {name} {precision} m={spec.m}", flush=True)
+    prob = emg.Problem.from_spec(ctx, spec)
+    st = prob.solve(rtol=1e-10, max_cycles=400, precision=precision)
+    assert st["converged"] and st["rel_res"] <= 1e-10
+    u = prob.displacement()
+    err = np.linalg.norm(u - ref.u) / np.linalg.norm(ref.u)
+    print(f"[gpu]   cycles={st['cycles']} rel_res={st['rel_res']:.2e} rel_err={err:.2e}", flush=True)
+    assert err <= 1e-8
+    # the oracle's own residual of the GPU iterate confirms the tolerance
+    g = oracle.Grid.of(spec)
+    C = spec.C
+    r = oracle.residual(g, C, u, ref.rhs)
+    lift = np.where(oracle.dirichlet_mask(g), ref.rhs, 0.0)
+    r0 = oracle.residual(g, C, lift, ref.rhs)
+    assert oracle.norm(g, r) / oracle.norm(g, r0) <= 1.2e-10
+    s = prob.stress()
+    s_ref = oracle.stress(g, C, spec.eps0, ref.u)
+    assert np.linalg.norm(s - s_ref) / np.linalg.norm(s_ref) <= 1e-7
+    prob.close()
+
+
+def test_fp64_cycle_count_matches_oracle(emg, ctx):
+    """Same algorithm: the FP64 GPU solve and the oracle need the same number
+    of V-cycles to reach 1e-10."""
+    spec = synth.inclusion_2d(n=65)
+    ref = oracle.solve(spec, tol=1e-10, max_cycles=400)
+    prob = emg.Problem.from_spec(ctx, spec)
+    st = prob.solve(rtol=1e-10, max_cycles=400)
+    assert abs(st["cycles"] - ref.cycles) <= 1
+    prob.close()
+
+
+def test_graph_and_eager_agree_bitwise(emg, ctx):
+    spec = synth.polycrystal_3d(n=17, grains=8, seed=2002)
+    out = []
+    for use_graph in (1, 0):
+        prob = emg.Problem.from_spec(ctx, spec)
+        st = prob.solve(rtol=1e-10, use_graph=use_graph, check_every=3)
+        out.append((st["cycles"], prob.displacement()))
+        prob.close()
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_check_every_does_not_change_result(emg, ctx):
+    spec = synth.inclusion_2d(n=33)
+    res = []
+    for k in (1, 4, 7):
+        prob = emg.Problem.from_spec(ctx, spec)
+        st = prob.solve(rtol=1e-10, check_every=k)
+        res.append((st["cycles"], prob.displacement()))
+        prob.close()
+    assert res[0][0] == res[1][0] == res[2][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][1], res[2][1])
+
+
+def test_error_paths(emg, ctx):
+    spec = synth.inclusion_2d(n=33)
+    bad = [dict(bc=("traction",) * 4 + ("periodic",) * 2),          # no Dirichlet face
+           dict(n=(34, 33, 1)),                                        # odd cells do not coarsen to the bottom
+           dict(bc=("periodic", "traction", "dirichlet", "traction", "periodic", "periodic"))]
+    for kw in bad:
+        args = dict(dim=2, n=spec.n, lo=spec.lo, hi=spec.hi, bc=spec.bc, kind="iso")
+        args.update(kw)
+        with pytest.raises(emg.EmgError) as ei:
+            emg.Problem(ctx, **args)
+        assert ei.value.status == emg.EMG_EINVAL
+    prob = emg.Problem(ctx, 2, spec.n, spec.lo, spec.hi, spec.bc, "iso")
+    st = prob.solve(raise_on_error=False)
+    assert st["status"] == emg.EMG_ESTATE
+    prob.set_moduli(spec.C)
+    prob.set_eigenstrain(spec.eps0)
+    st = prob.solve(raise_on_error=False, max_cycles=3)
+    assert st["status"] == emg.EMG_ENOTCONV and st["cycles"] == 3
+    C = spec.C.copy()
+    C[1, 0, 10, 10] = np.nan
+    prob.set_moduli(C)
+    st = prob.solve(raise_on_error=False)
+    assert st["status"] in (emg.EMG_EDIVERGED, emg.EMG_EINVAL)
+    prob.close()
+    small = emg.Context(0, hbm_budget_bytes=1 << 16)
+    with pytest.raises(emg.EmgError) as ei:
+        emg.Problem(small, 2, spec.n, spec.lo, spec.hi, spec.bc, "iso")
+    assert ei.value.status == emg.EMG_ENOMEM
+    small.close()
+
+
+def test_warm_start_from_solution_needs_no_cycle(emg, ctx):
+    spec = synth.inclusion_2d(n=33)
+    prob = emg.Problem.from_spec(ctx, spec)
+    prob.solve(rtol=1e-10)
+    st = prob.solve(rtol=1e-6, warm_start=1)
+    assert st["cycles"] <= 1
+    prob.close()
