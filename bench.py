@@ -1,0 +1,188 @@
+"""Benchmark: solve DoF/s of the multigrid elasticity solve on one MI355X.
+
+Workload: 3D Voronoi polycrystal, 129^3 nodes on [0,1]^3 (128 x 128 x 129
+stored nodes, periodic x/y), 16 grains with uniformly random orientations of
+a cubic crystal (C11=1.68, C12=1.21, C44=0.75), grain boundaries smoothed over
+about two cells, u=0 on z=0 and u=(0,0,1e-3) on z=1; plain FP64 V-cycles
+(damped Jacobi omega=2/3, 2 pre + 2 post sweeps) to relative residual 1e-10.
+
+A step is one whole solve with every input already resident in HBM: moduli,
+eigenstrain and face data copied device-to-device into the problem (which
+invalidates its hierarchy), hierarchy setup (coarse moduli, coarsest-level
+inverse), right-hand side, V-cycles to 1e-10, and the stress field.  `value`
+is DoF x steps / wall time of the timed steps.  The same steps are repeated
+with the mixed-precision solve (FP32 V-cycle inside FP64 refinement) and
+reported under "mixed".
+
+Roofline: the dominant kernel is the finest-level FP64 Jacobi sweep; its
+average duration is measured with HIP events on the problem's stream
+(emg_kernel_time) right after the timed steps; its algorithmic bytes are
+240 B per node (read u 3x8, C 21x8, f 3x8; write u 3x8).
+
+cpu_baseline: the CPU oracle (plain FP64 C + OpenMP) on this host, on a
+bounded sample of the same workload: hierarchy setup, right-hand side and
+a fixed number of V-cycles are timed, and the solve time is scaled to the
+GPU's cycle count (same algorithm, same cycle count).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=129, help="nodes per axis")
+    ap.add_argument("--grains", type=int, default=16)
+    ap.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample (0 = skip)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
+                         "(used for hardware-counter runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, gpu_cycles, ncycles):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    g = oracle.Grid.of(spec)
+    H = oracle.Hierarchy(g, spec.C)
+    f = oracle.rhs(g, H.C[0], spec.eps0, spec.b, spec.face)
+    u = np.where(oracle.dirichlet_mask(g), f, 0.0)
+    t1 = time.perf_counter()
+    for _ in range(ncycles):
+        u = oracle.vcycle(H, 0, u, f)
+        _ = oracle.norm(g, oracle.residual(g, H.C[0], u, f))
+    t2 = time.perf_counter()
+    per_cycle = (t2 - t1) / ncycles
+    est = (t1 - t0) + gpu_cycles * per_cycle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": spec.dofs() / est, "unit": "DoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"setup + rhs + {ncycles} V-cycle(s) + residual norm on the full {spec.n[0]}^3 workload "
+                      f"({t2 - t0:.1f} s); solve time scaled to {gpu_cycles} cycles",
+            "seconds_per_cycle": per_cycle, "setup_seconds": t1 - t0}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is single-GPU", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_2001_04789_amd as emg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spec = synth.polycrystal_3d(n=args.n, grains=args.grains, seed=2002)
+    ctx = emg.Context(0)
+    prob = emg.Problem(ctx, spec.dim, spec.n, spec.lo, spec.hi, spec.bc, spec.kind)
+    dev = "cuda:0"
+    C_d = torch.from_numpy(spec.C).to(dev)
+    faces_d = {f: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for f, v in spec.face.items()}
+    sigma_d = torch.empty((6,) + spec.C.shape[1:], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(precision):
+        prob.set_moduli(C_d)
+        prob.set_eigenstrain(None)
+        for f in (4, 5):
+            prob.set_face(f, faces_d.get(f))
+        st = prob.solve(rtol=1e-10, max_cycles=400, precision=precision)
+        prob.stress(out=sigma_d)
+        return st
+
+    def timed(precision):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [step(precision) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, stats
+
+    if args.kernel_only:
+        prob.set_moduli(C_d)
+        st = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed")
+        ms64 = prob.kernel_time(0, level=0, precision="fp64", reps=args.kernel_reps)
+        ms32 = prob.kernel_time(0, level=0, precision="mixed", reps=args.kernel_reps)
+        src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.kernel_reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": True, "cycles": st["cycles"], "sweep_fp64_ms": ms64, "sweep_fp32_ms": ms32,
+                          "nodes": spec.nodes, "copy_bytes": 2 * src.numel() * 8, "copy_reps": args.kernel_reps}))
+        return
+
+    dt64, st64 = timed("fp64")
+    u64 = prob.displacement()
+    dofs = st64[0]["dofs"]
+    # dominant kernel: finest-level FP64 Jacobi sweep, HIP events on the problem's stream
+    ms_sweep = prob.kernel_time(0, level=0, precision="fp64", reps=args.kernel_reps)
+    nodes = spec.nodes
+    bytes_per_launch = 240 * nodes
+    achieved = bytes_per_launch / (ms_sweep * 1e-3) / 1e9
+    ms_sweep32 = prob.kernel_time(0, level=0, precision="mixed", reps=args.kernel_reps) if not args.no_mixed else None
+
+    out = {
+        "metric": "solve DoF/s at rel. residual 1e-10 (FP64 vs mixed); served p50/p99 latency",
+        "value": dofs * args.steps / dt64,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"polycrystal {args.n}^3 nodes, {args.grains} grains (seed 2002), periodic x/y, "
+                               f"uniaxial z displacement 1e-3, FP64 V(2,2) damped Jacobi to rel. residual 1e-10",
+                   "nodes": nodes, "dofs": dofs, "levels": prob.num_levels(),
+                   "step": "setup + rhs + solve + stress, inputs resident in HBM"},
+        "fp64": {"cycles": st64[-1]["cycles"], "rel_res": st64[-1]["rel_res"],
+                 "conv_factor": st64[-1]["conv_factor"],
+                 "solve_only_dofs_per_s": dofs / np.mean([s["solve_seconds"] for s in st64]),
+                 "solve_ms": 1e3 * float(np.mean([s["solve_seconds"] for s in st64])),
+                 "setup_ms": 1e3 * float(np.mean([s["setup_seconds"] for s in st64]))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stencil<3,ANISO,double,JACOBI> finest level",
+                     "avg_ms": ms_sweep, "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_mixed:
+        dt32, st32 = timed("mixed")
+        u32 = prob.displacement()
+        out["mixed"] = {
+            "value": dofs * args.steps / dt32, "ms_per_step": 1e3 * dt32 / args.steps,
+            "cycles": st32[-1]["cycles"], "rel_res": st32[-1]["rel_res"],
+            "solve_only_dofs_per_s": dofs / np.mean([s["solve_seconds"] for s in st32]),
+            "solve_ms": 1e3 * float(np.mean([s["solve_seconds"] for s in st32])),
+            "speedup_vs_fp64_step": dt64 / dt32,
+            "rel_diff_vs_fp64": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
+            "fp32_sweep_ms": ms_sweep32,
+            "fp32_sweep_gbs": 120 * nodes / (ms_sweep32 * 1e-3) / 1e9,
+        }
+    prob.close()
+    ctx.close()
+    if args.cpu_cycles > 0:
+        out["cpu_baseline"] = cpu_baseline(spec, out["fp64"]["cycles"], args.cpu_cycles)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

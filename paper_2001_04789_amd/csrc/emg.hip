@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -52,10 +53,27 @@ void dispatch(int D, int K, F &&f) {
 }
 
 dim3 grid_of(const Geom &g) { return dim3((g.m[0] + BX - 1) / BX, (g.m[1] + BY - 1) / BY, g.m[2]); }
+dim3 grid_zc(const Geom &g, int zc) {
+  return dim3((g.m[0] + BX - 1) / BX, (g.m[1] + BY - 1) / BY, (g.m[2] + zc - 1) / zc);
+}
+
+// Planes per workgroup of the z-marching generic kernels.  Measured on
+// MI355X (128 x 128 x 129 anisotropic FP64 sweep): 1 plane 256 us, 2: 271,
+// 4: 283, 8: 311, 16: 366 -- an XCD's L2 cannot hold the z-reuse window of
+// ~100 concurrent tiles at 240 B per node, so more planes per workgroup only
+// cost parallelism.  Default 1; EMG_ZC overrides for tuning.
+int choose_zc(const Geom &) {
+  if (const char *e = std::getenv("EMG_ZC")) {
+    const int v = std::atoi(e);
+    if (v >= 1) return v;
+  }
+  return 1;
+}
 const dim3 kBlock(BX, BY, 1);
 
 struct Level {
   Geom g{};
+  int zc = 1;        // z-planes per workgroup of the z-marching kernels
   double *C64 = nullptr;
   float *C32 = nullptr;
   double *u64[2] = {nullptr, nullptr};
@@ -142,8 +160,8 @@ Geom coarse_of(const Geom &g) {
   return c;
 }
 
-long long nblocks(const Geom &g) {
-  dim3 gr = grid_of(g);
+long long nblocks(const Geom &g, int zc) {
+  dim3 gr = grid_zc(g, zc);
   return (long long)gr.x * gr.y * gr.z;
 }
 
@@ -160,8 +178,8 @@ void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *
                     const Ctl *ctl) {
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), grid_of(L.g), kBlock, 0, p->stream, L.g, moduli<R>(L), u, f,
-                       out, omega, partial, ctl);
+    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), grid_zc(L.g, L.zc), kBlock, 0, p->stream, L.g, moduli<R>(L), u,
+                       f, out, omega, partial, ctl, L.zc);
   });
 }
 
@@ -210,7 +228,7 @@ void launch_fill(emg_problem *p, long long n, T *out, T v) {
 }
 
 void launch_check(emg_problem *p, long long nparts, int ans) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, p->stream, p->partial, nparts, p->ctl, ans);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, p->stream, p->partial, nparts, p->ctl, ans);
 }
 
 // ---- setup: coarse moduli, coarsest inverse, right-hand side ----
@@ -335,7 +353,7 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
   Level &L0 = p->lv[0];
   int cur = 0;
   launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[0], L0.f64, L0.u64[1], omega, p->partial, p->ctl);
-  launch_check(p, nblocks(L0.g), 0);
+  launch_check(p, nblocks(L0.g, L0.zc), 0);
   cur = 1;
   for (int s = 1; s < nu1; s++) {
     launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
@@ -359,10 +377,10 @@ void record_mixed_iter(emg_problem *p, int a, int nu1, int nu2, float omega) {
   Level &L0 = p->lv[0];
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_resid_update<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, L0.u64[a],
-                       L0.u32[0], L0.f64, L0.u64[a ^ 1], L0.f32, p->partial, p->ctl);
+    hipLaunchKernelGGL((k_resid_update<D, K>), grid_zc(L0.g, L0.zc), kBlock, 0, p->stream, L0.g, L0.C64, L0.u64[a],
+                       L0.u32[0], L0.f64, L0.u64[a ^ 1], L0.f32, p->partial, p->ctl, L0.zc);
   });
-  launch_check(p, nblocks(L0.g), a ^ 1);
+  launch_check(p, nblocks(L0.g, L0.zc), a ^ 1);
   const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega);
   if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
 }
@@ -538,7 +556,8 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
   }
   emg_status s;
   if ((s = dalloc(p, &p->Ainv, (size_t)nbot * nbot)) != EMG_OK) return bail(s);
-  p->npartial = nblocks(gs[0]);
+  for (auto &L : p->lv) L.zc = choose_zc(L.g);
+  p->npartial = nblocks(gs[0], 1);
   if ((s = dalloc(p, &p->partial, (size_t)p->npartial)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->ctl, 1)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->status, 4)) != EMG_OK) return bail(s);
@@ -661,7 +680,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
   if (opt.warm_start) {
     launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
-    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(256), 0, p->stream, p->partial, nblocks(L0.g), p->ctl);
+    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, nblocks(L0.g, L0.zc), p->ctl);
   }
   if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[0], 0.0f);
   HIPCK(hipGetLastError());

@@ -16,20 +16,44 @@ __device__ __forceinline__ long long block_linear() {
   return ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
+// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round-robin in
+// dispatch order, and each XCD has its own L2.  Renumber them so that XCD x
+// walks one contiguous run of tiles (x fastest, then y, then z): its tiles'
+// y- and z-neighbours then sit in the same L2 instead of being fetched again
+// from HBM by another XCD.  Returns the tile coordinates of this block.
+constexpr int kXCD = 8;
+__device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
+  const unsigned B = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const unsigned q = B / kXCD, r = B % kXCD;
+  const unsigned x = b % kXCD, i = b / kXCD;
+  const unsigned L = x * q + (x < r ? x : r) + i;
+  tx = L % gridDim.x;
+  ty = (L / gridDim.x) % gridDim.y;
+  tz = L / (gridDim.x * gridDim.y);
+}
+
 // Operator application / residual / damped Jacobi sweep on one level.
 //   APPLY : out = D_H u
 //   RESID : out = f - D_H u                (norm partials if `partial`)
 //   JACOBI: out = u + omega (f - D_H u)/diag, Dirichlet rows out = f
 //           (norm partials of f - D_H u, i.e. of the input's residual, if `partial`)
 // Norm partials sum squares over non-Dirichlet rows, one value per block.
+// Each workgroup walks `zc` consecutive z-planes of its 64 x 4 tile, so the
+// z-neighbours a plane needs were read one iteration earlier and are still
+// in L2 (a whole plane of a 128^2 anisotropic level is larger than an XCD's L2).
 template <int D, int K, typename R, int MODE, typename TO>
 __global__ __launch_bounds__(256) void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
                                                  const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
   if (skip(ctl)) return;
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y;
+  const int z0 = tz_ * zc, z1 = min(g.m[2], z0 + zc);
   double nrm = 0.0;
-  if (x < g.m[0] && y < g.m[1]) {
+  if (x < g.m[0] && y < g.m[1])
+  for (int z = z0; z < z1; z++) {
     const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
     const int p[3] = {x, y, z};
     const int cls = row_class(g, p);
@@ -72,11 +96,15 @@ template <int D, int K>
 __global__ __launch_bounds__(256) void k_resid_update(Geom g, const double *__restrict__ C, const double *__restrict__ ui,
                                                       const float *__restrict__ e, const double *__restrict__ f,
                                                       double *__restrict__ uo, float *__restrict__ r32,
-                                                      double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+                                                      double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
   if (skip(ctl)) return;
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y;
+  const int z0 = tz_ * zc, z1 = min(g.m[2], z0 + zc);
   double nrm = 0.0;
-  if (x < g.m[0] && y < g.m[1]) {
+  if (x < g.m[0] && y < g.m[1])
+  for (int z = z0; z < z1; z++) {
     const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
     const int p[3] = {x, y, z};
     const int cls = row_class(g, p);
@@ -100,7 +128,9 @@ template <int D, int K, typename R>
 __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
                                                      R *__restrict__ out, R omega, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= g.m[0] || y >= g.m[1]) return;
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
@@ -121,7 +151,9 @@ template <int D, typename RI, typename RO>
 __global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf, RO *__restrict__ fc,
                                                   const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -164,7 +196,9 @@ template <int D, typename RC, typename RF>
 __global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
                                                      const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
   const int p[3] = {x, y, z};
@@ -196,7 +230,9 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC 
 // along an axis on whose end the coarse node sits.
 template <typename R>
 __global__ __launch_bounds__(256) void k_coarsen(Geom gf, Geom gc, int nc, const R *__restrict__ Cf, R *__restrict__ Cc) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long n = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -259,7 +295,9 @@ __device__ __forceinline__ double c_dot_e(const double *c, const double *E, int 
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ C, const double *__restrict__ eps,
                                              const double *__restrict__ b, Faces F, double *__restrict__ f) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= g.m[0] || y >= g.m[1]) return;
   constexpr int NC = nmod<D, K>(), NE = nvoigt<D>();
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
@@ -315,7 +353,9 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_stress(Geom g, const double *__restrict__ C, const double *__restrict__ eps,
                                                 const double *__restrict__ u, double *__restrict__ sig) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= g.m[0] || y >= g.m[1]) return;
   constexpr int NC = nmod<D, K>(), NE = nvoigt<D>();
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
@@ -350,7 +390,9 @@ __global__ __launch_bounds__(256) void k_stress(Geom g, const double *__restrict
 // Dirichlet lift: u = f on Dirichlet rows, 0 elsewhere.
 template <int D>
 __global__ __launch_bounds__(256) void k_lift(Geom g, const double *__restrict__ f, double *__restrict__ u) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= g.m[0] || y >= g.m[1]) return;
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
@@ -372,12 +414,17 @@ __global__ __launch_bounds__(256) void k_fill(long long n, T *__restrict__ out, 
 
 // Sum the norm partials in a fixed order and update the control block.
 // `ans` is the buffer index of the iterate whose residual was measured.
-__global__ __launch_bounds__(256) void k_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans) {
+__global__ __launch_bounds__(1024) void k_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans) {
   if (ctl->done) return;
-  double s = 0.0;
-  for (long long i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+  double s0 = 0.0, s1 = 0.0;
+  long long i = threadIdx.x;
+  for (; i + 1024 < nparts; i += 2048) {
+    s0 += partial[i];
+    s1 += partial[i + 1024];
+  }
+  if (i < nparts) s0 += partial[i];
   __shared__ double tot;
-  block_sum_256(s, &tot);
+  block_sum_1024(s0 + s1, &tot);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double v = tot;
@@ -396,11 +443,11 @@ __global__ __launch_bounds__(256) void k_check(const double *__restrict__ partia
 
 // Store the summed partials as the reference norm (warm starts measure
 // convergence relative to the Dirichlet lift's residual).
-__global__ __launch_bounds__(256) void k_set_r0(const double *__restrict__ partial, long long nparts, Ctl *ctl) {
+__global__ __launch_bounds__(1024) void k_set_r0(const double *__restrict__ partial, long long nparts, Ctl *ctl) {
   double s = 0.0;
-  for (long long i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+  for (long long i = threadIdx.x; i < nparts; i += 1024) s += partial[i];
   __shared__ double tot;
-  block_sum_256(s, &tot);
+  block_sum_1024(s, &tot);
   __syncthreads();
   if (threadIdx.x == 0) ctl->r0sq = tot;
 }
