@@ -11,7 +11,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libemg.so")
+LIB_PATH = os.environ.get("EMG_LIB") or os.path.join(_HERE, "libemg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2001_04789_amd.build` "

@@ -370,17 +370,17 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
   if (cur != 0) launch_cast<double, double>(p, (long long)p->D * L0.g.N, L0.u64[cur], L0.u64[0], p->ctl);
 }
 
-// One mixed-precision refinement step: FP64 residual of u_a + e written to
-// u_b and (as FP32) to the level-0 FP32 right-hand side, convergence check,
-// then one FP32 V-cycle for the new correction e (left in u32[0] of level 0).
-void record_mixed_iter(emg_problem *p, int a, int nu1, int nu2, float omega) {
+// One mixed-precision refinement step: u += e (the previous FP32
+// correction, zero at the start), FP64 residual written as FP32 to the
+// level-0 FP32 right-hand side with its norm, convergence check, then one
+// FP32 V-cycle for the new correction e (left in u32[0] of level 0).
+void record_mixed_iter(emg_problem *p, int, int nu1, int nu2, float omega) {
   Level &L0 = p->lv[0];
-  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
-    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_resid_update<D, K>), grid_zc(L0.g, L0.zc), kBlock, 0, p->stream, L0.g, L0.C64, L0.u64[a],
-                       L0.u32[0], L0.f64, L0.u64[a ^ 1], L0.f32, p->partial, p->ctl, L0.zc);
-  });
-  launch_check(p, nblocks(L0.g, L0.zc), a ^ 1);
+  const long long nd0 = (long long)p->D * L0.g.N;
+  hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
+                     p->stream, nd0, L0.u64[0], L0.u32[0], p->ctl);
+  launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
+  launch_check(p, nblocks(L0.g, L0.zc), 0);
   const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega);
   if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
 }
@@ -657,8 +657,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
   if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
   if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
-  int k = std::max(1, opt.check_every);
-  if (opt.precision == EMG_MIXED && (k & 1)) k += 1;
+  const int k = std::max(1, opt.check_every);
   const auto t0 = std::chrono::steady_clock::now();
   TRY(setup(p));
   if (opt.precision == EMG_MIXED) TRY(ensure_mixed(p));

@@ -42,8 +42,15 @@ __device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
 // Each workgroup walks `zc` consecutive z-planes of its 64 x 4 tile, so the
 // z-neighbours a plane needs were read one iteration earlier and are still
 // in L2 (a whole plane of a 128^2 anisotropic level is larger than an XCD's L2).
+// Optional occupancy target of the stencil kernel (waves per SIMD) for
+// tuning builds; by default the compiler's own register budget is used.
+#ifdef EMG_STENCIL_WAVES
+#define EMG_STENCIL_OCC __attribute__((amdgpu_waves_per_eu(EMG_STENCIL_WAVES)))
+#else
+#define EMG_STENCIL_OCC
+#endif
 template <int D, int K, typename R, int MODE, typename TO>
-__global__ __launch_bounds__(256) void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
+__global__ __launch_bounds__(256) EMG_STENCIL_OCC void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
                                                  const R *__restrict__ f, TO *__restrict__ out, R omega,
                                                  double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
   if (skip(ctl)) return;
@@ -82,45 +89,12 @@ __global__ __launch_bounds__(256) void k_stencil(Geom g, const R *__restrict__ C
   if (partial) block_sum_256(nrm, partial + block_linear());
 }
 
-// FP64 residual of the refined iterate for mixed-precision refinement:
-// uo = ui + e (e: FP32 correction), r = f - D_H uo written as FP32, norm partials.
-template <int D, int K>
-struct SumU {
-  const double *__restrict__ u;
-  const float *__restrict__ e;
-  long long N;
-  __device__ __forceinline__ double operator()(int k, long long i) const { return u[k * N + i] + double(e[k * N + i]); }
-};
-
-template <int D, int K>
-__global__ __launch_bounds__(256) void k_resid_update(Geom g, const double *__restrict__ C, const double *__restrict__ ui,
-                                                      const float *__restrict__ e, const double *__restrict__ f,
-                                                      double *__restrict__ uo, float *__restrict__ r32,
-                                                      double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
+// u += e (FP32 correction into the FP64 iterate), pointwise.
+__global__ __launch_bounds__(256) void k_add_correction(long long n, double *__restrict__ u, const float *__restrict__ e,
+                                                       const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y;
-  const int z0 = tz_ * zc, z1 = min(g.m[2], z0 + zc);
-  double nrm = 0.0;
-  if (x < g.m[0] && y < g.m[1])
-  for (int z = z0; z < z1; z++) {
-    const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
-    const int p[3] = {x, y, z};
-    const int cls = row_class(g, p);
-    double acc[D], dg[D];
-    rows_at<D, K, double>(g, C, SumU<D, K>{ui, e, g.N}, n, p, cls, acc, dg);
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      const long long q = i * g.N + n;
-      const double v = ui[q] + double(e[q]);
-      const double r = f[q] - acc[i];
-      uo[q] = v;
-      r32[q] = float(r);
-      if (cls != ROW_DIR) nrm += r * r;
-    }
-  }
-  block_sum_256(nrm, partial + block_linear());
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    u[i] += double(e[i]);
 }
 
 // First sweep from a zero initial guess: out = omega f / diag (Dirichlet: f).
