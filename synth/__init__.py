@@ -341,3 +341,121 @@ def plane_strain_voigt(V6: np.ndarray) -> np.ndarray:
 def upper_tri(V: np.ndarray) -> np.ndarray:
     """Row-major upper triangle of a symmetric matrix (the stored moduli layout)."""
     return upper21(V)
+
+
+# --------------------------------------------------------------------------
+# block-structured AMR inputs: a base problem plus nested boxes
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class AmrProblem:
+    """Base grid plus one box per refined level (ratio 2).  Box k (k >= 1)
+    holds nodes [lo, hi] (inclusive, even) of level k's index space; its
+    fields are sampled on the box grown by one ghost node per side."""
+    base: Problem
+    boxes: list
+    C: list
+    eps0: list
+    b: list
+    name: str = ""
+
+    def level_h(self, k):
+        return tuple(self.base.h[a] / 2 ** k if a < self.base.dim else 1.0 for a in range(3))
+
+    def box_coords(self, k):
+        lo, hi = self.boxes[k - 1]
+        h = self.level_h(k)
+        out = []
+        for a in range(3):
+            if a < self.base.dim:
+                out.append(self.base.lo[a] + h[a] * np.arange(lo[a] - 1, hi[a] + 2))
+            else:
+                out.append(np.zeros(1))
+        return out[0][None, None, :], out[1][None, :, None], out[2][:, None, None]
+
+    def composite_nodes(self):
+        n = self.base.nodes
+        for k, (lo, hi) in enumerate(self.boxes, start=1):
+            cnt = 1
+            cov = 1
+            for a in range(self.base.dim):
+                cnt *= hi[a] - lo[a] + 1
+                cov *= hi[a] // 2 - lo[a] // 2 + 1
+            n += cnt - cov
+        return n
+
+
+def _even_floor(v):
+    return int(np.floor(v / 2.0)) * 2
+
+
+def _even_ceil(v):
+    return int(np.ceil(v / 2.0)) * 2
+
+
+def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float = 0.01, floor: float = 1e-4,
+                opening: float = 1e-3, tag: float = 0.1) -> AmrProblem:
+    """Diffuse penny crack in an isotropic matrix (mu=1, lambda=1.5) on
+    [0,1]^3: moduli scaled by 1 - (1 - floor) eta, eta = sech^2(d / width),
+    d the distance to the disc (centre (0.5,0.5,0.5), normal z); opening
+    displacement +-opening/2 in z on the z faces, x/y faces traction-free.
+    Level k >= 1 is one box: the bounding box of the level-(k-1) nodes where
+    |grad eta| h > tag, grown by two coarse cells, refined, clipped so it
+    nests inside level k-1 with two coarse cells to spare."""
+    def eta_of(x, y, z):
+        rho = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+        d = np.sqrt(np.maximum(rho - radius, 0.0) ** 2 + (z - 0.5) ** 2)
+        return 1.0 / np.cosh(d / width) ** 2
+
+    def grad_eta(x, y, z, h):
+        g = 0.0
+        for a, (dx, dy, dz) in enumerate(((h, 0, 0), (0, h, 0), (0, 0, h))):
+            g = g + ((eta_of(x + dx, y + dy, z + dz) - eta_of(x - dx, y - dy, z - dz)) / (2 * h)) ** 2
+        return np.sqrt(g)
+
+    base = Problem(dim=3, n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                   bc=(TRACTION, TRACTION, TRACTION, TRACTION, DIRICHLET, DIRICHLET), kind="iso", C=np.zeros(0),
+                   name=f"penny_{n}_{levels}L")
+
+    def moduli(x, y, z):
+        s = 1.0 - (1.0 - floor) * eta_of(x, y, z)
+        s = np.broadcast_to(s, np.broadcast(x, y, z).shape)
+        return np.stack([1.5 * s, 1.0 * s])
+
+    x, y, z = base.coords()
+    base.C = moduli(x, y, z)
+    for f, v in ((4, -0.5 * opening), (5, 0.5 * opening)):
+        a = np.zeros((3,) + base.face_shape(f))
+        a[2] = v
+        base.face[f] = a
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    prev = (tuple([0, 0, 0]), tuple(m - 1 for m in base.m))
+    for k in range(1, levels):
+        h_prev = amr.level_h(k - 1)[0]
+        lo_p, hi_p = prev
+        idx = [np.arange(lo_p[a], hi_p[a] + 1) for a in range(3)]
+        X = base.lo[0] + h_prev * idx[0][None, None, :]
+        Y = base.lo[1] + h_prev * idx[1][None, :, None]
+        Z = base.lo[2] + h_prev * idx[2][:, None, None]
+        tagged = grad_eta(X, Y, Z, h_prev) * h_prev > tag
+        if not tagged.any():
+            break
+        zz, yy, xx = np.nonzero(tagged)
+        t_lo = [idx[0][xx.min()], idx[1][yy.min()], idx[2][zz.min()]]
+        t_hi = [idx[0][xx.max()], idx[1][yy.max()], idx[2][zz.max()]]
+        lo, hi = [], []
+        for a in range(3):
+            # tagged bounding box grown by two coarse cells, refined
+            l_f = _even_floor(2 * (t_lo[a] - 2))
+            h_f = _even_ceil(2 * (t_hi[a] + 2))
+            l_f = max(l_f, 2 * (lo_p[a] + 2))
+            h_f = min(h_f, 2 * (hi_p[a] - 2))
+            lo.append(l_f)
+            hi.append(h_f)
+        amr.boxes.append((tuple(lo), tuple(hi)))
+        Xf, Yf, Zf = amr.box_coords(k)
+        amr.C.append(moduli(Xf, Yf, Zf))
+        amr.eps0.append(None)
+        amr.b.append(None)
+        prev = (tuple(lo), tuple(hi))
+    return amr

@@ -1,0 +1,194 @@
+"""Pins of the oracle's reflux-free coarse/fine coupling (Sec. 3.2, App. A)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import amr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "appendix_a_cf_stencil.json")
+
+
+def _base2d(bc, lam, mu, n=17, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    p = synth.random_problem(2, (n, n), bc, "iso", seed=0, with_eps0=False, with_face_data=False,
+                             lo=lo + (0.0,), hi=hi + (0.0,))
+    p.C = np.stack([np.full(p.C.shape[1:], lam), np.full(p.C.shape[1:], mu)])
+    return p
+
+
+def _fine(p, lo, hi, fields):
+    """Fine box with moduli from `fields(x, y, z)` sampled on the ghosted box."""
+    d = p.dim
+    h = [p.h[a] / 2 for a in range(3)]
+    ax = []
+    for a in range(3):
+        if a < d:
+            ax.append(p.lo[a] + h[a] * np.arange(lo[a] - 1, hi[a] + 2))
+        else:
+            ax.append(np.zeros(1))
+    x, y, z = ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None]
+    C = fields(x, y, z)
+    shape = (len(ax[2]), len(ax[1]), len(ax[0]))
+    C = np.ascontiguousarray(np.broadcast_to(C, (C.shape[0],) + shape))
+    return amr.FineLevel(p.h, d, oracle.ISO if C.shape[0] == 2 else oracle.ANISO, lo, hi, C)
+
+
+def _laplace_composite():
+    bc = ("dirichlet",) * 4 + ("periodic",) * 2
+    p = _base2d(bc, -1.0, 1.0)
+    fl = _fine(p, (8, 8, 0), (24, 24, 0), lambda x, y, z: np.stack([-1.0 + 0 * x * y, 1.0 + 0 * x * y]))
+    return p, amr.Composite(p, [fl])
+
+
+def _row(comp, u_pert):
+    """Composite residual with every input zero except the given unit values."""
+    u = [np.zeros(comp.grid(k).shape(comp.dim)) for k in range(len(comp.fines) + 1)]
+    for (k, idx), v in u_pert.items():
+        u[k][idx] = v
+    return comp.residual(u)
+
+
+def test_appendix_a_effective_stencil():
+    """The composite Laplacian row at a fine node on the coarse/fine boundary
+    has the coefficients printed in App. A (face: normal part; box corner:
+    both directions)."""
+    g = json.load(open(GOLDEN))
+    p, comp = _laplace_composite()
+    hf = p.h[0] / 2
+    # fine level array index: (comp, z, y, x), ghosted: fine index I -> array I - lo + 1
+    face = (0, 0, 16 - 8 + 1, 1)            # fine node (x=8 (low face), y=16), component 0
+    corner = (0, 0, 1, 1)                   # fine node (8, 8), box corner
+
+    def coef(row, col):
+        r = _row(comp, {col: 1.0})
+        return -r[row[0]][row[1]] * hf * hf
+
+    one = g["one_d_normal"]
+    row = (1, face)
+    assert coef(row, (1, face)) == pytest.approx(one["self"] - 2.0, abs=1e-12)      # normal -1.5, tangential -2
+    assert coef(row, (1, (0, 0, 9, 2))) == pytest.approx(one["fine_inside"], abs=1e-12)
+    assert coef(row, (0, (0, 0, 8, 3))) == pytest.approx(one["coarse_outside"], abs=1e-12)
+    two = g["two_d_corner"]
+    row = (1, corner)
+    assert coef(row, (1, corner)) == pytest.approx(two["self"], abs=1e-12)
+    assert coef(row, (1, (0, 0, 1, 2))) == pytest.approx(two["fine_inside_x"], abs=1e-12)
+    assert coef(row, (1, (0, 0, 2, 1))) == pytest.approx(two["fine_inside_y"], abs=1e-12)
+    assert coef(row, (0, (0, 0, 4, 3))) == pytest.approx(two["coarse_outside_x"], abs=1e-12)
+    assert coef(row, (0, (0, 0, 3, 4))) == pytest.approx(two["coarse_outside_y"], abs=1e-12)
+    # quadratic along the normal is not reproduced at the coarse/fine node (App. A algebra gives 3, not 2)
+    X0 = 8 * hf                                      # x of the coarse/fine face
+    u = []
+    for k in range(2):
+        gk = comp.grid(k)
+        hk = p.h[0] / 2 ** k
+        off = 0 if k == 0 else 8 - 1
+        xs = (np.arange(gk.m[0]) + off) * hk - X0
+        ux = np.broadcast_to(xs[None, None, :] ** 2, gk.shape(2)[1:])
+        u.append(np.stack([ux, np.zeros_like(ux)]))
+    r = comp.residual(comp.sync(u))
+    val = -r[1][face] / 1.0
+    assert val == pytest.approx(g["quadratic_x2_normal_value"], rel=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_affine_patch_test(dim):
+    """P10(i): constant moduli, no eigenstrain or body force, affine
+    Dirichlet data: the composite solution is the affine field on every
+    level, across the coarse/fine boundary."""
+    rng = np.random.default_rng(4)
+    A = rng.uniform(-1, 1, size=(3, 3)) * 1e-3
+    c = rng.uniform(-1, 1, size=3) * 1e-3
+    if dim == 2:
+        p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, 1.5, 1.0, n=17)
+        lo, hi = (8, 8, 0), (24, 24, 0)
+        fields = lambda x, y, z: np.stack([1.5 + 0 * x * y, 1.0 + 0 * x * y])
+    else:
+        p = synth.random_problem(3, (9, 9, 9), ("dirichlet",) * 6, "aniso", seed=3, with_eps0=False,
+                                 with_face_data=False)
+        p.C = np.broadcast_to(p.C[:, :1, :1, :1], p.C.shape).copy()
+        c0 = p.C[:, 0, 0, 0].copy()
+        lo, hi = (4, 4, 4), (12, 12, 12)
+        fields = lambda x, y, z: c0.reshape(-1, 1, 1, 1) + 0 * x * y * z
+    x, y, z = p.coords()
+    shp = (p.m[2], p.m[1], p.m[0])
+    pos = [np.broadcast_to(v, shp) for v in (x, y, z)]
+    uex = np.stack([sum(A[k, l] * pos[l] for l in range(dim)) + c[k] for k in range(dim)])
+    for f in range(2 * dim):
+        a = f // 2
+        sl = [slice(None)] * 3
+        sl[2 - a] = slice(0, 1) if f % 2 == 0 else slice(p.m[a] - 1, p.m[a])
+        p.face[f] = uex[(slice(None),) + tuple(sl)].copy()
+    fl = _fine(p, lo, hi, fields)
+    comp = amr.Composite(p, [fl])
+    u = comp.dense_solve()
+    assert np.abs(u[0] - uex).max() <= 1e-12
+    hf = [p.h[a] / 2 for a in range(3)]
+    ax = [p.lo[a] + hf[a] * np.arange(lo[a] - 1, hi[a] + 2) if a < dim else np.zeros(1) for a in range(3)]
+    fpos = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    ufex = np.stack([sum(A[k, l] * fpos[2 - l] for l in range(dim)) + c[k] for k in range(dim)])
+    assert np.abs(u[1] - ufex).max() <= 1e-12
+
+
+def _smooth_composite_2d(levels=1):
+    def fields(x, y, z):
+        lam = 1.5 + 0.8 * np.sin(3 * x + 0.3) * np.cos(2 * y)
+        mu = 1.0 + 0.5 * np.cos(2 * x + y)
+        return np.stack([lam + 0 * x * y, mu + 0 * x * y])
+    p = synth.random_problem(2, (17, 17), ("dirichlet", "traction", "dirichlet", "traction", "periodic", "periodic"),
+                             "iso", seed=2, with_eps0=False, with_body=True)
+    x, y, _ = p.coords()
+    p.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, 0), p.C.shape))
+    fines = [_fine(p, (8, 8, 0), (24, 24, 0), fields)]
+    if levels == 2:
+        q = synth.Problem(**{**p.__dict__})
+        q.n = (33, 33, 1)
+        fines.append(_fine(q, (20, 20, 0), (44, 44, 0), fields))
+    return amr.Composite(p, fines)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_composite_cycle_reaches_dense_solution(levels):
+    """The composite cycle's fixed point is the dense solution of the
+    composite system (variable moduli, traction faces, 2 and 3 levels)."""
+    comp = _smooth_composite_2d(levels)
+    ud = comp.dense_solve()
+    assert comp.norm(comp.residual(ud)) <= 1e-10 * comp.norm(comp.residual(comp.initial()))
+    u, hist = comp.solve(tol=1e-13, max_cycles=200)
+    for a, b in zip(u, ud):
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(ud[0]).max()
+
+
+def test_amr_approaches_uniform_fine():
+    """P10(iii): refining the region where the solution varies most moves the
+    AMR solution towards the uniformly fine one (measured, not exact)."""
+    def fields(x, y, z):
+        r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+        eta = 0.5 * (1 - np.tanh((r - 0.2) / 0.05))
+        return np.stack([1.5 + 1.5 * eta + 0 * y, 1.0 + 1.0 * eta + 0 * x])
+    bc = ("dirichlet",) * 4 + ("periodic",) * 2
+    pc = _base2d(bc, 1.5, 1.0, n=17)
+    x, y, _ = pc.coords()
+    pc.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, 0), pc.C.shape))
+    pc.b = np.stack([np.broadcast_to(np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / 0.02), pc.C.shape[1:])] * 2)
+    pf = _base2d(bc, 1.5, 1.0, n=33)
+    x2, y2, _ = pf.coords()
+    pf.C = np.ascontiguousarray(np.broadcast_to(fields(x2, y2, 0), pf.C.shape))
+    pf.b = np.stack([np.broadcast_to(np.exp(-((x2 - 0.5) ** 2 + (y2 - 0.5) ** 2) / 0.02), pf.C.shape[1:])] * 2)
+    uf = oracle.dense_solve(pf)
+    uc = oracle.dense_solve(pc)
+    fl = _fine(pc, (8, 8, 0), (24, 24, 0), fields)
+    hf = pc.h[0] / 2
+    xs = np.arange(7, 26) * hf
+    fl.b = np.ascontiguousarray(np.stack([np.exp(-((xs[None, None, :] - 0.5) ** 2 + (xs[None, :, None] - 0.5) ** 2)
+                                                 / 0.02)] * 2))
+    comp = amr.Composite(pc, [fl])
+    ua = comp.dense_solve()
+    # compare at the fine nodes of the box against the uniform fine grid
+    ref = uf[:, :, 7:26, 7:26]
+    coarse_on_fine = amr.interp_to_box(uc, (0, 0, 0), fl)
+    err_amr = np.abs(ua[1] - ref)[:, :, 1:-1, 1:-1].max()
+    err_coarse = np.abs(coarse_on_fine - ref)[:, :, 1:-1, 1:-1].max()
+    assert err_amr < 0.5 * err_coarse
