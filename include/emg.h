@@ -169,6 +169,40 @@ emg_status emg_level_prolong_add(emg_problem *p, int level, int precision, const
 /* exact FP64 solve on the coarsest level: e = A^-1 f */
 emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, void *e);
 
+/* ---- block-structured AMR with reflux-free coarse/fine coupling (Sec. 3.2, App. A) ----
+ * Refined level k >= 1 (ratio 2) is one box of valid nodes [lo, hi] of its
+ * own index space (inclusive; every bound even, so the box corners fall on
+ * coarse nodes).  It must lie inside level k-1's box (the base grid for
+ * k = 1) with at least two coarse cells to spare, off the domain boundary and
+ * off periodic axes.  Level-k fields are laid out over the box grown by one
+ * ghost node per side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x].
+ * Composite system solved by emg_solve (FP64 only):
+ *   - unknowns: valid nodes of every box plus the coarser nodes not covered by
+ *     the next finer box; a covered coarse node takes the coincident fine
+ *     value (App. A, phi_c2 = phi_f4);
+ *   - fine ghost nodes take the bi/trilinear interpolation of the next coarser
+ *     level (App. A, phi_f3 = (phi_c1 + phi_c2)/2);
+ *   - fine valid rows use the fine operator, uncovered coarse rows the coarse
+ *     operator; moduli and eigenstrain of covered coarse nodes are replaced by
+ *     the full-weighting average of the finer level (Sec. 1: coarse levels
+ *     are updated from fine levels by averaging).
+ * The relative residual is the 2-norm over all composite rows.  With a warm
+ * start the reference norm is the warm iterate's own residual.  After a solve
+ * emg_get_displacement returns the base grid (covered nodes injected) and
+ * emg_amr_get_displacement a box with its ghosts interpolated. */
+emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t hi[3]);
+emg_status emg_amr_num_levels(emg_problem *p, int *levels);
+emg_status emg_amr_level_shape(emg_problem *p, int level, int64_t m[3]);
+emg_status emg_amr_set_moduli(emg_problem *p, int level, const double *C, int on_device);
+emg_status emg_amr_set_eigenstrain(emg_problem *p, int level, const double *eps0, int on_device);
+emg_status emg_amr_set_body_force(emg_problem *p, int level, const double *b, int on_device);
+emg_status emg_amr_get_displacement(emg_problem *p, int level, double *u, int on_device);
+emg_status emg_amr_set_displacement(emg_problem *p, int level, const double *u, int on_device);
+/* Composite residual of the current state on one level (0 = base grid; rows
+ * that are not composite rows are left as computed, callers mask them) into
+ * the device buffer r_dev; *norm (if non-NULL) = 2-norm over all composite rows. */
+emg_status emg_amr_residual(emg_problem *p, int level, double *r_dev, double *norm);
+
 /* Average duration in milliseconds of one launch of a cycle kernel on the
  * problem's stream, measured with HIP events around `reps` back-to-back
  * launches in the launch configuration the solve uses.  kernel: 0 = Jacobi

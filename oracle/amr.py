@@ -356,3 +356,14 @@ class Composite:
             if rel < 1e-11 and len(hist) > 3 and hist[-1] > 0.95 * hist[-4]:
                 break
         return u, hist
+
+
+def from_problem(ap) -> Composite:
+    """Composite system of an AMR problem description (``synth.AmrProblem``)."""
+    from . import ANISO, ISO
+    kind = ISO if ap.base.kind == "iso" else ANISO
+    fines = []
+    for k, (lo, hi) in enumerate(ap.boxes, start=1):
+        fines.append(FineLevel(ap.level_h(k - 1), ap.base.dim, kind, lo, hi, ap.C[k - 1], ap.eps0[k - 1],
+                               ap.b[k - 1]))
+    return Composite(ap.base, fines)

@@ -75,6 +75,15 @@ _SIGS = {
     "emg_level_prolong_add": ([c_void_p, c_int, c_int, c_void_p, c_void_p], c_int),
     "emg_level_bottom_solve": ([c_void_p, c_int, c_void_p, c_void_p], c_int),
     "emg_kernel_time": ([c_void_p, c_int, c_int, c_int, c_int, P(c_double)], c_int),
+    "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
+    "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
+    "emg_amr_level_shape": ([c_void_p, c_int, P(c_int64)], c_int),
+    "emg_amr_set_moduli": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_set_eigenstrain": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_set_body_force": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_get_displacement": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_set_displacement": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_residual": ([c_void_p, c_int, c_void_p, P(c_double)], c_int),
 }
 SYMBOLS = tuple(_SIGS)
 
@@ -295,6 +304,67 @@ class Problem:
     def level_bottom_solve(self, f, e, precision="fp64"):
         check(lib.emg_level_bottom_solve(self.handle, _PREC[precision], _dev(f), _dev(e)), "emg_level_bottom_solve")
         return e
+
+    # ---- block-structured AMR ----
+    @classmethod
+    def from_amr(cls, ctx: Context, amr) -> "Problem":
+        """Create from an AMR description (base problem + nested boxes with
+        fields on the ghosted boxes, e.g. ``synth.AmrProblem``)."""
+        p = cls.from_spec(ctx, amr.base)
+        for k, (lo, hi) in enumerate(amr.boxes, start=1):
+            p.amr_add_level(lo, hi)
+            p.amr_set_moduli(k, amr.C[k - 1])
+            if amr.eps0[k - 1] is not None:
+                p.amr_set_eigenstrain(k, amr.eps0[k - 1])
+            if amr.b[k - 1] is not None:
+                p.amr_set_body_force(k, amr.b[k - 1])
+        return p
+
+    def amr_add_level(self, lo, hi):
+        l3 = (c_int64 * 3)(*[int(v) for v in lo])
+        h3 = (c_int64 * 3)(*[int(v) for v in hi])
+        check(lib.emg_amr_add_level(self.handle, l3, h3), "emg_amr_add_level")
+
+    def amr_num_levels(self) -> int:
+        n = c_int()
+        check(lib.emg_amr_num_levels(self.handle, ctypes.byref(n)), "emg_amr_num_levels")
+        return n.value
+
+    def amr_level_shape(self, level):
+        m = (c_int64 * 3)()
+        check(lib.emg_amr_level_shape(self.handle, level, m), "emg_amr_level_shape")
+        return tuple(int(x) for x in m)
+
+    def amr_set_moduli(self, level, C):
+        ptr, dev, keep = _host_or_device(C)
+        check(lib.emg_amr_set_moduli(self.handle, level, ptr, dev), "emg_amr_set_moduli")
+
+    def amr_set_eigenstrain(self, level, e):
+        ptr, dev, keep = _host_or_device(e)
+        check(lib.emg_amr_set_eigenstrain(self.handle, level, ptr, dev), "emg_amr_set_eigenstrain")
+
+    def amr_set_body_force(self, level, b):
+        ptr, dev, keep = _host_or_device(b)
+        check(lib.emg_amr_set_body_force(self.handle, level, ptr, dev), "emg_amr_set_body_force")
+
+    def amr_displacement(self, level, out=None):
+        m = self.amr_level_shape(level)
+        if out is not None:
+            check(lib.emg_amr_get_displacement(self.handle, level, _dev(out), 1), "emg_amr_get_displacement")
+            return out
+        a = np.empty((self.dim, m[2], m[1], m[0]))
+        check(lib.emg_amr_get_displacement(self.handle, level, a.ctypes.data_as(c_void_p), 0),
+              "emg_amr_get_displacement")
+        return a
+
+    def amr_set_displacement(self, level, u):
+        ptr, dev, keep = _host_or_device(u)
+        check(lib.emg_amr_set_displacement(self.handle, level, ptr, dev), "emg_amr_set_displacement")
+
+    def amr_residual(self, level, out):
+        nrm = c_double()
+        check(lib.emg_amr_residual(self.handle, level, _dev(out), ctypes.byref(nrm)), "emg_amr_residual")
+        return nrm.value
 
     def kernel_time(self, kernel: int, level: int = 0, precision="fp64", reps: int = 20) -> float:
         ms = c_double()

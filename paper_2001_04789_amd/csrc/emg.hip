@@ -82,6 +82,16 @@ struct Level {
   float *f32 = nullptr, *r32 = nullptr;
 };
 
+// One refined AMR level: a box of valid nodes with a one-node ghost layer.
+struct Fine {
+  Geom g{};
+  Box b{};
+  double *C = nullptr, *eps = nullptr, *body = nullptr;
+  double *f = nullptr, *u = nullptr, *rr = nullptr, *t = nullptr;
+  double *e[2] = {nullptr, nullptr};
+  bool moduli_set = false;
+};
+
 }  // namespace
 
 struct emg_ctx {
@@ -116,6 +126,10 @@ struct emg_problem {
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
+  // block-structured AMR: refined levels 1.. (empty = single level)
+  std::vector<Fine> fine;
+  double *amr_u0 = nullptr, *amr_f0 = nullptr, *amr_partial = nullptr;
+  long long amr_nparts = 0;
 };
 
 namespace {
@@ -236,6 +250,27 @@ void launch_check(emg_problem *p, long long nparts, int ans) {
 emg_status setup(emg_problem *p) {
   if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
   if (p->setup_done) return EMG_OK;
+  for (auto &F : p->fine)
+    if (!F.moduli_set) return fail(EMG_ESTATE, "moduli of a refined level not set");
+  // coarse levels carry the average of the finer level where it exists (finest first)
+  for (int k = (int)p->fine.size(); k >= 1; k--) {
+    Fine &F = p->fine[k - 1];
+    const Geom gc = k == 1 ? p->lv[0].g : p->fine[k - 2].g;
+    const int3 co = k == 1 ? make_int3(0, 0, 0)
+                           : make_int3(p->fine[k - 2].b.lo[0] - 1, p->fine[k - 2].b.lo[1] - 1,
+                                       p->D == 3 ? p->fine[k - 2].b.lo[2] - 1 : 0);
+    double *Cc = k == 1 ? p->lv[0].C64 : p->fine[k - 2].C;
+    double *Ec = k == 1 ? p->eps : p->fine[k - 2].eps;
+    const dim3 gr((F.b.hi[0] / 2 - F.b.lo[0] / 2 + BX) / BX, (F.b.hi[1] / 2 - F.b.lo[1] / 2 + BY) / BY,
+                  p->D == 3 ? F.b.hi[2] / 2 - F.b.lo[2] / 2 + 1 : 1);
+    if (p->D == 2) {
+      hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc);
+      if (Ec && F.eps) hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne);
+    } else {
+      hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc);
+      if (Ec && F.eps) hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne);
+    }
+  }
   const int L = (int)p->lv.size();
   for (int l = 1; l < L; l++)
     hipLaunchKernelGGL((k_coarsen<double>), grid_of(p->lv[l].g), kBlock, 0, p->stream, p->lv[l - 1].g, p->lv[l].g,
@@ -292,9 +327,14 @@ emg_status assemble_rhs(emg_problem *p) {
   const Level &L0 = p->lv[0];
   Faces F;
   for (int f = 0; f < 6; f++) F.p[f] = p->face[f];
+  Faces none;
+  for (int f = 0; f < 6; f++) none.p[f] = nullptr;
+  double *f0 = p->fine.empty() ? L0.f64 : p->amr_f0;
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_rhs<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, p->body, F, L0.f64);
+    hipLaunchKernelGGL((k_rhs<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, p->body, F, f0);
+    for (auto &Fn : p->fine)
+      hipLaunchKernelGGL((k_rhs<D, K>), grid_of(Fn.g), kBlock, 0, p->stream, Fn.g, Fn.C, Fn.eps, Fn.body, none, Fn.f);
   });
   HIPCK(hipGetLastError());
   p->rhs_ready = true;
@@ -385,7 +425,152 @@ void record_mixed_iter(emg_problem *p, int, int nu1, int nu2, float omega) {
   if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
 }
 
+// ---- AMR helpers ----
+int3 parent_origin(emg_problem *p, int k) {
+  if (k == 1) return make_int3(0, 0, 0);
+  const Box &b = p->fine[k - 2].b;
+  return make_int3(b.lo[0] - 1, b.lo[1] - 1, p->D == 3 ? b.lo[2] - 1 : 0);
+}
+const Geom &parent_geom(emg_problem *p, int k) { return k == 1 ? p->lv[0].g : p->fine[k - 2].g; }
+dim3 covered_grid(emg_problem *p, const Box &b, int grow) {
+  return dim3((b.hi[0] / 2 - b.lo[0] / 2 + 1 + 2 * grow + BX - 1) / BX,
+              (b.hi[1] / 2 - b.lo[1] / 2 + 1 + 2 * grow + BY - 1) / BY,
+              p->D == 3 ? b.hi[2] / 2 - b.lo[2] / 2 + 1 + 2 * grow : 1);
+}
+// a box level seen through the single-level launch helpers
+Level box_level(const Fine &F) {
+  Level L;
+  L.g = F.g;
+  L.zc = 1;
+  L.C64 = F.C;
+  return L;
+}
+
+template <int D>
+void amr_sync(emg_problem *p, double *u0, const Ctl *ctl) {
+  const int Lf = (int)p->fine.size();
+  for (int k = Lf; k >= 1; k--) {
+    Fine &F = p->fine[k - 1];
+    double *uc = k == 1 ? u0 : p->fine[k - 2].u;
+    hipLaunchKernelGGL((k_inject<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, parent_geom(p, k),
+                       parent_origin(p, k), F.g, F.b, F.u, uc, D, ctl);
+  }
+  for (int k = 1; k <= Lf; k++) {
+    Fine &F = p->fine[k - 1];
+    const double *uc = k == 1 ? u0 : p->fine[k - 2].u;
+    hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, uc, F.u, (double *)nullptr, 1, ctl);
+  }
+}
+
+// covered region of level k+1 inside level k's array, for the masked norm
+void covered_array_box(emg_problem *p, int k, int3 &xlo, int3 &xhi) {
+  if (k + 1 > (int)p->fine.size()) {
+    xlo = make_int3(1, 1, 1);
+    xhi = make_int3(0, 0, 0);
+    return;
+  }
+  const Box &b = p->fine[k].b;
+  const int3 co = k == 0 ? make_int3(0, 0, 0) : parent_origin(p, k + 1);
+  xlo = make_int3(b.lo[0] / 2 - co.x, b.lo[1] / 2 - co.y, p->D == 3 ? b.lo[2] / 2 - co.z : 0);
+  xhi = make_int3(b.hi[0] / 2 - co.x, b.hi[1] / 2 - co.y, p->D == 3 ? b.hi[2] / 2 - co.z : 0);
+}
+
+// Composite residual of the (synced) state: base rows into L0.f64, box rows
+// into each box's rr, squared-norm partials of the composite rows.
+template <int D>
+void amr_residual(emg_problem *p, const Ctl *ctl) {
+  Level &L0 = p->lv[0];
+  launch_stencil<double, MODE_RESID, double>(p, L0, p->amr_u0, p->amr_f0, L0.f64, 0.0, nullptr, ctl);
+  long long off = 0;
+  int3 xlo, xhi;
+  covered_array_box(p, 0, xlo, xhi);
+  hipLaunchKernelGGL((k_masked_norm<D>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, xlo, xhi,
+                     p->amr_partial + off, ctl);
+  off += nblocks(L0.g, 1);
+  for (int k = 1; k <= (int)p->fine.size(); k++) {
+    Fine &F = p->fine[k - 1];
+    Level B = box_level(F);
+    launch_stencil<double, MODE_RESID, double>(p, B, F.u, F.f, F.rr, 0.0, nullptr, ctl);
+    covered_array_box(p, k, xlo, xhi);
+    hipLaunchKernelGGL((k_masked_norm<D>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr, xlo, xhi,
+                       p->amr_partial + off, ctl);
+    off += nblocks(F.g, 1);
+  }
+}
+
+// One composite correction cycle (Sec. 3.2): sync, composite residual and
+// convergence check; down the levels: fine corrections relaxed with zero
+// ghosts (the coarse/fine boundary acting as Dirichlet), coarse residual
+// updated for the injected correction, fine residual restricted onto the
+// covered coarse nodes; one V-cycle on the base grid; up the levels:
+// interpolation onto valid and ghost nodes, relaxation with the
+// interpolated ghosts as Dirichlet values; update.
+template <int D>
+void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega) {
+  Level &L0 = p->lv[0];
+  const int Lf = (int)p->fine.size();
+  amr_sync<D>(p, p->amr_u0, p->ctl);
+  amr_residual<D>(p, p->ctl);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, p->stream, p->amr_partial, p->amr_nparts, p->ctl, 0);
+  std::vector<int> cur(Lf + 1, 0);
+  for (int k = Lf; k >= 1; k--) {
+    Fine &F = p->fine[k - 1];
+    Level B = box_level(F);
+    hipLaunchKernelGGL((k_ghost_fill<D, double>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr, 0.0, p->ctl);
+    launch_jacobi_zero<double>(p, B, F.rr, F.e[0], omega, p->ctl);
+    int c = 0;
+    for (int s = 1; s < nu1; s++) {
+      launch_stencil<double, MODE_JACOBI, double>(p, B, F.e[c], F.rr, F.e[c ^ 1], omega, nullptr, p->ctl);
+      c ^= 1;
+    }
+    cur[k] = c;
+    launch_stencil<double, MODE_RESID, double>(p, B, F.e[c], F.rr, F.t, 0.0, nullptr, p->ctl);
+    const Geom &gc = parent_geom(p, k);
+    const int3 co = parent_origin(p, k);
+    double *rrc = k == 1 ? L0.f64 : p->fine[k - 2].rr;
+    const double *Cc = k == 1 ? L0.C64 : p->fine[k - 2].C;
+    dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+      constexpr int DD = decltype(Dc)::value, K = decltype(Kc)::value;
+      hipLaunchKernelGGL((k_cf_update<DD, K, double>), covered_grid(p, F.b, 1), kBlock, 0, p->stream, gc, co, F.g, F.b,
+                         Cc, (const double *)F.e[c], rrc, p->ctl);
+    });
+    hipLaunchKernelGGL((k_restrict_cf<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b,
+                       (const double *)F.t, gc, co, rrc, p->ctl);
+  }
+  const int cb = coarse_cycle<double>(p, 0, nu1, nu2, omega);
+  for (int k = 1; k <= Lf; k++) {
+    Fine &F = p->fine[k - 1];
+    Level B = box_level(F);
+    const double *ec = k == 1 ? L0.u64[cb] : p->fine[k - 2].e[cur[k - 1]];
+    int c = cur[k];
+    hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, ec, F.e[c], F.rr, 2, p->ctl);
+    for (int s = 0; s < nu2; s++) {
+      launch_stencil<double, MODE_JACOBI, double>(p, B, F.e[c], F.rr, F.e[c ^ 1], omega, nullptr, p->ctl);
+      c ^= 1;
+    }
+    cur[k] = c;
+  }
+  const long long nd0 = (long long)p->D * L0.g.N;
+  hipLaunchKernelGGL((k_axpy<double>), dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
+                     p->stream, nd0, p->amr_u0, (const double *)L0.u64[cb], p->ctl);
+  for (int k = 1; k <= Lf; k++) {
+    Fine &F = p->fine[k - 1];
+    const long long nd = (long long)p->D * F.g.N;
+    hipLaunchKernelGGL((k_axpy<double>), dim3((unsigned)std::min<long long>((nd + 255) / 256, 8192)), dim3(256), 0,
+                       p->stream, nd, F.u, (const double *)F.e[cur[k]], p->ctl);
+  }
+}
+
 void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double omega) {
+  if (!p->fine.empty()) {
+    for (int c = 0; c < k; c++) {
+      if (p->D == 2) record_amr_cycle<2>(p, nu1, nu2, omega);
+      else record_amr_cycle<3>(p, nu1, nu2, omega);
+    }
+    return;
+  }
   if (prec == EMG_FP64) {
     for (int c = 0; c < k; c++) record_fp64_cycle(p, nu1, nu2, omega);
   } else {
@@ -654,6 +839,8 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   emg_default_opts(&opt);
   if (o) opt = *o;
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  if (!p->fine.empty() && opt.precision != EMG_FP64)
+    return fail(EMG_EINVAL, "refined levels are solved in FP64 only");
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
   if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
   if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
@@ -670,14 +857,37 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   c0.max_cycles = opt.max_cycles;
   *p->ctl_host = c0;
   HIPCK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, p->stream));
+  if (!p->fine.empty()) {
+    // composite start: Dirichlet lift on the base grid (norm reference),
+    // refined levels interpolated from it, coarsest first
+    if (!opt.warm_start) {
+      if (p->D == 2)
+        hipLaunchKernelGGL((k_lift<2>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, p->amr_f0, p->amr_u0);
+      else
+        hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, p->amr_f0, p->amr_u0);
+      for (int k = 1; k <= (int)p->fine.size(); k++) {
+        Fine &F = p->fine[k - 1];
+        const double *uc = k == 1 ? p->amr_u0 : p->fine[k - 2].u;
+        if (p->D == 2)
+          hipLaunchKernelGGL((k_interp<2, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
+                             parent_origin(p, k), F.g, F.b, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+        else
+          hipLaunchKernelGGL((k_interp<3, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
+                             parent_origin(p, k), F.g, F.b, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+      }
+    }
+    // with a warm start the reference norm is the warm iterate's composite residual
+  }
   // the Dirichlet lift; with a warm start it goes to a scratch buffer and
   // only its residual norm is kept as the reference
   double *lift = opt.warm_start ? L0.u64[1] : L0.u64[0];
-  if (p->D == 2)
-    hipLaunchKernelGGL((k_lift<2>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
-  else
-    hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
-  if (opt.warm_start) {
+  if (p->fine.empty()) {
+    if (p->D == 2)
+      hipLaunchKernelGGL((k_lift<2>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
+    else
+      hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, lift);
+  }
+  if (opt.warm_start && p->fine.empty()) {
     launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
     hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, nblocks(L0.g, L0.zc), p->ctl);
   }
@@ -701,7 +911,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   const auto t3 = std::chrono::steady_clock::now();
   const Ctl c = *p->ctl_host;
   // the answer lives in buffer c.ans of level 0; keep it in buffer 0
-  if (c.ans != 0) {
+  if (c.ans != 0 && p->fine.empty()) {
     HIPCK(hipMemcpyAsync(L0.u64[0], L0.u64[c.ans], sizeof(double) * nd0, hipMemcpyDeviceToDevice, p->stream));
     HIPCK(hipStreamSynchronize(p->stream));
   }
@@ -724,28 +934,39 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     }
     dir_nodes = g.N - inner;
   }
-  s.dofs = (long long)p->D * (L0.g.N - dir_nodes);
+  long long unknown_nodes = L0.g.N - dir_nodes;
+  for (auto &F : p->fine) {
+    long long valid = 1, cov = 1;
+    for (int a = 0; a < p->D; a++) {
+      valid *= F.b.hi[a] - F.b.lo[a] + 1;
+      cov *= F.b.hi[a] / 2 - F.b.lo[a] / 2 + 1;
+    }
+    unknown_nodes += valid - cov;
+  }
+  s.dofs = (long long)p->D * unknown_nodes;
   if (st) *st = s;
   if (c.done == 2) return fail(EMG_EDIVERGED, "residual norm is not finite");
   if (c.done == 3) return fail(EMG_ENOTCONV, "cycle cap reached before the tolerance");
   return EMG_OK;
 }
 
+static double *base_u(emg_problem *p) { return p->fine.empty() ? p->lv[0].u64[0] : p->amr_u0; }
+
 emg_status emg_get_displacement(emg_problem *p, double *u, int on_device) {
   if (!p || !u) return fail(EMG_EINVAL, "null argument");
-  return copy_out(p, u, p->lv[0].u64[0], (size_t)p->D * p->lv[0].g.N, on_device);
+  return copy_out(p, u, base_u(p), (size_t)p->D * p->lv[0].g.N, on_device);
 }
 
 emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device) {
   if (!p || !u) return fail(EMG_EINVAL, "null argument");
-  return copy_in(p, p->lv[0].u64[0], u, (size_t)p->D * p->lv[0].g.N, on_device);
+  return copy_in(p, base_u(p), u, (size_t)p->D * p->lv[0].g.N, on_device);
 }
 
 emg_status emg_get_rhs(emg_problem *p, double *f, int on_device) {
   if (!p || !f) return fail(EMG_EINVAL, "null argument");
   if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
   TRY(assemble_rhs(p));
-  return copy_out(p, f, p->lv[0].f64, (size_t)p->D * p->lv[0].g.N, on_device);
+  return copy_out(p, f, p->fine.empty() ? p->lv[0].f64 : p->amr_f0, (size_t)p->D * p->lv[0].g.N, on_device);
 }
 
 emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device) {
@@ -755,7 +976,7 @@ emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device) {
   if (!p->sig) TRY(dalloc(p, &p->sig, (size_t)p->ne * L0.g.N));
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, L0.u64[0], p->sig);
+    hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, base_u(p), p->sig);
   });
   HIPCK(hipGetLastError());
   return copy_out(p, sigma, p->sig, (size_t)p->ne * L0.g.N, on_device);
@@ -900,6 +1121,162 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
   (void)hipEventDestroy(e1);
   *avg_ms = ms / reps;
   return finish(p);
+}
+
+// ---- block-structured AMR ----
+
+emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t hi[3]) {
+  if (!p || !lo || !hi) return fail(EMG_EINVAL, "null argument");
+  const int k = (int)p->fine.size() + 1;
+  const Geom &pg = parent_geom(p, k);
+  Fine F;
+  int plo[3], phi[3];
+  for (int a = 0; a < 3; a++) {
+    if (k == 1) { plo[a] = 0; phi[a] = pg.m[a] - 1; }
+    else { plo[a] = p->fine[k - 2].b.lo[a]; phi[a] = p->fine[k - 2].b.hi[a]; }
+  }
+  F.g.dim = p->D;
+  for (int a = 0; a < 3; a++) {
+    if (a < p->D) {
+      if (lo[a] % 2 || hi[a] % 2 || hi[a] <= lo[a]) return fail(EMG_EINVAL, "box bounds must be even with hi > lo");
+      if (lo[a] / 2 - 2 < plo[a] || hi[a] / 2 + 2 > phi[a])
+        return fail(EMG_EINVAL, "box must nest inside the coarser level with two coarse cells to spare");
+      if (k == 1 && pg.per[a]) return fail(EMG_EINVAL, "refined boxes need non-periodic axes");
+      F.b.lo[a] = (int)lo[a];
+      F.b.hi[a] = (int)hi[a];
+      F.g.m[a] = (int)(hi[a] - lo[a] + 3);
+      F.g.per[a] = 0;
+      F.g.h[a] = pg.h[a] / 2.0;
+      F.g.bc[2 * a] = F.g.bc[2 * a + 1] = EMG_BC_DIRICHLET;
+    } else {
+      F.b.lo[a] = F.b.hi[a] = 0;
+      F.g.m[a] = 1;
+      F.g.per[a] = 1;
+      F.g.h[a] = 1.0;
+      F.g.bc[2 * a] = F.g.bc[2 * a + 1] = EMG_BC_PERIODIC;
+    }
+  }
+  F.g.N = (long long)F.g.m[0] * F.g.m[1] * F.g.m[2];
+  const size_t nd = (size_t)p->D * F.g.N;
+  TRY(dalloc(p, &F.C, (size_t)p->nc * F.g.N));
+  TRY(dalloc(p, &F.f, nd));
+  TRY(dalloc(p, &F.u, nd));
+  TRY(dalloc(p, &F.rr, nd));
+  TRY(dalloc(p, &F.t, nd));
+  TRY(dalloc(p, &F.e[0], nd));
+  TRY(dalloc(p, &F.e[1], nd));
+  if (!p->amr_u0) {
+    const size_t nd0 = (size_t)p->D * p->lv[0].g.N;
+    TRY(dalloc(p, &p->amr_u0, nd0));
+    TRY(dalloc(p, &p->amr_f0, nd0));
+    launch_fill<double>(p, (long long)nd0, p->amr_u0, 0.0);
+  }
+  launch_fill<double>(p, (long long)nd, F.u, 0.0);
+  p->fine.push_back(F);
+  // norm partials of every level's composite rows
+  long long parts = nblocks(p->lv[0].g, 1);
+  for (auto &G : p->fine) parts += nblocks(G.g, 1);
+  TRY(dalloc(p, &p->amr_partial, (size_t)parts));
+  p->amr_nparts = parts;
+  destroy_graphs(p);
+  p->setup_done = p->rhs_ready = false;
+  HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+static emg_status fine_level(emg_problem *p, int level, Fine **F) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  if (level < 1 || level > (int)p->fine.size()) return fail(EMG_EINVAL, "no such refined level");
+  *F = &p->fine[level - 1];
+  return EMG_OK;
+}
+
+emg_status emg_amr_num_levels(emg_problem *p, int *levels) {
+  if (!p || !levels) return fail(EMG_EINVAL, "null argument");
+  *levels = (int)p->fine.size();
+  return EMG_OK;
+}
+
+emg_status emg_amr_level_shape(emg_problem *p, int level, int64_t m[3]) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  for (int a = 0; a < 3; a++) m[a] = F->g.m[a];
+  return EMG_OK;
+}
+
+emg_status emg_amr_set_moduli(emg_problem *p, int level, const double *C, int on_device) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  if (!C) return fail(EMG_EINVAL, "null moduli");
+  TRY(copy_in(p, F->C, C, (size_t)p->nc * F->g.N, on_device));
+  F->moduli_set = true;
+  p->setup_done = p->rhs_ready = p->mixed_ready = false;
+  return EMG_OK;
+}
+
+emg_status emg_amr_set_eigenstrain(emg_problem *p, int level, const double *e, int on_device) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  p->rhs_ready = p->setup_done = false;
+  if (!e) {
+    F->eps = nullptr;
+    return EMG_OK;
+  }
+  if (!F->eps) TRY(dalloc(p, &F->eps, (size_t)p->ne * F->g.N));
+  return copy_in(p, F->eps, e, (size_t)p->ne * F->g.N, on_device);
+}
+
+emg_status emg_amr_set_body_force(emg_problem *p, int level, const double *b, int on_device) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  p->rhs_ready = false;
+  if (!b) {
+    F->body = nullptr;
+    return EMG_OK;
+  }
+  if (!F->body) TRY(dalloc(p, &F->body, (size_t)p->D * F->g.N));
+  return copy_in(p, F->body, b, (size_t)p->D * F->g.N, on_device);
+}
+
+emg_status emg_amr_get_displacement(emg_problem *p, int level, double *u, int on_device) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  if (!u) return fail(EMG_EINVAL, "null output");
+  return copy_out(p, u, F->u, (size_t)p->D * F->g.N, on_device);
+}
+
+emg_status emg_amr_set_displacement(emg_problem *p, int level, const double *u, int on_device) {
+  Fine *F;
+  TRY(fine_level(p, level, &F));
+  if (!u) return fail(EMG_EINVAL, "null input");
+  return copy_in(p, F->u, u, (size_t)p->D * F->g.N, on_device);
+}
+
+emg_status emg_amr_residual(emg_problem *p, int level, double *r_dev, double *norm) {
+  if (!p || !r_dev) return fail(EMG_EINVAL, "null argument");
+  if (p->fine.empty()) return fail(EMG_ESTATE, "no refined levels");
+  if (level < 0 || level > (int)p->fine.size()) return fail(EMG_EINVAL, "no such level");
+  TRY(setup(p));
+  TRY(assemble_rhs(p));
+  if (p->D == 2) {
+    amr_sync<2>(p, p->amr_u0, nullptr);
+    amr_residual<2>(p, nullptr);
+  } else {
+    amr_sync<3>(p, p->amr_u0, nullptr);
+    amr_residual<3>(p, nullptr);
+  }
+  HIPCK(hipGetLastError());
+  if (norm) {
+    std::vector<double> parts(p->amr_nparts);
+    HIPCK(hipMemcpyAsync(parts.data(), p->amr_partial, sizeof(double) * parts.size(), hipMemcpyDeviceToHost,
+                         p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+    double s = 0.0;
+    for (double v : parts) s += v;
+    *norm = std::sqrt(s);
+  }
+  if (level == 0) return copy_out(p, r_dev, p->lv[0].f64, (size_t)p->D * p->lv[0].g.N, 1);
+  return copy_out(p, r_dev, p->fine[level - 1].rr, (size_t)p->D * p->fine[level - 1].g.N, 1);
 }
 
 }  // extern "C"

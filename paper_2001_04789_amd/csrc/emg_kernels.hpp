@@ -517,3 +517,224 @@ __global__ __launch_bounds__(256) void k_bottom_solve(const double *__restrict__
 }
 
 }  // namespace emg
+
+// ======================= block-structured AMR coupling =======================
+// A refined level is one box of valid nodes [lo, hi] (even bounds) in its own
+// index space, stored with a one-node ghost layer (array extents hi-lo+3) as a
+// level whose faces are all Dirichlet: the ghost layer are the Dirichlet rows,
+// the valid nodes (including the coarse/fine boundary layer) the interior
+// rows.  Coarse arrays are addressed with `co`, the global index of their
+// array index 0 (0 for the base grid, lo-1 for a refined level's box).
+namespace emg {
+
+struct Box {
+  int lo[3], hi[3];   // valid nodes, fine index space
+};
+
+// coarse node J (global) -> coarse array index, and fine global I -> fine array index
+__device__ __forceinline__ long long lin(const Geom &g, int x, int y, int z) {
+  return ((long long)z * g.m[1] + y) * g.m[0] + x;
+}
+
+// Covered coarse nodes <- coincident fine values (Sec. 3.2 / App. A:
+// phi_c2 = phi_f4).  One thread per covered coarse node.
+template <int D, typename R>
+__global__ __launch_bounds__(256) void k_inject(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ uf,
+                                                R *__restrict__ uc, int ncomp, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
+  const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
+  const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
+  if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
+  const long long nf = lin(gf, 2 * cx - b.lo[0] + 1, 2 * cy - b.lo[1] + 1, D == 3 ? 2 * cz - b.lo[2] + 1 : 0);
+  for (int i = 0; i < ncomp; i++) uc[i * gc.N + nc] = uf[i * gf.N + nf];
+}
+
+// Full weighting of a field given on the ghosted box (moduli, eigenstrain)
+// at the covered coarse nodes: coarse levels carry the average of the finer
+// level where it exists (Sec. 1).
+template <int D>
+__global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, Box b, const double *__restrict__ af,
+                                                    double *__restrict__ ac, int ncomp) {
+  const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
+  const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
+  const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
+  if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
+  const int fx = 2 * cx - b.lo[0] + 1, fy = 2 * cy - b.lo[1] + 1, fz = D == 3 ? 2 * cz - b.lo[2] + 1 : 0;
+  for (int i = 0; i < ncomp; i++) {
+    double s = 0.0;
+    for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); oz++)
+      for (int oy = -1; oy <= 1; oy++)
+        for (int ox = -1; ox <= 1; ox++) {
+          const double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
+          s += w * af[i * gf.N + lin(gf, fx + ox, fy + oy, fz + oz)];
+        }
+    ac[i * gc.N + nc] = s;
+  }
+}
+
+// Bi/trilinear interpolation of a coarse field at the nodes of the ghosted box.
+//   mode 0: dst = interp at every node
+//   mode 1: dst = interp at ghost nodes only
+//   mode 2: dst += interp at valid nodes, dst = interp at ghost nodes
+// dst2 (optional): = interp at ghost nodes.
+template <int D, typename R>
+__global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ uc,
+                                                R *__restrict__ dst, R *__restrict__ dst2, int mode,
+                                                const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  if (x >= gf.m[0] || y >= gf.m[1]) return;
+  const int p[3] = {x, y, z};
+  bool ghost = false;
+  for (int a = 0; a < D; a++) ghost = ghost || p[a] == 0 || p[a] == gf.m[a] - 1;
+  if (mode == 1 && !ghost) return;
+  const int cox[3] = {co.x, co.y, co.z};
+  int c0[3], c1[3];
+  R w1[3];
+  for (int a = 0; a < 3; a++) {
+    if (a < D) {
+      const int I = b.lo[a] - 1 + p[a];       // fine global index (>= 1: boxes keep off the domain boundary)
+      c0[a] = I / 2 - cox[a];
+      c1[a] = (I & 1) ? c0[a] + 1 : c0[a];
+      w1[a] = (I & 1) ? R(0.5) : R(0);
+    } else {
+      c0[a] = c1[a] = 0;
+      w1[a] = R(0);
+    }
+  }
+  const long long nf = lin(gf, x, y, z);
+  for (int i = 0; i < D; i++) {
+    R v = R(0);
+    for (int sz = 0; sz < (D == 3 ? 2 : 1); sz++)
+      for (int sy = 0; sy < 2; sy++)
+        for (int sx = 0; sx < 2; sx++) {
+          const R w = (sx ? w1[0] : R(1) - w1[0]) * (sy ? w1[1] : R(1) - w1[1]) * (D == 3 ? (sz ? w1[2] : R(1) - w1[2]) : R(1));
+          if (w == R(0)) continue;
+          v += w * uc[i * gc.N + lin(gc, sx ? c1[0] : c0[0], sy ? c1[1] : c0[1], sz ? c1[2] : c0[2])];
+        }
+    const long long q = i * gf.N + nf;
+    if (mode == 0 || ghost) dst[q] = v;
+    else if (mode == 2) dst[q] += v;
+    if (dst2 && ghost) dst2[q] = v;
+  }
+}
+
+// Ghost rows of a box array <- v.
+template <int D, typename R>
+__global__ __launch_bounds__(256) void k_ghost_fill(Geom gf, R *__restrict__ a, R v, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  if (x >= gf.m[0] || y >= gf.m[1]) return;
+  const int p[3] = {x, y, z};
+  bool ghost = false;
+  for (int a = 0; a < D; a++) ghost = ghost || p[a] == 0 || p[a] == gf.m[a] - 1;
+  if (!ghost) return;
+  for (int i = 0; i < D; i++) a[i * gf.N + lin(gf, x, y, z)] = v;
+}
+
+// Restriction of a fine residual onto the covered coarse nodes: full
+// weighting over the valid fine nodes only, weights renormalised to sum to
+// one where the stencil would reach a ghost node (coarse/fine boundary).
+template <int D, typename R>
+__global__ __launch_bounds__(256) void k_restrict_cf(Geom gf, Box b, const R *__restrict__ rf, Geom gc, int3 co,
+                                                     R *__restrict__ rc, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
+  const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
+  const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
+  if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
+  const int f[3] = {2 * cx - b.lo[0] + 1, 2 * cy - b.lo[1] + 1, D == 3 ? 2 * cz - b.lo[2] + 1 : 0};
+  R acc[D], wsum = R(0);
+  for (int i = 0; i < D; i++) acc[i] = R(0);
+  for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); oz++)
+    for (int oy = -1; oy <= 1; oy++)
+      for (int ox = -1; ox <= 1; ox++) {
+        const int q[3] = {f[0] + ox, f[1] + oy, f[2] + oz};
+        bool valid = true;
+        for (int a = 0; a < D; a++) valid = valid && q[a] >= 1 && q[a] <= gf.m[a] - 2;
+        if (!valid) continue;
+        const R w = (ox ? R(0.25) : R(0.5)) * (oy ? R(0.25) : R(0.5)) * (D == 3 ? (oz ? R(0.25) : R(0.5)) : R(1));
+        wsum += w;
+        for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + lin(gf, q[0], q[1], q[2])];
+      }
+  for (int i = 0; i < D; i++) rc[i * gc.N + nc] = acc[i] / wsum;
+}
+
+// Coarse-side effect of a fine correction: the uncovered coarse rows next to
+// the box see the correction through the covered (injected) nodes, so their
+// residual drops by the coarse operator applied to the injected correction.
+template <int D, int K, typename R>
+struct InjU {
+  const R *__restrict__ ef;
+  Geom gc, gf;
+  int3 co;
+  Box b;
+  __device__ __forceinline__ R operator()(int k, long long i) const {
+    const int x = int(i % gc.m[0]) + co.x, y = int((i / gc.m[0]) % gc.m[1]) + co.y;
+    const int z = D == 3 ? int(i / ((long long)gc.m[0] * gc.m[1])) + co.z : 0;
+    if (x < b.lo[0] / 2 || x > b.hi[0] / 2 || y < b.lo[1] / 2 || y > b.hi[1] / 2) return R(0);
+    if (D == 3 && (z < b.lo[2] / 2 || z > b.hi[2] / 2)) return R(0);
+    return ef[k * gf.N + lin(gf, 2 * x - b.lo[0] + 1, 2 * y - b.lo[1] + 1, D == 3 ? 2 * z - b.lo[2] + 1 : 0)];
+  }
+};
+
+template <int D, int K, typename R>
+__global__ __launch_bounds__(256) void k_cf_update(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ Cc,
+                                                   const R *__restrict__ ef, R *__restrict__ rc,
+                                                   const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  // coarse nodes of the covered box grown by one, minus the covered box
+  const int cx = b.lo[0] / 2 - 1 + blockIdx.x * BX + threadIdx.x;
+  const int cy = b.lo[1] / 2 - 1 + blockIdx.y * BY + threadIdx.y;
+  const int cz = (D == 3 ? b.lo[2] / 2 - 1 : 0) + blockIdx.z;
+  if (cx > b.hi[0] / 2 + 1 || cy > b.hi[1] / 2 + 1 || (D == 3 && cz > b.hi[2] / 2 + 1)) return;
+  const bool covered = cx >= b.lo[0] / 2 && cx <= b.hi[0] / 2 && cy >= b.lo[1] / 2 && cy <= b.hi[1] / 2 &&
+                       (D == 2 || (cz >= b.lo[2] / 2 && cz <= b.hi[2] / 2));
+  if (covered) return;
+  const int p[3] = {cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0};
+  const long long n = lin(gc, p[0], p[1], p[2]);
+  const int cls = row_class(gc, p);
+  if (cls == ROW_DIR) return;
+  R acc[D], dg[D];
+  rows_at<D, K, R>(gc, Cc, InjU<D, K, R>{ef, gc, gf, co, b}, n, p, cls, acc, dg);
+  for (int i = 0; i < D; i++) rc[i * gc.N + n] -= acc[i];
+}
+
+// Squared 2-norm partials of r over non-Dirichlet rows, excluding the nodes
+// of array box [xlo, xhi] (covered by a finer level; empty if xlo > xhi).
+template <int D>
+__global__ __launch_bounds__(256) void k_masked_norm(Geom g, const double *__restrict__ r, int3 xlo, int3 xhi,
+                                                     double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  double s = 0.0;
+  if (x < g.m[0] && y < g.m[1]) {
+    const int p[3] = {x, y, z};
+    const bool cov = x >= xlo.x && x <= xhi.x && y >= xlo.y && y <= xhi.y && (D == 2 || (z >= xlo.z && z <= xhi.z));
+    if (!cov && row_class(g, p) != ROW_DIR)
+      for (int i = 0; i < D; i++) {
+        const double v = r[i * g.N + lin(g, x, y, z)];
+        s += v * v;
+      }
+  }
+  block_sum_256(s, partial + block_linear());
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_axpy(long long n, R *__restrict__ u, const R *__restrict__ e,
+                                              const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) u[i] += e[i];
+}
+
+}  // namespace emg

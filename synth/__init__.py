@@ -459,3 +459,49 @@ def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float 
         amr.b.append(None)
         prev = (tuple(lo), tuple(hi))
     return amr
+
+
+def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> AmrProblem:
+    """Small composite test problem: smooth isotropic moduli (analytic,
+    sampled on every level), body force, mixed Dirichlet/traction faces, and
+    centred nested boxes (each half the previous box's width)."""
+    rng = np.random.default_rng(seed)
+    k = rng.uniform(1.0, 3.0, size=4)
+
+    def fields(x, y, z):
+        lam = 1.5 + 0.8 * np.sin(k[0] * x + 0.3) * np.cos(k[1] * y) * np.cos(k[2] * z)
+        mu = 1.0 + 0.5 * np.cos(k[3] * x + y - 0.5 * z)
+        return np.stack([lam + 0 * x * y * z, mu + 0 * x * y * z])
+
+    def body(x, y, z):
+        g = np.exp(-((x - 0.45) ** 2 + (y - 0.55) ** 2 + (z - 0.5) ** 2) / 0.05)
+        return np.stack([1e-2 * g, -2e-2 * g, 1.5e-2 * g][:dim])
+
+    n3 = (n,) * dim + (1,) * (3 - dim)
+    hi = (1.0,) * dim + (0.0,) * (3 - dim)
+    bc = ("dirichlet", "traction", "traction", "traction", "dirichlet", "traction") if dim == 3 else \
+        ("dirichlet", "traction", "dirichlet", "traction", PERIODIC, PERIODIC)
+    base = Problem(dim=dim, n=n3, lo=(0.0, 0.0, 0.0), hi=hi, bc=bc, kind="iso", C=np.zeros(0),
+                   name=f"smooth_amr_{dim}d_{levels}L")
+    x, y, z = base.coords()
+    shp = (base.m[2], base.m[1], base.m[0])
+    base.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, z), (2,) + shp))
+    base.b = np.ascontiguousarray(np.broadcast_to(body(x, y, z), (dim,) + shp))
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    lo_p, hi_p = [0] * 3, [m - 1 for m in base.m]
+    for lev in range(1, levels):
+        lo, hi = [0, 0, 0], [0, 0, 0]
+        for a in range(dim):
+            span = hi_p[a] - lo_p[a]
+            c0 = lo_p[a] + span // 4
+            c1 = hi_p[a] - span // 4
+            lo[a] = 2 * max(c0, lo_p[a] + 2)
+            hi[a] = 2 * min(c1, hi_p[a] - 2)
+        amr.boxes.append((tuple(lo), tuple(hi)))
+        X, Y, Z = amr.box_coords(lev)
+        mshape = tuple(len(v.ravel()) for v in (Z, Y, X))
+        amr.C.append(np.ascontiguousarray(np.broadcast_to(fields(X, Y, Z), (2,) + mshape)))
+        amr.eps0.append(None)
+        amr.b.append(np.ascontiguousarray(np.broadcast_to(body(X, Y, Z), (dim,) + mshape)))
+        lo_p, hi_p = lo, hi
+    return amr

@@ -1,0 +1,142 @@
+"""GPU parity of the reflux-free AMR composite solve (Sec. 3.2, App. A)
+against the oracle's composite system, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import amr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def emg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_04789_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(emg):
+    c = emg.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {"2d_2L": (2, 2, 17), "2d_3L": (2, 3, 17), "3d_2L": (3, 2, 9), "3d_2L_17": (3, 2, 17)}
+
+
+def _state(prob, comp, u):
+    prob.set_displacement(u[0])
+    for k in range(1, len(u)):
+        prob.amr_set_displacement(k, u[k])
+
+
+def _gpu_solution(prob, nlev):
+    return [prob.displacement()] + [prob.amr_displacement(k) for k in range(1, nlev)]
+
+
+def _rel(u, ref, comp):
+    """Relative 2-norm difference over base nodes and valid box nodes."""
+    num = float(np.sum((u[0] - ref[0]) ** 2))
+    den = float(np.sum(ref[0] ** 2))
+    for k in range(1, len(u)):
+        v = (slice(None),) + comp.fines[k - 1].valid()
+        num += float(np.sum((u[k][v] - ref[k][v]) ** 2))
+        den += float(np.sum(ref[k][v] ** 2))
+    return np.sqrt(num / den)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_composite_residual_matches_oracle(emg, ctx, name):
+    ap = synth.smooth_amr(*CASES[name])
+    print(f"[gpu] amr residual {name} boxes={ap.boxes}", flush=True)
+    comp = amr.from_problem(ap)
+    prob = emg.Problem.from_amr(ctx, ap)
+    rng = np.random.default_rng(1)
+    u = [1e-3 * rng.standard_normal(comp.grid(k).shape(ap.base.dim)) for k in range(len(ap.boxes) + 1)]
+    # Dirichlet rows of the base carry their prescribed values in both
+    f0 = comp.f[0]
+    u[0] = np.where(oracle.dirichlet_mask(comp.g0), f0, u[0])
+    _state(prob, comp, u)
+    ref = comp.residual(u)
+    masks = comp.unknown_masks()
+    gnorm = None
+    for k in range(len(u)):
+        out = torch.empty(comp.grid(k).shape(ap.base.dim), dtype=torch.float64, device=DEV)
+        gnorm = prob.amr_residual(k, out)
+        got = out.cpu().numpy()
+        m = masks[k]
+        scale = np.abs(ref[k][m]).max()
+        assert np.abs(got[m] - ref[k][m]).max() <= 1e-12 * scale, k
+    assert gnorm == pytest.approx(comp.norm(ref), rel=1e-12)
+    prob.close()
+
+
+_REF = {}
+
+
+def _reference(name):
+    if name not in _REF:
+        ap = synth.smooth_amr(*CASES[name])
+        comp = amr.from_problem(ap)
+        u, hist = comp.solve(tol=1e-13, max_cycles=300)
+        _, hist10 = comp.solve(tol=1e-10, max_cycles=300)
+        _REF[name] = (ap, comp, u, len(hist10) - 1)
+    return _REF[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_composite_solve_matches_oracle(emg, ctx, name):
+    ap, comp, uref, cycles10 = _reference(name)
+    print(f"[gpu] amr solve {name}", flush=True)
+    prob = emg.Problem.from_amr(ctx, ap)
+    st = prob.solve(rtol=1e-10, max_cycles=300)
+    assert st["converged"] and st["rel_res"] <= 1e-10
+    assert abs(st["cycles"] - cycles10) <= 1
+    u = _gpu_solution(prob, len(ap.boxes) + 1)
+    err = _rel(u, uref, comp)
+    print(f"[gpu]   cycles={st['cycles']} (oracle {cycles10}) rel_err={err:.2e}", flush=True)
+    assert err <= 1e-8
+    # the oracle's composite residual of the GPU solution
+    r0 = comp.norm(comp.residual(comp.initial()))
+    assert comp.norm(comp.residual(u)) / r0 <= 1.2e-10
+    nodes = ap.composite_nodes() - ap.base.dirichlet_count()
+    assert st["dofs"] == ap.base.dim * nodes
+    prob.close()
+
+
+def test_penny_crack_three_levels(emg, ctx):
+    """Config-4-style problem (diffuse penny crack, 3 levels) on a 33^3 base:
+    the GPU solution satisfies the oracle's composite system to 1e-10."""
+    ap = synth.penny_crack(n=33, levels=3, floor=1e-2, width=0.05)
+    print(f"[gpu] penny crack 33^3 boxes={ap.boxes}", flush=True)
+    comp = amr.from_problem(ap)
+    prob = emg.Problem.from_amr(ctx, ap)
+    st = prob.solve(rtol=1e-10, max_cycles=400)
+    assert st["converged"]
+    u = _gpu_solution(prob, 3)
+    r0 = comp.norm(comp.residual(comp.initial()))
+    rel = comp.norm(comp.residual(u)) / r0
+    print(f"[gpu]   cycles={st['cycles']} oracle rel residual={rel:.2e}", flush=True)
+    assert rel <= 1.2e-10
+    prob.close()
+
+
+def test_amr_rejects_bad_boxes(emg, ctx):
+    ap = synth.smooth_amr(2, 1, 17)
+    prob = emg.Problem.from_spec(ctx, ap.base)
+    for lo, hi in [((2, 8, 0), (24, 24, 0)),      # too close to the domain boundary
+                   ((7, 8, 0), (24, 24, 0)),      # odd bound
+                   ((8, 8, 0), (8, 24, 0))]:      # empty
+        with pytest.raises(emg.EmgError) as ei:
+            prob.amr_add_level(lo, hi)
+        assert ei.value.status == emg.EMG_EINVAL
+    prob.amr_add_level((8, 8, 0), (24, 24, 0))
+    st = prob.solve(raise_on_error=False)
+    assert st["status"] == emg.EMG_ESTATE          # refined level without moduli
+    prob.close()
