@@ -169,6 +169,18 @@ emg_status emg_level_prolong_add(emg_problem *p, int level, int precision, const
 /* exact FP64 solve on the coarsest level: e = A^-1 f */
 emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, void *e);
 
+/* ---- ragged batches ----
+ * Solve n independent problems (any sizes, both moduli kinds, same context
+ * and dimension) together: every step of the cycle is one launch per
+ * (dimension, moduli kind) group whose workgroups walk a device work list of
+ * (problem, level, tiles) entries, captured once as a HIP graph and replayed
+ * until every problem has converged; a converged problem's entries are
+ * skipped.  Each problem's arithmetic is that of emg_solve, so its result is
+ * bit-identical alone and in the batch.  Runs on probs[0]'s stream.  stats
+ * (n entries, may be NULL) get per-problem cycles/residuals; solve_seconds is
+ * the batch's wall time.  Refined (AMR) problems and warm starts are rejected. */
+emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *opts, emg_solve_stats *stats);
+
 /* ---- block-structured AMR with reflux-free coarse/fine coupling (Sec. 3.2, App. A) ----
  * Refined level k >= 1 (ratio 2) is one box of valid nodes [lo, hi] of its
  * own index space (inclusive; every bound even, so the box corners fall on

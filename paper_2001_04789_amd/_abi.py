@@ -75,6 +75,7 @@ _SIGS = {
     "emg_level_prolong_add": ([c_void_p, c_int, c_int, c_void_p, c_void_p], c_int),
     "emg_level_bottom_solve": ([c_void_p, c_int, c_void_p, c_void_p], c_int),
     "emg_kernel_time": ([c_void_p, c_int, c_int, c_int, c_int, P(c_double)], c_int),
+    "emg_solve_batch": ([P(c_void_p), c_int, P(emg_solve_opts), P(emg_solve_stats)], c_int),
     "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
     "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
     "emg_amr_level_shape": ([c_void_p, c_int, P(c_int64)], c_int),
@@ -153,6 +154,19 @@ def default_opts(**kw) -> emg_solve_opts:
             v = _PREC[v]
         setattr(o, k, v)
     return o
+
+
+def solve_batch(problems, raise_on_error: bool = True, **opts):
+    """Solve several problems together (emg_solve_batch); per-problem stats."""
+    n = len(problems)
+    arr = (c_void_p * n)(*[p.handle for p in problems])
+    o = default_opts(**opts)
+    st = (emg_solve_stats * n)()
+    s = lib.emg_solve_batch(arr, n, ctypes.byref(o), st)
+    out = [dict({k: getattr(x, k) for k, _ in emg_solve_stats._fields_}, status=s) for x in st]
+    if raise_on_error and s != EMG_OK:
+        check(s, "emg_solve_batch")
+    return out
 
 
 class Problem:
@@ -373,7 +387,7 @@ class Problem:
         return ms.value
 
 
-__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "EmgError", "check", "default_opts",
+__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "EmgError", "check", "default_opts", "solve_batch",
            "emg_domain", "emg_solve_opts", "emg_solve_stats",
            "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE",
            "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_MOD_ISO", "EMG_MOD_ANISO",

@@ -622,6 +622,447 @@ void destroy_graphs(emg_problem *p) {
 
 }  // namespace
 
+// ============================ ragged batching ============================
+namespace {
+
+constexpr int kBatchGrid = 2048;   // workgroups of a batched launch (grid-strided over the work list)
+
+struct Step {
+  int kind, D, K;
+  bool f32;
+  int list;
+};
+
+struct BatchPlan {
+  std::vector<Step> steps;
+  std::vector<std::vector<BEnt>> lists;
+  std::vector<int> sig;            // step sequence signature (graph reuse)
+};
+
+BEnt ent_level(const Geom &g) {
+  BEnt e{};
+  e.g = g;
+  e.gx = (g.m[0] + BX - 1) / BX;
+  e.gy = (g.m[1] + BY - 1) / BY;
+  e.gz = g.m[2];
+  return e;
+}
+
+struct Planner {
+  std::vector<emg_problem *> probs;
+  BatchPlan plan;
+  std::vector<std::pair<int, int>> groups;
+  int maxdepth = 0;
+
+  explicit Planner(const std::vector<emg_problem *> &ps) : probs(ps) {
+    for (auto *p : probs) {
+      std::pair<int, int> g{p->D, p->K};
+      if (std::find(groups.begin(), groups.end(), g) == groups.end()) groups.push_back(g);
+      maxdepth = std::max(maxdepth, (int)p->lv.size());
+    }
+    std::sort(groups.begin(), groups.end());
+  }
+
+  // one launch per group, entries from `make(p)` for the problems it returns true for
+  template <class F>
+  void step(int kind, bool f32, F make) {
+    for (auto &gr : groups) {
+      std::vector<BEnt> es;
+      for (auto *p : probs) {
+        if (p->D != gr.first || p->K != gr.second) continue;
+        BEnt e{};
+        if (make(p, e)) es.push_back(e);
+      }
+      if (es.empty()) continue;
+      long long t = 0;
+      for (auto &e : es) {
+        e.tile0 = t;
+        t += (long long)e.gx * e.gy * e.gz;
+      }
+      plan.steps.push_back({kind, gr.first, gr.second, f32, (int)plan.lists.size()});
+      plan.lists.push_back(std::move(es));
+      plan.sig.push_back(kind * 64 + gr.first * 8 + gr.second * 2 + (f32 ? 1 : 0));
+      plan.sig.push_back((int)plan.lists.back().size());
+    }
+  }
+
+  template <typename R>
+  static R *U(Level &L, int b) { return vbuf<R>(L, b); }
+
+  // coarse levels l >= 1 of the correction V-cycle (all problems with l < L_p)
+  template <typename R>
+  void down_up(int nu1, int nu2) {
+    constexpr bool F = std::is_same<R, float>::value;
+    for (int d = 1; d < maxdepth; d++) {
+      step(BK_BOTTOM, F, [&](emg_problem *p, BEnt &e) {
+        if (d != (int)p->lv.size() - 1) return false;
+        Level &L = p->lv[d];
+        e = BEnt{};
+        e.g = L.g;
+        e.gx = (p->nbot + 3) / 4;
+        e.gy = e.gz = 1;
+        e.Ainv = p->Ainv;
+        e.nbot = p->nbot;
+        e.a = fbuf<R>(L);
+        e.out = U<R>(L, 0);
+        e.ctl = p->ctl;
+        return true;
+      });
+      step(BK_JZERO, F, [&](emg_problem *p, BEnt &e) {
+        if (d >= (int)p->lv.size() - 1) return false;
+        Level &L = p->lv[d];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = fbuf<R>(L);
+        e.out = U<R>(L, 0);
+        e.ctl = p->ctl;
+        return true;
+      });
+      int cur = 0;
+      for (int s2 = 1; s2 < nu1; s2++, cur ^= 1)
+        step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
+          if (d >= (int)p->lv.size() - 1) return false;
+          Level &L = p->lv[d];
+          e = ent_level(L.g);
+          e.C = moduli<R>(L);
+          e.a = U<R>(L, cur);
+          e.b = fbuf<R>(L);
+          e.out = U<R>(L, cur ^ 1);
+          e.ctl = p->ctl;
+          return true;
+        });
+      step(BK_RESID, F, [&](emg_problem *p, BEnt &e) {
+        if (d >= (int)p->lv.size() - 1) return false;
+        Level &L = p->lv[d];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = U<R>(L, cur);
+        e.b = fbuf<R>(L);
+        e.out = rbuf<R>(L);
+        e.ctl = p->ctl;
+        return true;
+      });
+      step(BK_RESTRICT, F, [&](emg_problem *p, BEnt &e) {
+        if (d >= (int)p->lv.size() - 1) return false;
+        Level &L = p->lv[d], &Lc = p->lv[d + 1];
+        e = ent_level(Lc.g);
+        e.g = L.g;
+        e.g2 = Lc.g;
+        e.a = rbuf<R>(L);
+        e.out = fbuf<R>(Lc);
+        e.ctl = p->ctl;
+        return true;
+      });
+    }
+    // up: deepest first
+    const int post_cur = (nu1 - 1) & 1;   // buffer after the pre-sweeps of a coarse level
+    const int end_cur = (nu1 - 1 + nu2) & 1;
+    for (int d = maxdepth - 2; d >= 1; d--) {
+      step(BK_PROLONG, F, [&](emg_problem *p, BEnt &e) {
+        if (d >= (int)p->lv.size() - 1) return false;
+        Level &L = p->lv[d], &Lc = p->lv[d + 1];
+        const int cb = (d + 1 == (int)p->lv.size() - 1) ? 0 : end_cur;
+        e = ent_level(L.g);
+        e.g2 = Lc.g;
+        e.a = U<R>(Lc, cb);
+        e.out = U<R>(L, post_cur);
+        e.ctl = p->ctl;
+        return true;
+      });
+      int cur = post_cur;
+      for (int s2 = 0; s2 < nu2; s2++, cur ^= 1)
+        step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
+          if (d >= (int)p->lv.size() - 1) return false;
+          Level &L = p->lv[d];
+          e = ent_level(L.g);
+          e.C = moduli<R>(L);
+          e.a = U<R>(L, cur);
+          e.b = fbuf<R>(L);
+          e.out = U<R>(L, cur ^ 1);
+          e.ctl = p->ctl;
+          return true;
+        });
+    }
+  }
+
+  // level 0 of the correction cycle for the mixed path (from zero) / the
+  // FP64 path (on the iterate); ends with the result in buffer 0
+  template <typename R>
+  void level0(int nu1, int nu2, bool from_zero) {
+    constexpr bool F = std::is_same<R, float>::value;
+    int cur;
+    if (from_zero) {
+      step(BK_JZERO, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = fbuf<R>(L);
+        e.out = U<R>(L, 0);
+        e.ctl = p->ctl;
+        return true;
+      });
+      cur = 0;
+    } else {
+      step(BK_JACOBI_NORM, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = U<R>(L, 0);
+        e.b = fbuf<R>(L);
+        e.out = U<R>(L, 1);
+        e.partial = p->partial;
+        e.ctl = p->ctl;
+        return true;
+      });
+      check(0);
+      cur = 1;
+    }
+    for (int s2 = 1; s2 < nu1; s2++, cur ^= 1)
+      step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = U<R>(L, cur);
+        e.b = fbuf<R>(L);
+        e.out = U<R>(L, cur ^ 1);
+        e.ctl = p->ctl;
+        return true;
+      });
+    step(BK_RESID, F, [&](emg_problem *p, BEnt &e) {
+      Level &L = p->lv[0];
+      e = ent_level(L.g);
+      e.C = moduli<R>(L);
+      e.a = U<R>(L, cur);
+      e.b = fbuf<R>(L);
+      e.out = rbuf<R>(L);
+      e.ctl = p->ctl;
+      return true;
+    });
+    step(BK_RESTRICT, F, [&](emg_problem *p, BEnt &e) {
+      Level &L = p->lv[0], &Lc = p->lv[1];
+      e = ent_level(Lc.g);
+      e.g = L.g;
+      e.g2 = Lc.g;
+      e.a = rbuf<R>(L);
+      e.out = fbuf<R>(Lc);
+      e.ctl = p->ctl;
+      return true;
+    });
+    down_up<R>(nu1, nu2);
+    const int end_cur = (nu1 - 1 + nu2) & 1;
+    step(BK_PROLONG, F, [&](emg_problem *p, BEnt &e) {
+      Level &L = p->lv[0], &Lc = p->lv[1];
+      const int cb = ((int)p->lv.size() == 2) ? 0 : end_cur;
+      e = ent_level(L.g);
+      e.g2 = Lc.g;
+      e.a = U<R>(Lc, cb);
+      e.out = U<R>(L, cur);
+      e.ctl = p->ctl;
+      return true;
+    });
+    for (int s2 = 0; s2 < nu2; s2++, cur ^= 1)
+      step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = U<R>(L, cur);
+        e.b = fbuf<R>(L);
+        e.out = U<R>(L, cur ^ 1);
+        e.ctl = p->ctl;
+        return true;
+      });
+    if (cur != 0)
+      step(BK_COPY, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.a = U<R>(L, cur);
+        e.out = U<R>(L, 0);
+        e.ctl = p->ctl;
+        return true;
+      });
+  }
+
+  void check(int ans) {
+    for (auto &gr : groups) {
+      (void)gr;
+    }
+    std::vector<BEnt> es;
+    for (auto *p : probs) {
+      BEnt e{};
+      e.partial = p->partial;
+      e.nparts = nblocks(p->lv[0].g, p->lv[0].zc);
+      e.ctl = p->ctl;
+      e.ans = ans;
+      e.gx = e.gy = e.gz = 1;
+      es.push_back(e);
+    }
+    long long t = 0;
+    for (auto &e : es) e.tile0 = t++;
+    plan.steps.push_back({-1, 0, 0, false, (int)plan.lists.size()});
+    plan.lists.push_back(std::move(es));
+    plan.sig.push_back(-1);
+    plan.sig.push_back((int)plan.lists.back().size());
+  }
+
+  void mixed_outer() {
+    step(BK_ADDC, false, [&](emg_problem *p, BEnt &e) {
+      Level &L = p->lv[0];
+      e = ent_level(L.g);
+      e.a = L.u32[0];
+      e.out = L.u64[0];
+      e.ctl = p->ctl;
+      return true;
+    });
+    step(BK_RESID_F32, false, [&](emg_problem *p, BEnt &e) {
+      Level &L = p->lv[0];
+      e = ent_level(L.g);
+      e.C = L.C64;
+      e.a = L.u64[0];
+      e.b = L.f64;
+      e.out = L.f32;
+      e.partial = p->partial;
+      e.ctl = p->ctl;
+      return true;
+    });
+    check(0);
+  }
+
+  void cycles(int prec, int k, int nu1, int nu2) {
+    for (int c = 0; c < k; c++) {
+      if (prec == EMG_FP64) {
+        level0<double>(nu1, nu2, false);
+      } else {
+        mixed_outer();
+        level0<float>(nu1, nu2, true);
+      }
+    }
+  }
+};
+
+template <int D, int K>
+void launch_batch_kind(hipStream_t st, int kind, bool f32, const BList *L, double omega) {
+#define EMG_BK(KIND)                                                                                         \
+  case KIND:                                                                                                 \
+    if (f32)                                                                                                 \
+      hipLaunchKernelGGL((k_batch<D, K, float, KIND>), dim3(kBatchGrid), dim3(BX, BY, 1), 0, st, L, (float)omega); \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_batch<D, K, double, KIND>), dim3(kBatchGrid), dim3(BX, BY, 1), 0, st, L, omega); \
+    break;
+  switch (kind) {
+    EMG_BK(BK_JACOBI)
+    EMG_BK(BK_JACOBI_NORM)
+    EMG_BK(BK_RESID)
+    EMG_BK(BK_JZERO)
+    EMG_BK(BK_RESTRICT)
+    EMG_BK(BK_PROLONG)
+    EMG_BK(BK_BOTTOM)
+    EMG_BK(BK_COPY)
+    case BK_ADDC:
+      hipLaunchKernelGGL((k_batch<D, K, double, BK_ADDC>), dim3(kBatchGrid), dim3(BX, BY, 1), 0, st, L, omega);
+      break;
+    case BK_RESID_F32:
+      hipLaunchKernelGGL((k_batch<D, K, double, BK_RESID_F32>), dim3(kBatchGrid), dim3(BX, BY, 1), 0, st, L, omega);
+      break;
+  }
+#undef EMG_BK
+}
+
+// Device copy of a plan's work lists (capacity-sized, fixed addresses).
+struct BatchDev {
+  char *buf = nullptr;
+  size_t bytes = 0;
+  int nlists = 0, cap = 0;
+  std::vector<char> host;
+  const BList *list(int i) const { return (const BList *)(buf + (size_t)i * blist_bytes(cap)); }
+};
+
+emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st) {
+  int cap = 1;
+  for (auto &l : plan.lists) cap = std::max(cap, (int)l.size());
+  const int nl = (int)plan.lists.size();
+  if (!dev.buf || nl > dev.nlists || cap > dev.cap) {
+    if (dev.buf) HIPCK(hipFree(dev.buf));
+    dev.nlists = std::max(nl, 1);
+    dev.cap = std::max(cap, 16);
+    dev.bytes = (size_t)dev.nlists * blist_bytes(dev.cap);
+    HIPCK(hipMalloc((void **)&dev.buf, dev.bytes));
+    dev.host.assign(dev.bytes, 0);
+  }
+  const size_t stride = blist_bytes(dev.cap);
+  for (int i = 0; i < nl; i++) {
+    BList *h = (BList *)(dev.host.data() + (size_t)i * stride);
+    const auto &es = plan.lists[i];
+    h->n = (int)es.size();
+    h->total = 0;
+    for (size_t j = 0; j < es.size(); j++) {
+      h->e[j] = es[j];
+      h->total += (long long)es[j].gx * es[j].gy * es[j].gz;
+    }
+  }
+  HIPCK(hipMemcpyAsync(dev.buf, dev.host.data(), (size_t)nl * stride, hipMemcpyHostToDevice, st));
+  return EMG_OK;
+}
+
+void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, double omega) {
+  for (auto &s : plan.steps) {
+    const BList *L = dev.list(s.list);
+    if (s.kind < 0) {
+      hipLaunchKernelGGL(k_batch_check, dim3((unsigned)std::max<size_t>(plan.lists[s.list].size(), 1)), dim3(1024), 0,
+                         st, L);
+      continue;
+    }
+    if (s.D == 2 && s.K == MOD_ISO) launch_batch_kind<2, MOD_ISO>(st, s.kind, s.f32, L, omega);
+    else if (s.D == 2) launch_batch_kind<2, MOD_ANISO>(st, s.kind, s.f32, L, omega);
+    else if (s.K == MOD_ISO) launch_batch_kind<3, MOD_ISO>(st, s.kind, s.f32, L, omega);
+    else launch_batch_kind<3, MOD_ANISO>(st, s.kind, s.f32, L, omega);
+  }
+}
+
+// Per-problem preparation before joining a batch: hierarchy, right-hand
+// side, Dirichlet lift, control block.
+emg_status prepare(emg_problem *p, const emg_solve_opts &opt, hipStream_t st) {
+  if (!p->fine.empty()) return fail(EMG_EINVAL, "problems with refined levels are not batched");
+  hipStream_t keep = p->stream;
+  p->stream = st;
+  emg_status s = setup(p);
+  if (s == EMG_OK && opt.precision == EMG_MIXED) s = ensure_mixed(p);
+  if (s == EMG_OK) s = assemble_rhs(p);
+  if (s == EMG_OK) {
+    Level &L0 = p->lv[0];
+    if (p->D == 2) hipLaunchKernelGGL((k_lift<2>), grid_of(L0.g), kBlock, 0, st, L0.g, L0.f64, L0.u64[0]);
+    else hipLaunchKernelGGL((k_lift<3>), grid_of(L0.g), kBlock, 0, st, L0.g, L0.f64, L0.u64[0]);
+    if (opt.precision == EMG_MIXED) launch_fill<float>(p, (long long)p->D * L0.g.N, L0.u32[0], 0.0f);
+    Ctl c0{};
+    c0.r0sq = -1.0;
+    c0.tol2 = opt.rtol * opt.rtol;
+    c0.max_cycles = opt.max_cycles;
+    *p->ctl_host = c0;
+    if (hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st) != hipSuccess)
+      s = fail(EMG_EDEVICE, "control block upload failed");
+  }
+  p->stream = keep;
+  return s;
+}
+
+void fill_stats(emg_problem *p, const Ctl &c, emg_solve_stats *st) {
+  emg_solve_stats s{};
+  s.cycles = c.cycles;
+  s.rel_res = c.r0sq > 0 ? std::sqrt(c.rsq / c.r0sq) : 0.0;
+  s.converged = c.done == 1;
+  s.conv_factor = (c.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / c.cycles) : 0.0;
+  const Geom &g = p->lv[0].g;
+  long long inner = 1;
+  for (int a = 0; a < g.dim; a++) {
+    int cut = 0;
+    if (!g.per[a]) cut = (g.bc[2 * a] == EMG_BC_DIRICHLET) + (g.bc[2 * a + 1] == EMG_BC_DIRICHLET);
+    inner *= (g.m[a] - cut);
+  }
+  s.dofs = (long long)p->D * inner;
+  *st = s;
+}
+
+}  // namespace
+
 // ============================== C ABI ==============================
 
 extern "C" {
@@ -1121,6 +1562,82 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
   (void)hipEventDestroy(e1);
   *avg_ms = ms / reps;
   return finish(p);
+}
+
+// ---- ragged batches ----
+
+emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, emg_solve_stats *stats) {
+  if (!probs || n < 1) return fail(EMG_EINVAL, "empty batch");
+  emg_solve_opts opt;
+  emg_default_opts(&opt);
+  if (o) opt = *o;
+  if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
+  if (!(opt.omega > 0.0 && opt.omega < 2.0) || opt.warm_start) return fail(EMG_EINVAL, "bad omega or warm start");
+  std::vector<emg_problem *> ps(probs, probs + n);
+  for (auto *p : ps)
+    if (!p || p->ctx != ps[0]->ctx) return fail(EMG_EINVAL, "null problem or problems of different contexts");
+  for (size_t i = 0; i < ps.size(); i++)
+    for (size_t j = 0; j < i; j++)
+      if (ps[i] == ps[j]) return fail(EMG_EINVAL, "a problem appears twice in the batch");
+  hipStream_t st = ps[0]->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (auto *p : ps) {
+    HIPCK(hipStreamSynchronize(p->stream));
+    TRY(prepare(p, opt, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  Planner pl(ps);
+  pl.cycles(opt.precision, std::max(1, opt.check_every), opt.nu1, opt.nu2);
+  BatchDev dev;
+  emg_status s = upload_plan(pl.plan, dev, st);
+  hipGraphExec_t exec = nullptr;
+  if (s == EMG_OK && opt.use_graph) {
+    hipGraph_t graph;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) s = fail(EMG_EDEVICE, "capture");
+    if (s == EMG_OK) {
+      launch_plan(pl.plan, dev, st, opt.omega);
+      if (hipStreamEndCapture(st, &graph) != hipSuccess) s = fail(EMG_EDEVICE, "capture end");
+      else {
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) s = fail(EMG_EDEVICE, "instantiate");
+        (void)hipGraphDestroy(graph);
+      }
+    }
+  }
+  const auto t2 = std::chrono::steady_clock::now();
+  while (s == EMG_OK) {
+    if (exec) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) { s = fail(EMG_EDEVICE, "graph launch"); break; }
+    } else {
+      launch_plan(pl.plan, dev, st, opt.omega);
+    }
+    for (auto *p : ps)
+      if (hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st) != hipSuccess)
+        s = fail(EMG_EDEVICE, "control read");
+    if (hipStreamSynchronize(st) != hipSuccess) s = fail(EMG_EDEVICE, "batch cycle failed");
+    bool all = true;
+    for (auto *p : ps) all = all && p->ctl_host->done;
+    if (all) break;
+  }
+  const auto t3 = std::chrono::steady_clock::now();
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (dev.buf) (void)hipFree(dev.buf);
+  if (s != EMG_OK) return s;
+  emg_status worst = EMG_OK;
+  for (int i = 0; i < n; i++) {
+    const Ctl c = *ps[i]->ctl_host;
+    emg_solve_stats one;
+    fill_stats(ps[i], c, &one);
+    one.solve_seconds = std::chrono::duration<double>(t3 - t2).count();
+    one.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
+    if (stats) stats[i] = one;
+    if (c.done == 2) worst = EMG_EDIVERGED;
+    else if (c.done == 3 && worst == EMG_OK) worst = EMG_ENOTCONV;
+  }
+  if (worst == EMG_EDIVERGED) return fail(worst, "a problem of the batch diverged");
+  if (worst == EMG_ENOTCONV) return fail(worst, "a problem of the batch hit the cycle cap");
+  return EMG_OK;
 }
 
 // ---- block-structured AMR ----

@@ -22,7 +22,7 @@ __device__ __forceinline__ long long block_linear() {
 // y- and z-neighbours then sit in the same L2 instead of being fetched again
 // from HBM by another XCD.  Returns the tile coordinates of this block.
 constexpr int kXCD = 8;
-__device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
+__device__ __forceinline__ unsigned tile_of(int &tx, int &ty, int &tz) {
   const unsigned B = gridDim.x * gridDim.y * gridDim.z;
   const unsigned b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   const unsigned q = B / kXCD, r = B % kXCD;
@@ -31,6 +31,7 @@ __device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
   tx = L % gridDim.x;
   ty = (L / gridDim.x) % gridDim.y;
   tz = L / (gridDim.x * gridDim.y);
+  return L;
 }
 
 // Operator application / residual / damped Jacobi sweep on one level.
@@ -50,14 +51,11 @@ __device__ __forceinline__ void tile_of(int &tx, int &ty, int &tz) {
 #define EMG_STENCIL_OCC
 #endif
 template <int D, int K, typename R, int MODE, typename TO>
-__global__ __launch_bounds__(256) EMG_STENCIL_OCC void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
-                                                 const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
-  if (skip(ctl)) return;
-  int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y;
-  const int z0 = tz_ * zc, z1 = min(g.m[2], z0 + zc);
+__device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict__ C, const R *__restrict__ u,
+                                             const R *__restrict__ f, TO *__restrict__ out, R omega,
+                                             double *__restrict__ pslot, int tx, int ty, int tz, int zc) {
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
+  const int z0 = tz * zc, z1 = min(g.m[2], z0 + zc);
   double nrm = 0.0;
   if (x < g.m[0] && y < g.m[1])
   for (int z = z0; z < z1; z++) {
@@ -86,7 +84,17 @@ __global__ __launch_bounds__(256) EMG_STENCIL_OCC void k_stencil(Geom g, const R
       }
     }
   }
-  if (partial) block_sum_256(nrm, partial + block_linear());
+  if (pslot) block_sum_256(nrm, pslot);
+}
+
+template <int D, int K, typename R, int MODE, typename TO>
+__global__ __launch_bounds__(256) EMG_STENCIL_OCC void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
+                                                 const R *__restrict__ f, TO *__restrict__ out, R omega,
+                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  const unsigned L = tile_of(tx_, ty_, tz_);
+  body_stencil<D, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + L : nullptr, tx_, ty_, tz_, zc);
 }
 
 // u += e (FP32 correction into the FP64 iterate), pointwise.
@@ -99,12 +107,9 @@ __global__ __launch_bounds__(256) void k_add_correction(long long n, double *__r
 
 // First sweep from a zero initial guess: out = omega f / diag (Dirichlet: f).
 template <int D, int K, typename R>
-__global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
-                                                     R *__restrict__ out, R omega, const Ctl *__restrict__ ctl) {
-  if (skip(ctl)) return;
-  int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+__device__ __forceinline__ void body_jacobi_zero(const Geom &g, const R *__restrict__ C, const R *__restrict__ f,
+                                                 R *__restrict__ out, R omega, int tx, int ty, int tz) {
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
   if (x >= g.m[0] || y >= g.m[1]) return;
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
@@ -118,16 +123,22 @@ __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict
   }
 }
 
+template <int D, int K, typename R>
+__global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
+                                                     R *__restrict__ out, R omega, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  body_jacobi_zero<D, K, R>(g, C, f, out, omega, tx_, ty_, tz_);
+}
+
 // Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
 // axis on whose end the coarse node sits only the coincident fine node
 // enters; Dirichlet coarse rows get 0.
 template <int D, typename RI, typename RO>
-__global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf, RO *__restrict__ fc,
-                                                  const Ctl *__restrict__ ctl) {
-  if (skip(ctl)) return;
-  int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+__device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, const RI *__restrict__ rf,
+                                              RO *__restrict__ fc, int tx, int ty, int tz) {
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -164,15 +175,21 @@ __global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__
   for (int i = 0; i < D; i++) fc[i * gc.N + nc] = RO(acc[i]);
 }
 
-// u_fine += bilinear/trilinear interpolation of the coarse correction;
-// Dirichlet fine rows untouched.
-template <int D, typename RC, typename RF>
-__global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
-                                                     const Ctl *__restrict__ ctl) {
+template <int D, typename RI, typename RO>
+__global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf, RO *__restrict__ fc,
+                                                  const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  body_restrict<D, RI, RO>(gf, gc, rf, fc, tx_, ty_, tz_);
+}
+
+// u_fine += bilinear/trilinear interpolation of the coarse correction;
+// Dirichlet fine rows untouched.
+template <int D, typename RC, typename RF>
+__device__ __forceinline__ void body_prolong(const Geom &gc, const Geom &gf, const RC *__restrict__ ec,
+                                             RF *__restrict__ uf, int tx, int ty, int tz) {
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
   const int p[3] = {x, y, z};
@@ -198,6 +215,15 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC 
         for (int i = 0; i < D; i++) acc[i] += w * ec[i * gc.N + q];
       }
   for (int i = 0; i < D; i++) uf[i * gf.N + n] += RF(acc[i]);
+}
+
+template <int D, typename RC, typename RF>
+__global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
+                                                     const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  body_prolong<D, RC, RF>(gc, gf, ec, uf, tx_, ty_, tz_);
 }
 
 // Coarse-level moduli: full weighting of each stored component, injection
@@ -388,7 +414,13 @@ __global__ __launch_bounds__(256) void k_fill(long long n, T *__restrict__ out, 
 
 // Sum the norm partials in a fixed order and update the control block.
 // `ans` is the buffer index of the iterate whose residual was measured.
+__device__ __forceinline__ void body_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans);
+
 __global__ __launch_bounds__(1024) void k_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans) {
+  body_check(partial, nparts, ctl, ans);
+}
+
+__device__ __forceinline__ void body_check(const double *__restrict__ partial, long long nparts, Ctl *ctl, int ans) {
   if (ctl->done) return;
   double s0 = 0.0, s1 = 0.0;
   long long i = threadIdx.x;
@@ -504,17 +536,24 @@ __global__ __launch_bounds__(256) void k_gj_extract(const double *__restrict__ M
 
 // e = A^-1 f in FP64, one wavefront per row.
 template <typename RI, typename RO>
-__global__ __launch_bounds__(256) void k_bottom_solve(const double *__restrict__ Ainv, int n, const RI *__restrict__ f,
-                                                      RO *__restrict__ e, const Ctl *__restrict__ ctl) {
-  if (skip(ctl)) return;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void body_bottom(const double *__restrict__ Ainv, int n, const RI *__restrict__ f,
+                                            RO *__restrict__ e, int tile) {
+  const int row = tile * 4 + (int)((threadIdx.x + threadIdx.y * blockDim.x) >> 6);
+  const int lane = (threadIdx.x + threadIdx.y * blockDim.x) & 63;
   if (row >= n) return;
   double s = 0.0;
   for (int j = lane; j < n; j += 64) s += Ainv[(long long)row * n + j] * double(f[j]);
   s = wave_sum(s);
   if (lane == 0) e[row] = RO(s);
 }
+
+template <typename RI, typename RO>
+__global__ __launch_bounds__(256) void k_bottom_solve(const double *__restrict__ Ainv, int n, const RI *__restrict__ f,
+                                                      RO *__restrict__ e, const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  body_bottom<RI, RO>(Ainv, n, f, e, blockIdx.x);
+}
+
 
 }  // namespace emg
 
@@ -735,6 +774,98 @@ __global__ __launch_bounds__(256) void k_axpy(long long n, R *__restrict__ u, co
                                               const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) u[i] += e[i];
+}
+
+}  // namespace emg
+
+// ============================ ragged batching ============================
+// Many independent problems of different sizes go through one launch per
+// cycle step: the launch grid-strides over a device work list of entries
+// (problem, level, operands), each covering a run of tiles.  The per-tile
+// bodies are the single-problem ones, so every problem's arithmetic -- and
+// its norm partials, indexed by tile -- is the same alone and in a batch.
+// Converged problems (their control block says done) are skipped per entry.
+namespace emg {
+
+enum {
+  BK_JACOBI = 0, BK_JACOBI_NORM = 1, BK_RESID = 2, BK_JZERO = 3, BK_RESTRICT = 4, BK_PROLONG = 5, BK_BOTTOM = 6,
+  BK_COPY = 7, BK_ADDC = 8, BK_RESID_F32 = 9
+};
+
+struct BEnt {
+  Geom g, g2;            // level (fine level for restriction / interpolation), coarse level
+  const void *C, *a, *b; // moduli, first and second input
+  void *out;
+  double *partial;
+  Ctl *ctl;
+  const double *Ainv;
+  int nbot, ans;
+  int gx, gy, gz;        // tiles of this entry
+  long long tile0;       // first global tile
+  long long nparts;      // norm partials of the problem (check entries)
+};
+
+struct BList {
+  int n, pad;
+  long long total;       // tiles over all entries
+  BEnt e[1];             // n entries (allocated with capacity)
+};
+
+constexpr size_t blist_bytes(int cap) { return sizeof(BList) + sizeof(BEnt) * (cap > 1 ? cap - 1 : 0); }
+
+template <int D, int K, typename R, int KIND>
+__global__ __launch_bounds__(256) void k_batch(const BList *__restrict__ L, R omega) {
+  const int n = L->n;
+  const long long total = L->total;
+  for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L->e[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BEnt &E = L->e[lo];
+    if (E.ctl && E.ctl->done) continue;
+    const long long local = t - E.tile0;
+    const int tx = int(local % E.gx), ty = int((local / E.gx) % E.gy), tz = int(local / ((long long)E.gx * E.gy));
+    if constexpr (KIND == BK_JACOBI || KIND == BK_JACOBI_NORM) {
+      body_stencil<D, K, R, MODE_JACOBI, R>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (R *)E.out, omega,
+                                           KIND == BK_JACOBI_NORM ? E.partial + local : nullptr, tx, ty, tz, 1);
+    } else if constexpr (KIND == BK_RESID) {
+      body_stencil<D, K, R, MODE_RESID, R>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (R *)E.out, R(0),
+                                          nullptr, tx, ty, tz, 1);
+    } else if constexpr (KIND == BK_RESID_F32) {
+      body_stencil<D, K, double, MODE_RESID, float>(E.g, (const double *)E.C, (const double *)E.a,
+                                                    (const double *)E.b, (float *)E.out, 0.0, E.partial + local, tx,
+                                                    ty, tz, 1);
+    } else if constexpr (KIND == BK_JZERO) {
+      body_jacobi_zero<D, K, R>(E.g, (const R *)E.C, (const R *)E.a, (R *)E.out, omega, tx, ty, tz);
+    } else if constexpr (KIND == BK_RESTRICT) {
+      body_restrict<D, R, R>(E.g, E.g2, (const R *)E.a, (R *)E.out, tx, ty, tz);
+    } else if constexpr (KIND == BK_PROLONG) {
+      body_prolong<D, R, R>(E.g2, E.g, (const R *)E.a, (R *)E.out, tx, ty, tz);
+    } else if constexpr (KIND == BK_BOTTOM) {
+      body_bottom<R, R>(E.Ainv, E.nbot, (const R *)E.a, (R *)E.out, (int)local);
+    } else {
+      const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
+      if (x < E.g.m[0] && y < E.g.m[1]) {
+        const long long nn = ((long long)z * E.g.m[1] + y) * E.g.m[0] + x;
+        for (int i = 0; i < D; i++) {
+          const long long q = i * E.g.N + nn;
+          if constexpr (KIND == BK_COPY) ((R *)E.out)[q] = ((const R *)E.a)[q];
+          else ((double *)E.out)[q] += double(((const float *)E.a)[q]);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_check(const BList *__restrict__ L) {
+  for (int i = blockIdx.x; i < L->n; i += gridDim.x) {
+    const BEnt &E = L->e[i];
+    body_check(E.partial, E.nparts, E.ctl, E.ans);
+    __syncthreads();
+  }
 }
 
 }  // namespace emg

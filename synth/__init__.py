@@ -505,3 +505,24 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> Amr
         amr.b.append(np.ascontiguousarray(np.broadcast_to(body(X, Y, Z), (dim,) + mshape)))
         lo_p, hi_p = lo, hi
     return amr
+
+
+def inclusion_3d(n: int = 33, seed: int = 0, radius: float = 0.25, eigen: float = 1e-3) -> Problem:
+    """3D spherical inclusion in an isotropic matrix (matrix mu=1, lambda=1.5;
+    inclusion mu=2, lambda=3), centre jittered by up to 0.05 per axis, tanh
+    blend of width max(0.02, 1.5 h), isotropic eigenstrain inside; z = 0
+    clamped, the other faces traction-free."""
+    rng = np.random.default_rng(seed)
+    c = 0.5 + rng.uniform(-0.05, 0.05, size=3)
+    p = Problem(dim=3, n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                bc=(TRACTION, TRACTION, TRACTION, TRACTION, DIRICHLET, TRACTION), kind="iso", C=np.zeros(0),
+                name=f"inclusion3d_{n}_{seed}")
+    x, y, z = p.coords()
+    r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+    w = max(0.02, 1.5 * p.h[0])
+    eta = _tanh_step((r - radius) / w)
+    p.C = np.stack([1.5 + 1.5 * eta, 1.0 + 1.0 * eta]).astype(np.float64)
+    e = eigen * eta
+    zz = np.zeros_like(e)
+    p.eps0 = np.stack([e, e, e, zz, zz, zz]).astype(np.float64)
+    return p
