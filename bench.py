@@ -19,6 +19,13 @@ average duration is measured with HIP events on the problem's stream
 (emg_kernel_time) right after the timed steps; its algorithmic bytes are
 240 B per node (read u 3x8, C 21x8, f 3x8; write u 3x8).
 
+serving: a stream of 512 independent solve requests (3D spherical
+inclusions and 8-32-grain polycrystals, 33^3 to 129^3 nodes, log-uniform
+sizes, Poisson arrivals at 200 requests/s, seed 2005) is submitted to the
+continuous-batching server (mixed precision to 1e-10) with its inputs drawn
+from a pool pre-generated and resident in HBM; reported are p50/p99 latency
+(submit to result), solves/s and solve-DoF/s over the stream.
+
 cpu_baseline: the CPU oracle (plain FP64 C + OpenMP) on this host, on a
 bounded sample of the same workload: hierarchy setup, right-hand side and
 a fixed number of V-cycles are timed, and the solve time is scaled to the
@@ -46,6 +53,9 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=1, help="oracle V-cycles in the CPU sample (0 = skip)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=512, help="served stream length (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=16, help="concurrent requests on the GPU")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
                          "(used for hardware-counter runs)")
@@ -72,6 +82,57 @@ def cpu_baseline(spec, gpu_cycles, ncycles):
             "sample": f"setup + rhs + {ncycles} V-cycle(s) + residual norm on the full {spec.n[0]}^3 workload "
                       f"({t2 - t0:.1f} s); solve time scaled to {gpu_cycles} cycles",
             "seconds_per_cycle": per_cycle, "setup_seconds": t1 - t0}
+
+
+def serve(emg, torch, ctx, args):
+    """Served stream (continuous batching); latencies from the server's clock."""
+    import types
+    import numpy as np
+    import synth
+    trace = synth.serving_trace(count=args.serve_requests, seed=2005, rate=args.serve_rate)
+    dev = "cuda:0"
+    pool = {}
+    t0 = time.perf_counter()
+    for key in sorted({(r.kind, r.n, r.variant) for r in trace}):
+        sp = synth.serving_problem(*key)
+        d = types.SimpleNamespace(dim=sp.dim, n=sp.n, lo=sp.lo, hi=sp.hi, bc=sp.bc, kind=sp.kind, m=sp.m,
+                                  C=torch.from_numpy(sp.C).to(dev),
+                                  eps0=None if sp.eps0 is None else torch.from_numpy(sp.eps0).to(dev),
+                                  b=None if sp.b is None else torch.from_numpy(sp.b).to(dev),
+                                  face={f: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+                                        for f, v in (sp.face or {}).items() if v is not None})
+        pool[key] = (d, sp.dofs())
+    gen_s = time.perf_counter() - t0
+    def out_for(d):
+        return torch.empty((d.dim,) + tuple(d.m[::-1]), dtype=torch.float64, device=dev)
+
+    outs = [out_for(pool[(r.kind, r.n, r.variant)][0]) for r in trace]
+    torch.cuda.synchronize()
+    srv = emg.Server(ctx, max_slots=args.serve_slots, rtol=1e-10, max_cycles=400, precision="mixed")
+    # warm-up: one request per pooled input, so hierarchies and graphs are resident
+    warm = [srv.submit(d, out=out_for(d)) for d, _ in pool.values()]
+    for t in warm:
+        srv.wait(t)
+    base = srv.now()
+    tickets = []
+    for i, r in enumerate(trace):
+        while srv.now() - base < r.t:
+            time.sleep(min(1e-4, max(0.0, r.t - (srv.now() - base))))
+        tickets.append(srv.submit(pool[(r.kind, r.n, r.variant)][0], out=outs[i]))
+    infos = [srv.wait(t)[1] for t in tickets]
+    srv.close()
+    bad = [i for i in infos if i["status"] != 0 or not i["converged"]]
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    qwait = np.array([i["t_admit"] - i["t_submit"] for i in infos])
+    span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    dofs = sum(pool[(r.kind, r.n, r.variant)][1] for r in trace)
+    return {"requests": len(trace), "rate_req_per_s": args.serve_rate, "slots": args.serve_slots,
+            "precision": "mixed", "failed": len(bad),
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "mean_ms": 1e3 * float(lat.mean()), "queue_p50_ms": 1e3 * float(np.percentile(qwait, 50)),
+            "solves_per_s": len(trace) / span, "served_dofs_per_s": dofs / span, "span_s": span,
+            "offered_span_s": trace[-1].t, "mean_cycles": float(np.mean([i["cycles"] for i in infos])),
+            "inputs": f"{len(pool)} pre-generated inputs resident in HBM ({gen_s:.0f} s to generate)"}
 
 
 def main():
@@ -178,6 +239,9 @@ def main():
             "fp32_sweep_gbs": 120 * nodes / (ms_sweep32 * 1e-3) / 1e9,
         }
     prob.close()
+    del C_d, faces_d, sigma_d
+    if args.serve_requests > 0:
+        out["serving"] = serve(emg, torch, ctx, args)
     ctx.close()
     if args.cpu_cycles > 0:
         out["cpu_baseline"] = cpu_baseline(spec, out["fp64"]["cycles"], args.cpu_cycles)

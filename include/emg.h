@@ -181,6 +181,45 @@ emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, 
  * the batch's wall time.  Refined (AMR) problems and warm starts are rejected. */
 emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *opts, emg_solve_stats *stats);
 
+/* ---- serving: continuous batching of independent solves ----
+ * A server owns a scheduler thread and one stream.  Submitted requests wait in
+ * a FIFO queue; at every cycle boundary the scheduler admits queued requests
+ * while fewer than max_slots are active and the request's device footprint
+ * fits the context's HBM budget (idle resident hierarchies are freed to make
+ * room), runs one batched launch sequence (as emg_solve_batch) over all
+ * active requests for opts->check_every cycles, and retires converged ones:
+ * the displacement is copied to u_out and the problem's device memory stays
+ * resident for the next request with the same domain.  Requests that arrive
+ * while others are on the GPU therefore join the running batch, and each
+ * result is bit-identical to its emg_solve result.  Host inputs are copied at
+ * submit; with EMG_REQ_DEVICE every array (inputs and u_out) is a device
+ * pointer that is borrowed, not copied, and must stay valid and unchanged
+ * until the ticket is done.  u_out must stay valid until the ticket is done.
+ * Times are seconds on the server's steady clock (emg_server_now).  Ticket
+ * records are kept until the server is destroyed.  Calls are thread-safe. */
+typedef struct emg_server emg_server;
+#define EMG_REQ_DEVICE 1
+typedef struct {
+  emg_domain dom;
+  const double *C, *eps0, *body;   /* arrays as for emg_set_moduli / _eigenstrain / _body_force (eps0, body may be NULL) */
+  const double *face[6];           /* face data as for emg_set_face (NULL = 0) */
+  double *u_out;                   /* buffer for the displacement (d components, as emg_get_displacement), or NULL */
+  int flags;                       /* 0: host arrays; EMG_REQ_DEVICE: device arrays */
+} emg_request;
+typedef struct {
+  int done;
+  emg_status status;               /* EMG_OK, EMG_ENOTCONV, EMG_EDIVERGED, or the admission error */
+  emg_solve_stats stats;           /* solve_seconds = admission to completion */
+  double t_submit, t_admit, t_done;
+} emg_ticket_info;
+emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *opts, emg_server **out);
+emg_status emg_server_submit(emg_server *s, const emg_request *req, uint64_t *ticket);
+emg_status emg_server_poll(emg_server *s, uint64_t ticket, emg_ticket_info *info);
+emg_status emg_server_wait(emg_server *s, uint64_t ticket, emg_ticket_info *info);
+emg_status emg_server_now(emg_server *s, double *t);
+/* Finishes every submitted request, then frees the server and its resident hierarchies. */
+emg_status emg_server_destroy(emg_server *s);
+
 /* ---- block-structured AMR with reflux-free coarse/fine coupling (Sec. 3.2, App. A) ----
  * Refined level k >= 1 (ratio 2) is one box of valid nodes [lo, hi] of its
  * own index space (inclusive; every bound even, so the box corners fall on

@@ -46,6 +46,16 @@ class emg_solve_stats(ctypes.Structure):
                 ("solve_seconds", c_double), ("setup_seconds", c_double), ("dofs", c_int64)]
 
 
+class emg_request(ctypes.Structure):
+    _fields_ = [("dom", emg_domain), ("C", c_void_p), ("eps0", c_void_p), ("body", c_void_p),
+                ("face", c_void_p * 6), ("u_out", c_void_p), ("flags", c_int)]
+
+
+class emg_ticket_info(ctypes.Structure):
+    _fields_ = [("done", c_int), ("status", c_int), ("stats", emg_solve_stats), ("t_submit", c_double),
+                ("t_admit", c_double), ("t_done", c_double)]
+
+
 P = ctypes.POINTER
 _SIGS = {
     "emg_last_error": ([], ctypes.c_char_p),
@@ -76,6 +86,12 @@ _SIGS = {
     "emg_level_bottom_solve": ([c_void_p, c_int, c_void_p, c_void_p], c_int),
     "emg_kernel_time": ([c_void_p, c_int, c_int, c_int, c_int, P(c_double)], c_int),
     "emg_solve_batch": ([P(c_void_p), c_int, P(emg_solve_opts), P(emg_solve_stats)], c_int),
+    "emg_server_create": ([c_void_p, c_int, P(emg_solve_opts), P(c_void_p)], c_int),
+    "emg_server_submit": ([c_void_p, P(emg_request), P(ctypes.c_uint64)], c_int),
+    "emg_server_poll": ([c_void_p, ctypes.c_uint64, P(emg_ticket_info)], c_int),
+    "emg_server_wait": ([c_void_p, ctypes.c_uint64, P(emg_ticket_info)], c_int),
+    "emg_server_now": ([c_void_p, P(c_double)], c_int),
+    "emg_server_destroy": ([c_void_p], c_int),
     "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
     "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
     "emg_amr_level_shape": ([c_void_p, c_int, P(c_int64)], c_int),
@@ -169,19 +185,108 @@ def solve_batch(problems, raise_on_error: bool = True, **opts):
     return out
 
 
+def _domain(dim: int, n, lo, hi, bc, kind) -> emg_domain:
+    d = emg_domain()
+    d.dim = dim
+    for a in range(3):
+        d.n[a] = int(n[a])
+        d.lo[a] = float(lo[a])
+        d.hi[a] = float(hi[a]) if a < dim else float(lo[a]) + 1.0
+    for f in range(6):
+        d.bc[f] = _BC[bc[f]] if isinstance(bc[f], str) else int(bc[f])
+    d.kind = _KIND[kind] if isinstance(kind, str) else int(kind)
+    return d
+
+
+class Server:
+    """Continuous-batching solve server (emg_server_*): submit host problems,
+    collect displacements and per-request timing."""
+
+    def __init__(self, ctx: Context, max_slots: int = 8, **opts):
+        o = default_opts(**opts)
+        h = c_void_p()
+        check(lib.emg_server_create(ctx.handle, max_slots, ctypes.byref(o), ctypes.byref(h)), "emg_server_create")
+        self.handle, self.ctx = h, ctx
+        self._keep = {}
+
+    def submit(self, spec, out=None) -> int:
+        """Queue ``spec`` (attributes as for Problem.from_spec: numpy arrays,
+        copied at submit, or contiguous float64 device tensors, borrowed until
+        the request is done); returns a ticket.  ``out`` is an optional
+        device tensor for the displacement (required with device inputs)."""
+        r = emg_request()
+        r.dom = _domain(spec.dim, spec.n, spec.lo, spec.hi, spec.bc, spec.kind)
+        dev = hasattr(spec.C, "is_cuda") and spec.C.is_cuda
+        keep = []
+
+        def arr(a):
+            if a is None:
+                return None
+            if dev:
+                assert a.is_cuda and a.is_contiguous() and str(a.dtype) == "torch.float64"
+                keep.append(a)
+                return c_void_p(a.data_ptr())
+            x = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(x)
+            return x.ctypes.data_as(c_void_p)
+
+        r.C, r.eps0, r.body = arr(spec.C), arr(spec.eps0), arr(spec.b)
+        for f in range(6):
+            r.face[f] = arr(spec.face.get(f)) if spec.face and f < 2 * spec.dim else None
+        if dev:
+            assert out is not None, "device inputs need a device output tensor"
+            u = out
+            r.u_out = _dev(out)
+            r.flags = 1
+        else:
+            u = np.empty((spec.dim,) + tuple(spec.m[::-1]), dtype=np.float64)
+            r.u_out = u.ctypes.data_as(c_void_p)
+        t = ctypes.c_uint64()
+        check(lib.emg_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "emg_server_submit")
+        # the output (and, for device requests, the borrowed inputs) must outlive the request
+        self._keep[t.value] = (u, keep if dev else None)
+        return t.value
+
+    @staticmethod
+    def _info(i: emg_ticket_info) -> dict:
+        return {"done": bool(i.done), "status": i.status, "t_submit": i.t_submit, "t_admit": i.t_admit,
+                "t_done": i.t_done, **{k: getattr(i.stats, k) for k, _ in emg_solve_stats._fields_}}
+
+    def poll(self, ticket: int) -> dict:
+        i = emg_ticket_info()
+        check(lib.emg_server_poll(self.handle, ticket, ctypes.byref(i)), "emg_server_poll")
+        return self._info(i)
+
+    def wait(self, ticket: int):
+        """Block until the request is done; returns (displacement, info)."""
+        i = emg_ticket_info()
+        check(lib.emg_server_wait(self.handle, ticket, ctypes.byref(i)), "emg_server_wait")
+        u = self._keep.pop(ticket, (None, None))[0]
+        return u, self._info(i)
+
+    def now(self) -> float:
+        t = c_double()
+        check(lib.emg_server_now(self.handle, ctypes.byref(t)), "emg_server_now")
+        return t.value
+
+    def close(self):
+        if self.handle:
+            lib.emg_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Problem:
     """One solve problem on the GPU (owns its hierarchy and stream)."""
 
     def __init__(self, ctx: Context, dim: int, n, lo, hi, bc, kind: str):
-        d = emg_domain()
-        d.dim = dim
-        for a in range(3):
-            d.n[a] = int(n[a])
-            d.lo[a] = float(lo[a])
-            d.hi[a] = float(hi[a]) if a < dim else float(lo[a]) + 1.0
-        for f in range(6):
-            d.bc[f] = _BC[bc[f]] if isinstance(bc[f], str) else int(bc[f])
-        d.kind = _KIND[kind] if isinstance(kind, str) else int(kind)
+        d = _domain(dim, n, lo, hi, bc, kind)
         h = c_void_p()
         check(lib.emg_problem_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "emg_problem_create")
         self.handle, self.ctx, self.dim = h, ctx, dim
@@ -387,8 +492,8 @@ class Problem:
         return ms.value
 
 
-__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "EmgError", "check", "default_opts", "solve_batch",
-           "emg_domain", "emg_solve_opts", "emg_solve_stats",
+__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch",
+           "emg_domain", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
            "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE",
            "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_MOD_ISO", "EMG_MOD_ANISO",
            "EMG_FP64", "EMG_MIXED"] + list(SYMBOLS)

@@ -14,9 +14,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <utility>
 #include <vector>
@@ -119,6 +123,7 @@ struct emg_problem {
   bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
   std::vector<void *> allocs;
   size_t bytes = 0;
+  size_t accounted = 0;   // bytes charged to the context's HBM budget
   // graph cache: key = (precision, cycles per replay, nu1, nu2, omega)
   struct GraphEntry {
     int prec, k, nu1, nu2;
@@ -306,6 +311,15 @@ emg_status setup(emg_problem *p) {
 
 emg_status ensure_mixed(emg_problem *p) {
   if (p->mixed_ready) return EMG_OK;
+  if (!p->lv[0].C32 && p->ctx) {   // first use: charge the FP32 copies to the context's budget
+    size_t extra = 0;
+    for (auto &L : p->lv) extra += (size_t)L.g.N * (p->nc + 4 * p->D) * sizeof(float);
+    std::lock_guard<std::mutex> lk(p->ctx->mu);
+    if (p->ctx->budget && p->ctx->in_use + extra > p->ctx->budget)
+      return fail(EMG_ENOMEM, "HBM budget exceeded by the FP32 copies of mixed precision");
+    p->ctx->in_use += extra;
+    p->accounted += extra;
+  }
   for (auto &L : p->lv) {
     const long long nd = (long long)p->D * L.g.N;
     if (!L.C32) {
@@ -682,7 +696,6 @@ struct Planner {
       plan.steps.push_back({kind, gr.first, gr.second, f32, (int)plan.lists.size()});
       plan.lists.push_back(std::move(es));
       plan.sig.push_back(kind * 64 + gr.first * 8 + gr.second * 2 + (f32 ? 1 : 0));
-      plan.sig.push_back((int)plan.lists.back().size());
     }
   }
 
@@ -901,7 +914,6 @@ struct Planner {
     plan.steps.push_back({-1, 0, 0, false, (int)plan.lists.size()});
     plan.lists.push_back(std::move(es));
     plan.sig.push_back(-1);
-    plan.sig.push_back((int)plan.lists.back().size());
   }
 
   void mixed_outer() {
@@ -976,14 +988,22 @@ struct BatchDev {
   const BList *list(int i) const { return (const BList *)(buf + (size_t)i * blist_bytes(cap)); }
 };
 
-emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st) {
+// Writes the plan's lists into the device pool (reallocated, and *grew set,
+// only if it is too small: list addresses are what captured graphs hold).
+emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st, int min_cap = 16, int min_lists = 1,
+                       bool *grew = nullptr) {
   int cap = 1;
   for (auto &l : plan.lists) cap = std::max(cap, (int)l.size());
   const int nl = (int)plan.lists.size();
+  if (grew) *grew = false;
   if (!dev.buf || nl > dev.nlists || cap > dev.cap) {
-    if (dev.buf) HIPCK(hipFree(dev.buf));
-    dev.nlists = std::max(nl, 1);
-    dev.cap = std::max(cap, 16);
+    if (grew) *grew = dev.buf != nullptr;
+    if (dev.buf) {
+      HIPCK(hipStreamSynchronize(st));
+      HIPCK(hipFree(dev.buf));
+    }
+    dev.nlists = std::max(std::max(nl, 1), min_lists);
+    dev.cap = std::max(cap, min_cap);
     dev.bytes = (size_t)dev.nlists * blist_bytes(dev.cap);
     HIPCK(hipMalloc((void **)&dev.buf, dev.bytes));
     dev.host.assign(dev.bytes, 0);
@@ -1003,12 +1023,13 @@ emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st) {
   return EMG_OK;
 }
 
-void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, double omega) {
+// check_grid: workgroups of the batched convergence checks (grid-strided
+// over the problems), fixed so a captured graph serves any batch size
+void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, double omega, int check_grid) {
   for (auto &s : plan.steps) {
     const BList *L = dev.list(s.list);
     if (s.kind < 0) {
-      hipLaunchKernelGGL(k_batch_check, dim3((unsigned)std::max<size_t>(plan.lists[s.list].size(), 1)), dim3(1024), 0,
-                         st, L);
+      hipLaunchKernelGGL(k_batch_check, dim3((unsigned)std::max(check_grid, 1)), dim3(1024), 0, st, L);
       continue;
     }
     if (s.D == 2 && s.K == MOD_ISO) launch_batch_kind<2, MOD_ISO>(st, s.kind, s.f32, L, omega);
@@ -1063,6 +1084,273 @@ void fill_stats(emg_problem *p, const Ctl &c, emg_solve_stats *st) {
 
 }  // namespace
 
+namespace {
+
+// Validate a domain and build its multigrid level shapes.
+emg_status level_chain(const emg_domain *dom, std::vector<Geom> &gs) {
+  if (dom->dim != 2 && dom->dim != 3) return fail(EMG_EINVAL, "dim must be 2 or 3");
+  if (dom->kind != EMG_MOD_ISO && dom->kind != EMG_MOD_ANISO) return fail(EMG_EINVAL, "bad moduli kind");
+  Geom g{};
+  g.dim = dom->dim;
+  bool any_dir = false;
+  for (int a = 0; a < 3; a++) {
+    if (a < dom->dim) {
+      const int b0 = dom->bc[2 * a], b1 = dom->bc[2 * a + 1];
+      for (int b : {b0, b1})
+        if (b != EMG_BC_DIRICHLET && b != EMG_BC_TRACTION && b != EMG_BC_PERIODIC)
+          return fail(EMG_EINVAL, "bad boundary type");
+      if ((b0 == EMG_BC_PERIODIC) != (b1 == EMG_BC_PERIODIC))
+        return fail(EMG_EINVAL, "both faces of a periodic axis must be periodic");
+      any_dir = any_dir || b0 == EMG_BC_DIRICHLET || b1 == EMG_BC_DIRICHLET;
+      if (dom->n[a] < 5 || dom->n[a] > (1 << 20)) return fail(EMG_EINVAL, "every axis needs 5..2^20 nodes");
+      if (!(dom->hi[a] > dom->lo[a])) return fail(EMG_EINVAL, "empty domain extent");
+      g.per[a] = b0 == EMG_BC_PERIODIC;
+      g.m[a] = (int)(g.per[a] ? dom->n[a] - 1 : dom->n[a]);
+      g.h[a] = (dom->hi[a] - dom->lo[a]) / double(dom->n[a] - 1);
+      g.bc[2 * a] = b0;
+      g.bc[2 * a + 1] = b1;
+    } else {
+      if (dom->n[a] != 1) return fail(EMG_EINVAL, "n[2] must be 1 in 2D");
+      g.m[a] = 1;
+      g.per[a] = 1;
+      g.h[a] = 1.0;
+      g.bc[2 * a] = g.bc[2 * a + 1] = EMG_BC_PERIODIC;
+    }
+  }
+  if (!any_dir) return fail(EMG_EINVAL, "at least one Dirichlet face is required (rigid-body null space)");
+  g.N = (long long)g.m[0] * g.m[1] * g.m[2];
+  gs.assign(1, g);
+  while (can_coarsen(gs.back())) gs.push_back(coarse_of(gs.back()));
+  if (gs.size() < 2) return fail(EMG_EINVAL, "grid does not coarsen (need even cell counts >= 8)");
+  const long long nbot = (long long)dom->dim * gs.back().N;
+  if (nbot > kMaxBottom) return fail(EMG_EINVAL, "coarsest level too large (" + std::to_string(nbot) + " unknowns)");
+  return EMG_OK;
+}
+
+// Device bytes a problem on this level chain holds (FP64 arrays; FP32
+// copies for mixed precision when `mixed`).
+size_t footprint_of(const std::vector<Geom> &gs, int dim, int kind, bool mixed) {
+  const int nc = kind == MOD_ISO ? 2 : (dim == 3 ? 21 : 6), ne = dim == 3 ? 6 : 3;
+  const long long nbot = (long long)dim * gs.back().N;
+  size_t b = 0;
+  for (auto &g : gs) {
+    b += g.N * (nc + 4 * dim) * sizeof(double);
+    if (mixed) b += g.N * (nc + 4 * dim) * sizeof(float);
+  }
+  return b + gs[0].N * (ne + dim) * sizeof(double) + sizeof(double) * (size_t)nbot * nbot;
+}
+
+}  // namespace
+
+
+// ============================ serving ============================
+namespace {
+
+struct Served {
+  uint64_t ticket = 0;
+  emg_domain dom{};
+  std::vector<double> C, eps, body, face[6];   // owned copies of host inputs
+  const double *pC = nullptr, *peps = nullptr, *pbody = nullptr, *pface[6] = {};
+  int on_device = 0;
+  double *u_out = nullptr;
+  emg_problem *p = nullptr;
+  size_t need = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  bool done = false;
+  emg_status status = EMG_OK;
+  emg_solve_stats stats{};
+};
+
+std::vector<long long> dom_key(const emg_domain &d) {
+  std::vector<long long> k = {d.dim, d.kind};
+  for (int a = 0; a < 3; a++) {
+    k.push_back(d.n[a]);
+    long long lo, hi;
+    std::memcpy(&lo, &d.lo[a], 8);
+    std::memcpy(&hi, &d.hi[a], 8);
+    k.push_back(lo);
+    k.push_back(hi);
+  }
+  for (int f = 0; f < 6; f++) k.push_back(d.bc[f]);
+  return k;
+}
+
+}  // namespace
+
+struct emg_server {
+  emg_ctx *ctx = nullptr;
+  int slots = 8;
+  emg_solve_opts opt{};
+  hipStream_t stream = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  bool stop = false;
+  uint64_t next = 1;
+  std::deque<Served *> pending;
+  std::vector<Served *> active;
+  std::map<uint64_t, Served *> all;
+  std::multimap<std::vector<long long>, emg_problem *> pool;   // resident hierarchies for reuse
+  std::map<std::vector<int>, hipGraphExec_t> graphs;
+  BatchDev dev;
+  std::chrono::steady_clock::time_point t0;
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+// Bring a request onto the device: a pooled problem of the same domain if
+// there is one, else a new one; upload its inputs; prepare it.
+emg_status admit(emg_server *S, Served *r) {
+  emg_problem *p = nullptr;
+  auto it = S->pool.find(dom_key(r->dom));
+  if (it != S->pool.end()) {
+    p = it->second;
+    S->pool.erase(it);
+  } else {
+    TRY(emg_problem_create(S->ctx, &r->dom, &p));
+  }
+  r->p = p;
+  TRY(emg_set_moduli(p, r->pC, r->on_device));
+  TRY(emg_set_eigenstrain(p, r->peps, r->on_device));
+  TRY(emg_set_body_force(p, r->pbody, r->on_device));
+  for (int f = 0; f < 2 * r->dom.dim; f++)
+    if (r->dom.bc[f] != EMG_BC_PERIODIC) TRY(emg_set_face(p, f, r->pface[f], r->on_device));
+  return prepare(p, S->opt, S->stream);
+}
+
+// Free pooled problems until `need` more bytes fit the context's budget.
+bool make_room(emg_server *S, size_t need) {
+  emg_ctx *c = S->ctx;
+  auto fits = [&]() {
+    std::lock_guard<std::mutex> lk(c->mu);
+    return c->budget == 0 || c->in_use + need <= c->budget;
+  };
+  while (!fits()) {
+    if (S->pool.empty()) return false;
+    auto it = S->pool.begin();
+    emg_problem_destroy(it->second);
+    S->pool.erase(it);
+  }
+  return true;
+}
+
+void finish(emg_server *S, Served *r, emg_status st) {
+  r->status = st;
+  r->t_done = S->now();
+  if (r->p) {
+    if (st == EMG_OK || st == EMG_ENOTCONV) {
+      if (r->u_out)
+        (void)copy_out(r->p, r->u_out, r->p->lv[0].u64[0], (size_t)r->p->D * r->p->lv[0].g.N, r->on_device);
+      fill_stats(r->p, *r->p->ctl_host, &r->stats);
+      r->stats.solve_seconds = r->t_done - r->t_admit;
+    }
+    S->pool.emplace(dom_key(r->dom), r->p);
+    r->p = nullptr;
+  }
+  r->C = std::vector<double>();
+  r->eps = std::vector<double>();
+  r->body = std::vector<double>();
+  for (auto &f : r->face) f = std::vector<double>();
+  r->pC = r->peps = r->pbody = nullptr;
+  for (auto &f : r->pface) f = nullptr;
+  std::lock_guard<std::mutex> lk(S->mu);
+  r->done = true;
+  S->cv_done.notify_all();
+}
+
+// Scheduler: admit at cycle boundaries (continuous batching), replay the
+// batched cycle graph for the active slot set, retire converged requests.
+void serve_loop(emg_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  hipGraphExec_t exec = nullptr;
+  bool changed = true;
+  BatchPlan plan;
+  const int k = std::max(1, S->opt.check_every);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (!S->stop && S->pending.empty() && S->active.empty()) S->cv.wait(lk);
+      if (S->stop && S->pending.empty() && S->active.empty()) break;
+    }
+    // Admit one at a time, so each admission sees the memory the previous one took.
+    for (;;) {
+      Served *r = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->pending.empty() || (int)S->active.size() >= S->slots) break;
+        r = S->pending.front();
+      }
+      const bool pooled = S->pool.count(dom_key(r->dom)) > 0;
+      if (!pooled && !make_room(S, r->need) && !S->active.empty()) break;   // wait for memory to free up
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->pending.pop_front();
+      }
+      r->t_admit = S->now();
+      const emg_status st = admit(S, r);
+      if (st != EMG_OK) {
+        finish(S, r, st);
+        continue;
+      }
+      S->active.push_back(r);
+      changed = true;
+    }
+    if (S->active.empty()) continue;
+    if (changed) {
+      std::vector<emg_problem *> ps;
+      for (auto *r : S->active) ps.push_back(r->p);
+      Planner pl(ps);
+      pl.cycles(S->opt.precision, k, S->opt.nu1, S->opt.nu2);
+      plan = std::move(pl.plan);
+      bool grew = false;
+      if (upload_plan(plan, S->dev, S->stream, S->slots, 256, &grew) != EMG_OK) {
+        for (auto *r : S->active) finish(S, r, EMG_EDEVICE);
+        S->active.clear();
+        continue;
+      }
+      if (grew) {
+        for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.second);
+        S->graphs.clear();
+      }
+      auto it = S->graphs.find(plan.sig);
+      if (it == S->graphs.end()) {
+        hipGraph_t graph;
+        exec = nullptr;
+        if (hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+          launch_plan(plan, S->dev, S->stream, S->opt.omega, S->slots);
+          if (hipStreamEndCapture(S->stream, &graph) == hipSuccess) {
+            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+            (void)hipGraphDestroy(graph);
+          }
+        }
+        if (exec) S->graphs[plan.sig] = exec;
+      } else {
+        exec = it->second;
+      }
+      changed = false;
+    }
+    if (exec) (void)hipGraphLaunch(exec, S->stream);
+    else launch_plan(plan, S->dev, S->stream, S->opt.omega, S->slots);
+    for (auto *r : S->active)
+      (void)hipMemcpyAsync(r->p->ctl_host, r->p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, S->stream);
+    const bool ok = hipStreamSynchronize(S->stream) == hipSuccess;
+    std::vector<Served *> keep;
+    for (auto *r : S->active) {
+      const int d = ok ? r->p->ctl_host->done : 2;
+      if (!ok) finish(S, r, EMG_EDEVICE);
+      else if (d == 0) keep.push_back(r);
+      else finish(S, r, d == 1 ? EMG_OK : (d == 2 ? EMG_EDIVERGED : EMG_ENOTCONV));
+    }
+    if (keep.size() != S->active.size()) changed = true;
+    S->active.swap(keep);
+  }
+  for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.second);
+  S->graphs.clear();
+}
+
+}  // namespace
+
 // ============================== C ABI ==============================
 
 extern "C" {
@@ -1101,42 +1389,9 @@ emg_status emg_ctx_destroy(emg_ctx *ctx) {
 
 emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem **out) {
   if (!ctx || !dom || !out) return fail(EMG_EINVAL, "null argument");
-  if (dom->dim != 2 && dom->dim != 3) return fail(EMG_EINVAL, "dim must be 2 or 3");
-  if (dom->kind != EMG_MOD_ISO && dom->kind != EMG_MOD_ANISO) return fail(EMG_EINVAL, "bad moduli kind");
-  Geom g{};
-  g.dim = dom->dim;
-  bool any_dir = false;
-  for (int a = 0; a < 3; a++) {
-    if (a < dom->dim) {
-      const int b0 = dom->bc[2 * a], b1 = dom->bc[2 * a + 1];
-      for (int b : {b0, b1})
-        if (b != EMG_BC_DIRICHLET && b != EMG_BC_TRACTION && b != EMG_BC_PERIODIC)
-          return fail(EMG_EINVAL, "bad boundary type");
-      if ((b0 == EMG_BC_PERIODIC) != (b1 == EMG_BC_PERIODIC))
-        return fail(EMG_EINVAL, "both faces of a periodic axis must be periodic");
-      any_dir = any_dir || b0 == EMG_BC_DIRICHLET || b1 == EMG_BC_DIRICHLET;
-      if (dom->n[a] < 5 || dom->n[a] > (1 << 20)) return fail(EMG_EINVAL, "every axis needs 5..2^20 nodes");
-      if (!(dom->hi[a] > dom->lo[a])) return fail(EMG_EINVAL, "empty domain extent");
-      g.per[a] = b0 == EMG_BC_PERIODIC;
-      g.m[a] = (int)(g.per[a] ? dom->n[a] - 1 : dom->n[a]);
-      g.h[a] = (dom->hi[a] - dom->lo[a]) / double(dom->n[a] - 1);
-      g.bc[2 * a] = b0;
-      g.bc[2 * a + 1] = b1;
-    } else {
-      if (dom->n[a] != 1) return fail(EMG_EINVAL, "n[2] must be 1 in 2D");
-      g.m[a] = 1;
-      g.per[a] = 1;
-      g.h[a] = 1.0;
-      g.bc[2 * a] = g.bc[2 * a + 1] = EMG_BC_PERIODIC;
-    }
-  }
-  if (!any_dir) return fail(EMG_EINVAL, "at least one Dirichlet face is required (rigid-body null space)");
-  g.N = (long long)g.m[0] * g.m[1] * g.m[2];
-  std::vector<Geom> gs{g};
-  while (can_coarsen(gs.back())) gs.push_back(coarse_of(gs.back()));
-  if (gs.size() < 2) return fail(EMG_EINVAL, "grid does not coarsen (need even cell counts >= 8)");
+  std::vector<Geom> gs;
+  TRY(level_chain(dom, gs));
   const long long nbot = (long long)dom->dim * gs.back().N;
-  if (nbot > kMaxBottom) return fail(EMG_EINVAL, "coarsest level too large (" + std::to_string(nbot) + " unknowns)");
 
   emg_problem *p = new emg_problem;
   p->ctx = ctx;
@@ -1157,16 +1412,12 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
     return bail(fail(EMG_EDEVICE, "hipStreamCreate failed"));
   p->stream = p->own;
   // footprint check before allocating
-  size_t need = 0;
-  for (size_t l = 0; l < gs.size(); l++) need += gs[l].N * (p->nc + 4 * p->D) * sizeof(double);
-  need += gs[0].N * (p->ne + p->D) * sizeof(double) + sizeof(double) * (size_t)nbot * nbot;
+  const size_t need = footprint_of(gs, p->D, p->K, false);
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->budget && ctx->in_use + need > ctx->budget) {
-      delete p;
-      return fail(EMG_ENOMEM, "HBM budget exceeded");
-    }
+    if (ctx->budget && ctx->in_use + need > ctx->budget) return bail(fail(EMG_ENOMEM, "HBM budget exceeded"));
     ctx->in_use += need;
+    p->accounted = need;
   }
   p->lv.resize(gs.size());
   for (size_t l = 0; l < gs.size(); l++) {
@@ -1203,12 +1454,9 @@ emg_status emg_problem_destroy(emg_problem *p) {
   for (void *a : p->allocs) (void)hipFree(a);
   if (p->ctl_host) (void)hipHostFree(p->ctl_host);
   if (p->own) (void)hipStreamDestroy(p->own);
-  if (p->ctx) {
+  if (p->ctx && p->accounted) {
     std::lock_guard<std::mutex> lk(p->ctx->mu);
-    size_t need = 0;
-    for (auto &L : p->lv) need += L.g.N * (p->nc + 4 * p->D) * sizeof(double);
-    if (!p->lv.empty()) need += p->lv[0].g.N * (p->ne + p->D) * sizeof(double) + sizeof(double) * (size_t)p->nbot * p->nbot;
-    p->ctx->in_use -= std::min(p->ctx->in_use, need);
+    p->ctx->in_use -= std::min(p->ctx->in_use, p->accounted);
   }
   delete p;
   return EMG_OK;
@@ -1597,7 +1845,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
     hipGraph_t graph;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) s = fail(EMG_EDEVICE, "capture");
     if (s == EMG_OK) {
-      launch_plan(pl.plan, dev, st, opt.omega);
+      launch_plan(pl.plan, dev, st, opt.omega, n);
       if (hipStreamEndCapture(st, &graph) != hipSuccess) s = fail(EMG_EDEVICE, "capture end");
       else {
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) s = fail(EMG_EDEVICE, "instantiate");
@@ -1610,7 +1858,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
     if (exec) {
       if (hipGraphLaunch(exec, st) != hipSuccess) { s = fail(EMG_EDEVICE, "graph launch"); break; }
     } else {
-      launch_plan(pl.plan, dev, st, opt.omega);
+      launch_plan(pl.plan, dev, st, opt.omega, n);
     }
     for (auto *p : ps)
       if (hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1637,6 +1885,122 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   }
   if (worst == EMG_EDIVERGED) return fail(worst, "a problem of the batch diverged");
   if (worst == EMG_ENOTCONV) return fail(worst, "a problem of the batch hit the cycle cap");
+  return EMG_OK;
+}
+
+// ---- serving ----
+
+emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *o, emg_server **out) {
+  if (!ctx || !out || max_slots < 1 || max_slots > 1024) return fail(EMG_EINVAL, "bad context, slots or output");
+  emg_server *S = new emg_server;
+  S->ctx = ctx;
+  S->slots = max_slots;
+  emg_default_opts(&S->opt);
+  if (o) S->opt = *o;
+  if ((S->opt.precision != EMG_FP64 && S->opt.precision != EMG_MIXED) || S->opt.nu1 < 1 || S->opt.nu2 < 0 ||
+      !(S->opt.omega > 0.0 && S->opt.omega < 2.0) || S->opt.warm_start) {
+    delete S;
+    return fail(EMG_EINVAL, "bad solve options");
+  }
+  S->t0 = std::chrono::steady_clock::now();
+  if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete S;
+    return fail(EMG_EDEVICE, "stream creation failed");
+  }
+  S->th = std::thread(serve_loop, S);
+  *out = S;
+  return EMG_OK;
+}
+
+emg_status emg_server_submit(emg_server *S, const emg_request *req, uint64_t *ticket) {
+  if (!S || !req || !ticket || !req->C) return fail(EMG_EINVAL, "null argument");
+  std::vector<Geom> gs;
+  TRY(level_chain(&req->dom, gs));
+  Served *r = new Served;
+  r->dom = req->dom;
+  const Geom &g = gs[0];
+  const int D = req->dom.dim, nc = req->dom.kind == EMG_MOD_ISO ? 2 : (D == 3 ? 21 : 6), ne = D == 3 ? 6 : 3;
+  r->on_device = (req->flags & EMG_REQ_DEVICE) != 0;
+  if (r->on_device) {   // borrowed device arrays
+    r->pC = req->C;
+    r->peps = req->eps0;
+    r->pbody = req->body;
+    for (int f = 0; f < 2 * D; f++) r->pface[f] = g.per[f / 2] ? nullptr : req->face[f];
+  } else {              // host arrays are copied now
+    r->C.assign(req->C, req->C + (size_t)nc * g.N);
+    if (req->eps0) r->eps.assign(req->eps0, req->eps0 + (size_t)ne * g.N);
+    if (req->body) r->body.assign(req->body, req->body + (size_t)D * g.N);
+    for (int f = 0; f < 2 * D; f++)
+      if (req->face[f] && !g.per[f / 2]) r->face[f].assign(req->face[f], req->face[f] + (size_t)D * (g.N / g.m[f / 2]));
+    r->pC = r->C.data();
+    r->peps = r->eps.empty() ? nullptr : r->eps.data();
+    r->pbody = r->body.empty() ? nullptr : r->body.data();
+    for (int f = 0; f < 2 * D; f++) r->pface[f] = r->face[f].empty() ? nullptr : r->face[f].data();
+  }
+  r->u_out = req->u_out;
+  r->need = footprint_of(gs, D, req->dom.kind, S->opt.precision == EMG_MIXED);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) {
+    delete r;
+    return fail(EMG_ESTATE, "server is shutting down");
+  }
+  r->ticket = S->next++;
+  r->t_submit = S->now();
+  S->all[r->ticket] = r;
+  S->pending.push_back(r);
+  S->cv.notify_all();
+  *ticket = r->ticket;
+  return EMG_OK;
+}
+
+static void ticket_info(const Served *r, emg_ticket_info *info) {
+  info->done = r->done;
+  info->status = r->status;
+  info->stats = r->stats;
+  info->t_submit = r->t_submit;
+  info->t_admit = r->t_admit;
+  info->t_done = r->t_done;
+}
+
+emg_status emg_server_poll(emg_server *S, uint64_t ticket, emg_ticket_info *info) {
+  if (!S || !info) return fail(EMG_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) return fail(EMG_EINVAL, "unknown ticket");
+  ticket_info(it->second, info);
+  return EMG_OK;
+}
+
+emg_status emg_server_wait(emg_server *S, uint64_t ticket, emg_ticket_info *info) {
+  if (!S || !info) return fail(EMG_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) return fail(EMG_EINVAL, "unknown ticket");
+  Served *r = it->second;
+  S->cv_done.wait(lk, [&] { return r->done; });
+  ticket_info(r, info);
+  return EMG_OK;
+}
+
+emg_status emg_server_now(emg_server *S, double *t) {
+  if (!S || !t) return fail(EMG_EINVAL, "null argument");
+  *t = S->now();
+  return EMG_OK;
+}
+
+emg_status emg_server_destroy(emg_server *S) {
+  if (!S) return EMG_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv.notify_all();
+  }
+  if (S->th.joinable()) S->th.join();
+  for (auto &kv : S->pool) emg_problem_destroy(kv.second);
+  for (auto &kv : S->all) delete kv.second;
+  if (S->dev.buf) (void)hipFree(S->dev.buf);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
   return EMG_OK;
 }
 

@@ -526,3 +526,47 @@ def inclusion_3d(n: int = 33, seed: int = 0, radius: float = 0.25, eigen: float 
     zz = np.zeros_like(e)
     p.eps0 = np.stack([e, e, e, zz, zz, zz]).astype(np.float64)
     return p
+
+
+SERVE_SIZES = (33, 49, 65, 97, 129)
+
+
+@dataclasses.dataclass(frozen=True)
+class ServeRequest:
+    """One request of a served stream: arrival time (s), problem type
+    ("inclusion" or "polycrystal"), nodes per axis, and the pooled input
+    variant it draws (inputs are pre-generated per (type, n, variant))."""
+    t: float
+    kind: str
+    n: int
+    variant: int
+
+
+def serving_trace(count: int = 512, seed: int = 2005, rate: float = 200.0, variants: int = 2):
+    """Poisson stream of independent solve requests: exponential gaps of mean
+    1/rate; size log-uniform in [33, 129] nodes per axis rounded in log space
+    to the nearest of 33, 49, 65, 97, 129; even ids are 3D spherical
+    inclusions, odd ids polycrystals; each request draws one of ``variants``
+    pre-generated inputs of its type and size."""
+    rng = np.random.default_rng(seed)
+    logs = np.log(np.array(SERVE_SIZES, dtype=np.float64))
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        s = rng.uniform(logs[0], logs[-1])
+        n = SERVE_SIZES[int(np.argmin(np.abs(logs - s)))]
+        v = int(rng.integers(variants))
+        out.append(ServeRequest(t, "inclusion" if i % 2 == 0 else "polycrystal", n, v))
+    return out
+
+
+def serving_problem(kind: str, n: int, variant: int, seed: int = 2005) -> Problem:
+    """Input of a served request type: a spherical inclusion (isotropic, as
+    ``inclusion_3d``) or a polycrystal with 8 to 32 grains (as
+    ``polycrystal_3d``), seeded by (seed, type, n, variant)."""
+    key = seed * 1000003 + (0 if kind == "inclusion" else 1) * 1009 * 1013 + n * 1013 + variant
+    if kind == "inclusion":
+        return inclusion_3d(n=n, seed=key)
+    rng = np.random.default_rng(key)
+    return polycrystal_3d(n=n, grains=int(rng.integers(8, 33)), seed=int(rng.integers(2 ** 31)))
