@@ -175,8 +175,7 @@ def main():
         return dt, stats
 
     if args.kernel_only:
-        prob.set_moduli(C_d)
-        st = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed")
+        st = step("mixed")
         ms64 = prob.kernel_time(0, level=0, precision="fp64", reps=args.kernel_reps)
         ms32 = prob.kernel_time(0, level=0, precision="mixed", reps=args.kernel_reps)
         src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device=dev)

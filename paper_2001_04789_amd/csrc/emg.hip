@@ -57,27 +57,10 @@ void dispatch(int D, int K, F &&f) {
 }
 
 dim3 grid_of(const Geom &g) { return dim3((g.m[0] + BX - 1) / BX, (g.m[1] + BY - 1) / BY, g.m[2]); }
-dim3 grid_zc(const Geom &g, int zc) {
-  return dim3((g.m[0] + BX - 1) / BX, (g.m[1] + BY - 1) / BY, (g.m[2] + zc - 1) / zc);
-}
-
-// Planes per workgroup of the z-marching generic kernels.  Measured on
-// MI355X (128 x 128 x 129 anisotropic FP64 sweep): 1 plane 256 us, 2: 271,
-// 4: 283, 8: 311, 16: 366 -- an XCD's L2 cannot hold the z-reuse window of
-// ~100 concurrent tiles at 240 B per node, so more planes per workgroup only
-// cost parallelism.  Default 1; EMG_ZC overrides for tuning.
-int choose_zc(const Geom &) {
-  if (const char *e = std::getenv("EMG_ZC")) {
-    const int v = std::atoi(e);
-    if (v >= 1) return v;
-  }
-  return 1;
-}
 const dim3 kBlock(BX, BY, 1);
 
 struct Level {
   Geom g{};
-  int zc = 1;        // z-planes per workgroup of the z-marching kernels
   double *C64 = nullptr;
   float *C32 = nullptr;
   double *u64[2] = {nullptr, nullptr};
@@ -179,10 +162,12 @@ Geom coarse_of(const Geom &g) {
   return c;
 }
 
-long long nblocks(const Geom &g, int zc) {
-  dim3 gr = grid_zc(g, zc);
+// workgroups of a grid_of launch / of a stencil pass (one norm partial each)
+long long grid_blocks(const Geom &g) {
+  dim3 gr = grid_of(g);
   return (long long)gr.x * gr.y * gr.z;
 }
+long long stencil_blocks(const Geom &g) { return split_of(g).blocks; }
 
 // ---- kernel launch helpers (all on the problem's stream) ----
 
@@ -197,8 +182,8 @@ void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *
                     const Ctl *ctl) {
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), grid_zc(L.g, L.zc), kBlock, 0, p->stream, L.g, moduli<R>(L), u,
-                       f, out, omega, partial, ctl, L.zc);
+    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0, p->stream, L.g,
+                       moduli<R>(L), u, f, out, omega, partial, ctl);
   });
 }
 
@@ -407,7 +392,7 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
   Level &L0 = p->lv[0];
   int cur = 0;
   launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[0], L0.f64, L0.u64[1], omega, p->partial, p->ctl);
-  launch_check(p, nblocks(L0.g, L0.zc), 0);
+  launch_check(p, stencil_blocks(L0.g), 0);
   cur = 1;
   for (int s = 1; s < nu1; s++) {
     launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
@@ -434,7 +419,7 @@ void record_mixed_iter(emg_problem *p, int, int nu1, int nu2, float omega) {
   hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
                      p->stream, nd0, L0.u64[0], L0.u32[0], p->ctl);
   launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
-  launch_check(p, nblocks(L0.g, L0.zc), 0);
+  launch_check(p, stencil_blocks(L0.g), 0);
   const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega);
   if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
 }
@@ -455,7 +440,6 @@ dim3 covered_grid(emg_problem *p, const Box &b, int grow) {
 Level box_level(const Fine &F) {
   Level L;
   L.g = F.g;
-  L.zc = 1;
   L.C64 = F.C;
   return L;
 }
@@ -501,7 +485,7 @@ void amr_residual(emg_problem *p, const Ctl *ctl) {
   covered_array_box(p, 0, xlo, xhi);
   hipLaunchKernelGGL((k_masked_norm<D>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, xlo, xhi,
                      p->amr_partial + off, ctl);
-  off += nblocks(L0.g, 1);
+  off += grid_blocks(L0.g);
   for (int k = 1; k <= (int)p->fine.size(); k++) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
@@ -509,7 +493,7 @@ void amr_residual(emg_problem *p, const Ctl *ctl) {
     covered_array_box(p, k, xlo, xhi);
     hipLaunchKernelGGL((k_masked_norm<D>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr, xlo, xhi,
                        p->amr_partial + off, ctl);
-    off += nblocks(F.g, 1);
+    off += grid_blocks(F.g);
   }
 }
 
@@ -685,7 +669,12 @@ struct Planner {
       for (auto *p : probs) {
         if (p->D != gr.first || p->K != gr.second) continue;
         BEnt e{};
-        if (make(p, e)) es.push_back(e);
+        if (!make(p, e)) continue;
+        if (kind == BK_JACOBI || kind == BK_JACOBI_NORM || kind == BK_RESID || kind == BK_RESID_F32) {
+          e.gx = (int)stencil_blocks(e.g);   // stencil passes walk the interior/shell split
+          e.gy = e.gz = 1;
+        }
+        es.push_back(e);
       }
       if (es.empty()) continue;
       long long t = 0;
@@ -903,7 +892,7 @@ struct Planner {
     for (auto *p : probs) {
       BEnt e{};
       e.partial = p->partial;
-      e.nparts = nblocks(p->lv[0].g, p->lv[0].zc);
+      e.nparts = stencil_blocks(p->lv[0].g);
       e.ctl = p->ctl;
       e.ans = ans;
       e.gx = e.gy = e.gz = 1;
@@ -1433,8 +1422,7 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
   }
   emg_status s;
   if ((s = dalloc(p, &p->Ainv, (size_t)nbot * nbot)) != EMG_OK) return bail(s);
-  for (auto &L : p->lv) L.zc = choose_zc(L.g);
-  p->npartial = nblocks(gs[0], 1);
+  p->npartial = std::max(grid_blocks(gs[0]), stencil_blocks(gs[0]));
   if ((s = dalloc(p, &p->partial, (size_t)p->npartial)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->ctl, 1)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->status, 4)) != EMG_OK) return bail(s);
@@ -1578,7 +1566,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   }
   if (opt.warm_start && p->fine.empty()) {
     launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
-    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, nblocks(L0.g, L0.zc), p->ctl);
+    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, stencil_blocks(L0.g), p->ctl);
   }
   if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[0], 0.0f);
   HIPCK(hipGetLastError());
@@ -2055,8 +2043,8 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
   launch_fill<double>(p, (long long)nd, F.u, 0.0);
   p->fine.push_back(F);
   // norm partials of every level's composite rows
-  long long parts = nblocks(p->lv[0].g, 1);
-  for (auto &G : p->fine) parts += nblocks(G.g, 1);
+  long long parts = grid_blocks(p->lv[0].g);
+  for (auto &G : p->fine) parts += grid_blocks(G.g);
   TRY(dalloc(p, &p->amr_partial, (size_t)parts));
   p->amr_nparts = parts;
   destroy_graphs(p);

@@ -73,15 +73,16 @@ __device__ __forceinline__ int end_of(const Geom &g, int a, int c) {
 }
 
 __device__ __forceinline__ int row_class(const Geom &g, const int p[3]) {
-  int on = 0;
-  for (int a = 0; a < g.dim; a++) {
-    int e = end_of(g, a, p[a]);
+  int on = 0, dir = 0;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const int e = a < g.dim ? end_of(g, a, p[a]) : 0;
     if (e) {
       on = 1;
-      if (g.bc[2 * a + (e > 0)] == BC_DIR) return ROW_DIR;
+      if (g.bc[2 * a + (e > 0)] == BC_DIR) dir = 1;
     }
   }
-  return on ? ROW_TRAC : ROW_INT;
+  return dir ? ROW_DIR : (on ? ROW_TRAC : ROW_INT);
 }
 
 __device__ __forceinline__ long long stride_of(const Geom &g, int a) {
@@ -100,10 +101,18 @@ __device__ __forceinline__ long long shift(const Geom &g, int a, int c, int o) {
 }
 
 // Accessors for the displacement-like vector the rows act on.
+// Element i of the array at `base`.  With a 32-bit unsigned index the byte
+// offset is formed in 32 bits (valid while i * sizeof(R) < 2^32), so a load
+// from a wavefront-uniform base takes the scalar-base + 32-bit-offset form.
+template <typename R, typename I> __device__ __forceinline__ R ld(const R *__restrict__ base, I i) {
+  if constexpr (sizeof(I) == 4) return *(const R *)((const char *)base + (unsigned)(i * (unsigned)sizeof(R)));
+  else return base[i];
+}
+
 template <typename R> struct PtrU {
   const R *__restrict__ p;
   long long N;
-  __device__ __forceinline__ R operator()(int k, long long i) const { return p[k * N + i]; }
+  template <typename I> __device__ __forceinline__ R operator()(int k, I i) const { return ld(p + k * N, i); }
 };
 template <typename R> struct UnitU {   // unit vector e_q
   long long q, N;
@@ -111,33 +120,70 @@ template <typename R> struct UnitU {   // unit vector e_q
 };
 
 // ---- interior rows: product-rule operator with central differences ----
-template <int D, int K, typename R, class U>
-__device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long N, U u, long long n,
-                                              const long long om[3], const long long op[3], const R i2h[3],
-                                              const R ih2[3], R acc[D], R dg[D]) {
-  R G[D][D], H[D][D][D];
+// Loads are issued in two groups (displacement stencil and centre moduli,
+// then the neighbour moduli), each complete before its arithmetic starts, so
+// a wavefront waits for memory twice per node instead of once per operand.
+// With `f` given, the node's right-hand side (f[i N + n]) is loaded with the
+// first group into fc[], and the centre displacement is returned in uc[].
+// I is the node-index type: long long in general, 32-bit unsigned on the
+// interior fast path (offsets then wrap modulo 2^32 to the true index).
+template <int D, int K, typename R, class U, typename I = long long>
+__device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long N, U u, I n, const I om[3],
+                                              const I op[3], const R i2h[3], const R ih2[3], R acc[D], R dg[D],
+                                              const R *__restrict__ f = nullptr, R *fc = nullptr,
+                                              R *uc_out = nullptr) {
+  constexpr int NP = D == 3 ? 3 : 1;   // mixed pairs (j, l), j < l: (0,1) (0,2) (1,2)
+  constexpr int PJ[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+  R uc[D], up[D][D], um[D][D], upp[D][NP], upm[D][NP], ump[D][NP], umm[D][NP];
+  if (f) {
+#pragma unroll
+    for (int k = 0; k < D; k++) fc[k] = ld(f + k * N, n);
+  }
 #pragma unroll
   for (int k = 0; k < D; k++) {
-    R c0 = u(k, n);
+    uc[k] = u(k, n);
+    if (uc_out) uc_out[k] = uc[k];
 #pragma unroll
     for (int j = 0; j < D; j++) {
-      R up = u(k, n + op[j]), um = u(k, n + om[j]);
-      G[k][j] = (up - um) * i2h[j];
-      H[k][j][j] = (up - R(2) * c0 + um) * ih2[j];
+      up[k][j] = u(k, I(n + op[j]));
+      um[k][j] = u(k, I(n + om[j]));
     }
 #pragma unroll
-    for (int j = 0; j < D; j++)
+    for (int q = 0; q < NP; q++) {
+      const int j = PJ[q], l = PL[q];
+      upp[k][q] = u(k, I(n + op[j] + op[l]));
+      upm[k][q] = u(k, I(n + op[j] + om[l]));
+      ump[k][q] = u(k, I(n + om[j] + op[l]));
+      umm[k][q] = u(k, I(n + om[j] + om[l]));
+    }
+  }
+  if constexpr (K == MOD_ISO) {
+    const R *__restrict__ Cm = C + N;
+    R lam = ld(C, n), mu = ld(Cm, n), lp[D], lm[D], mp[D], mm[D];
 #pragma unroll
-      for (int l = j + 1; l < D; l++) {
-        R v = ((u(k, n + op[j] + op[l]) - u(k, n + op[j] + om[l])) -
-               (u(k, n + om[j] + op[l]) - u(k, n + om[j] + om[l]))) *
-              (i2h[j] * i2h[l]);
+    for (int j = 0; j < D; j++) {
+      lp[j] = ld(C, I(n + op[j]));
+      lm[j] = ld(C, I(n + om[j]));
+      mp[j] = ld(Cm, I(n + op[j]));
+      mm[j] = ld(Cm, I(n + om[j]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    R G[D][D], H[D][D][D];
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+        G[k][j] = (up[k][j] - um[k][j]) * i2h[j];
+        H[k][j][j] = (up[k][j] - R(2) * uc[k] + um[k][j]) * ih2[j];
+      }
+#pragma unroll
+      for (int q = 0; q < NP; q++) {
+        const int j = PJ[q], l = PL[q];
+        R v = ((upp[k][q] - upm[k][q]) - (ump[k][q] - umm[k][q])) * (i2h[j] * i2h[l]);
         H[k][j][l] = v;
         H[k][l][j] = v;
       }
-  }
-  if constexpr (K == MOD_ISO) {
-    const R lam = C[n], mu = C[N + n];
+    }
     R divu = R(0);
 #pragma unroll
     for (int k = 0; k < D; k++) divu += G[k][k];
@@ -151,11 +197,11 @@ __device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long
         lap += H[i][j][j];
         s2 += (j == i ? R(0) : ih2[j]);
       }
-      R dlam = (C[n + op[i]] - C[n + om[i]]) * i2h[i];
+      R dlam = (lp[i] - lm[i]) * i2h[i];
       R t1 = dlam * divu;
 #pragma unroll
       for (int j = 0; j < D; j++) {
-        R dmu = (C[N + n + op[j]] - C[N + n + om[j]]) * i2h[j];
+        R dmu = (mp[j] - mm[j]) * i2h[j];
         t1 += dmu * (G[i][j] + G[j][i]);
       }
       acc[i] = (lam + mu) * gd + mu * lap + t1;
@@ -165,7 +211,24 @@ __device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long
     constexpr int NV = nvoigt<D>(), NC = nmod<D, K>();
     R cc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; c++) cc[c] = C[c * N + n];
+    for (int c = 0; c < NC; c++) cc[c] = ld(C + c * N, n);
+    __builtin_amdgcn_sched_barrier(0);
+    R G[D][D], H[D][D][D];
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+        G[k][j] = (up[k][j] - um[k][j]) * i2h[j];
+        H[k][j][j] = (up[k][j] - R(2) * uc[k] + um[k][j]) * ih2[j];
+      }
+#pragma unroll
+      for (int q = 0; q < NP; q++) {
+        const int j = PJ[q], l = PL[q];
+        R v = ((upp[k][q] - upm[k][q]) - (ump[k][q] - umm[k][q])) * (i2h[j] * i2h[l]);
+        H[k][j][l] = v;
+        H[k][l][j] = v;
+      }
+    }
     R e[NV];
 #pragma unroll
     for (int a = 0; a < D; a++) e[a] = G[a][a];
@@ -190,21 +253,33 @@ __device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long
       acc[i] = a2;
       dg[i] = R(-2) * d2;
     }
-    // modulus-derivative term: sum_j [ (C(n+e_j) e)_{V(i,j)} - (C(n-e_j) e)_{V(i,j)} ] / (2 h_j)
+    // modulus-derivative term: sum_j [ (C(n+e_j) e)_{V(i,j)} - (C(n-e_j) e)_{V(i,j)} ] / (2 h_j);
+    // only the Voigt rows V(i,j) of the neighbours are read (15 of 21 in 3D)
+    R cq[D][2][NC];
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const I q = I(n + (s == 0 ? op[j] : om[j]));
+#pragma unroll
+        for (int i = 0; i < D; i++)
+#pragma unroll
+          for (int J = 0; J < NV; J++) {
+            const int c = utri(NV, vslot<D>(i, j), J);
+            cq[j][s][c] = ld(C + c * N, q);
+          }
+      }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
 #pragma unroll
       for (int s = 0; s < 2; s++) {
-        const long long q = n + (s == 0 ? op[j] : om[j]);
-        R cq[NC];
-#pragma unroll
-        for (int c = 0; c < NC; c++) cq[c] = C[c * N + q];
 #pragma unroll
         for (int i = 0; i < D; i++) {
-          const int I = vslot<D>(i, j);
+          const int Iv = vslot<D>(i, j);
           R sg = R(0);
 #pragma unroll
-          for (int J = 0; J < NV; J++) sg += cq[utri(NV, I, J)] * e[J];
+          for (int J = 0; J < NV; J++) sg += cq[j][s][utri(NV, Iv, J)] * e[J];
           acc[i] += (s == 0 ? sg : -sg) * i2h[j];
         }
       }
@@ -214,13 +289,15 @@ __device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long
 
 // ---- boundary rows on traction faces (3-point one-sided normal derivatives) ----
 template <int D, int K, typename R, class U>
-__device__ void traction_rows(const Geom &g, const R *__restrict__ C, U u, long long n, const int p[3], R acc[D],
+__device__ __forceinline__ void traction_rows(const Geom &g, const R *__restrict__ C, U u, long long n, const int p[3], R acc[D],
                               R dg[D]) {
   constexpr int NC = nmod<D, K>();
   R cc[NC];
+#pragma unroll
   for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
   R Gh[D][D], c0[D];
   int en[D];
+#pragma unroll
   for (int l = 0; l < D; l++) {
     const R hl = R(g.h[l]);
     en[l] = end_of(g, l, p[l]);
@@ -228,22 +305,30 @@ __device__ void traction_rows(const Geom &g, const R *__restrict__ C, U u, long 
       const int s = -en[l];   // inward direction
       const long long s1 = shift(g, l, p[l], s), s2 = shift(g, l, p[l], 2 * s);
       c0[l] = R(-3 * s) / (R(2) * hl);
+#pragma unroll
       for (int k = 0; k < D; k++)
         Gh[k][l] = R(s) * (R(-3) * u(k, n) + R(4) * u(k, n + s1) - u(k, n + s2)) / (R(2) * hl);
     } else {
       c0[l] = R(0);
       const long long sp = shift(g, l, p[l], 1), sm = shift(g, l, p[l], -1);
+#pragma unroll
       for (int k = 0; k < D; k++) Gh[k][l] = (u(k, n + sp) - u(k, n + sm)) / (R(2) * hl);
     }
   }
+#pragma unroll
   for (int i = 0; i < D; i++) { acc[i] = R(0); dg[i] = R(0); }
+#pragma unroll
   for (int a = 0; a < D; a++) {
     if (en[a] == 0) continue;
     const R na = R(en[a]);
+#pragma unroll
     for (int i = 0; i < D; i++) {
       R s = R(0), sd = R(0);
+#pragma unroll
       for (int k = 0; k < D; k++)
+#pragma unroll
         for (int l = 0; l < D; l++) s += cfull<D, K, R>(cc, i, a, k, l) * Gh[k][l];
+#pragma unroll
       for (int l = 0; l < D; l++) sd += cfull<D, K, R>(cc, i, a, i, l) * c0[l];
       acc[i] += na * s;
       dg[i] += na * sd;
@@ -253,6 +338,7 @@ __device__ void traction_rows(const Geom &g, const R *__restrict__ C, U u, long 
 
 // Neighbour offsets (with periodic wrap) of node p for the interior rows.
 __device__ __forceinline__ void neighbour_offsets(const Geom &g, const int p[3], long long om[3], long long op[3]) {
+#pragma unroll
   for (int a = 0; a < 3; a++) {
     if (a < g.dim) {
       om[a] = shift(g, a, p[a], -1);
@@ -271,6 +357,7 @@ __device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, 
     long long om[3], op[3];
     neighbour_offsets(g, p, om, op);
     R i2h[3], ih2[3];
+#pragma unroll
     for (int a = 0; a < 3; a++) {
       i2h[a] = R(0.5 / g.h[a]);
       ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
@@ -279,6 +366,7 @@ __device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, 
   } else if (cls == ROW_TRAC) {
     traction_rows<D, K, R, U>(g, C, u, n, p, acc, dg);
   } else {
+#pragma unroll
     for (int i = 0; i < D; i++) {
       acc[i] = u(i, n);
       dg[i] = R(1);
@@ -291,25 +379,33 @@ template <int D, int K, typename R>
 __device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, long long n, const int p[3], int cls,
                                         R dg[D]) {
   if (cls == ROW_DIR) {
+#pragma unroll
     for (int i = 0; i < D; i++) dg[i] = R(1);
     return;
   }
   constexpr int NC = nmod<D, K>();
   R cc[NC];
+#pragma unroll
   for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
   if (cls == ROW_INT) {
+#pragma unroll
     for (int i = 0; i < D; i++) {
       R s = R(0);
+#pragma unroll
       for (int j = 0; j < D; j++) s += cfull<D, K, R>(cc, i, j, i, j) * R(1.0 / (g.h[j] * g.h[j]));
       dg[i] = R(-2) * s;
     }
     return;
   }
+#pragma unroll
   for (int i = 0; i < D; i++) dg[i] = R(0);
+#pragma unroll
   for (int a = 0; a < D; a++) {
     int ea = end_of(g, a, p[a]);
     if (!ea) continue;
+#pragma unroll
     for (int i = 0; i < D; i++)
+#pragma unroll
       for (int l = 0; l < D; l++) {
         int el = end_of(g, l, p[l]);
         if (!el) continue;

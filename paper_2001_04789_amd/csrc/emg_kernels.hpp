@@ -34,67 +34,205 @@ __device__ __forceinline__ unsigned tile_of(int &tx, int &ty, int &tz) {
   return L;
 }
 
+// Work decomposition of a stencil pass over one level.  The interior box
+// holds the nodes whose rows are interior rows with in-range or periodically
+// wrapped neighbours: per axis the full range if periodic, else 1..m-2.  The
+// shell is the rest (boundary rows).  Blocks of 256 shell nodes come first,
+// then tiles of 64 x 4 nodes of one plane over the box, so the slower shell
+// blocks overlap the tiles instead of forming a tail.  Interior tiles take a
+// path with no row classification.  Block index = norm-partial index.
+struct Split {
+  int lo[3], hi[3];     // interior box per axis (inclusive)
+  int ntx, nty, ntz;    // interior tiles per axis (all 0 if the box is empty)
+  long long inner;      // interior tiles
+  long long shell;      // shell nodes
+  long long sblocks;    // ceil(shell / 256)
+  long long blocks;     // sblocks + inner
+};
+
+__host__ __device__ inline Split split_of(const Geom &g) {
+  Split s;
+  long long box = 1;
+  bool empty = false;
+  for (int a = 0; a < 3; a++) {
+    if (a >= g.dim) {
+      s.lo[a] = 0;
+      s.hi[a] = 0;
+    } else if (g.per[a]) {
+      s.lo[a] = 0;
+      s.hi[a] = g.m[a] - 1;
+    } else {
+      s.lo[a] = 1;
+      s.hi[a] = g.m[a] - 2;
+    }
+    const int b = s.hi[a] - s.lo[a] + 1;
+    if (b <= 0) empty = true;
+    box *= b > 0 ? b : 0;
+  }
+  if (!empty) {
+    s.ntx = (s.hi[0] - s.lo[0] + BX) / BX;
+    s.nty = (s.hi[1] - s.lo[1] + BY) / BY;
+    s.ntz = s.hi[2] - s.lo[2] + 1;
+    s.inner = (long long)s.ntx * s.nty * s.ntz;
+    s.shell = g.N - box;
+  } else {
+    s.ntx = s.nty = s.ntz = 0;
+    s.inner = 0;
+    s.shell = g.N;
+  }
+  s.sblocks = (s.shell + 255) / 256;
+  s.blocks = s.sblocks + s.inner;
+  return s;
+}
+
+// Coordinates of shell node s: the planes below the box (z < lo), then for
+// every box plane its ring (full rows outside the box, then the columns
+// outside the box of the box rows), then the planes above the box.  With an
+// empty box the shell is every node in storage order.
+__device__ __forceinline__ void shell_node(const Geom &g, const Split &sp, long long s, int p[3]) {
+  const int m0 = g.m[0], m1 = g.m[1];
+  const long long plane = (long long)m0 * m1;
+  if (sp.inner == 0) {
+    p[0] = int(s % m0);
+    p[1] = int((s / m0) % m1);
+    p[2] = int(s / plane);
+    return;
+  }
+  const int nzlo = sp.lo[2], nylo = sp.lo[1], nyhi = m1 - 1 - sp.hi[1], nxlo = sp.lo[0], nxhi = m0 - 1 - sp.hi[0];
+  const int by = sp.hi[1] - sp.lo[1] + 1;
+  if (s < nzlo * plane) {
+    p[2] = int(s / plane);
+    p[0] = int(s % m0);
+    p[1] = int((s / m0) % m1);
+    return;
+  }
+  s -= nzlo * plane;
+  const long long ring = (long long)(nylo + nyhi) * m0 + (long long)by * (nxlo + nxhi);
+  if (s < sp.ntz * ring) {
+    p[2] = sp.lo[2] + int(s / ring);
+    long long t = s % ring;
+    if (t < (long long)nylo * m0) {
+      p[1] = 0;
+      p[0] = int(t);
+      return;
+    }
+    t -= (long long)nylo * m0;
+    if (t < (long long)nyhi * m0) {
+      p[1] = m1 - 1;
+      p[0] = int(t);
+      return;
+    }
+    t -= (long long)nyhi * m0;
+    const int cpr = nxlo + nxhi;
+    p[1] = sp.lo[1] + int(t / cpr);
+    p[0] = int(t % cpr) < nxlo ? 0 : m0 - 1;
+    return;
+  }
+  s -= sp.ntz * ring;
+  p[2] = sp.hi[2] + 1 + int(s / plane);
+  p[0] = int(s % m0);
+  p[1] = int((s / m0) % m1);
+}
+
 // Operator application / residual / damped Jacobi sweep on one level.
 //   APPLY : out = D_H u
 //   RESID : out = f - D_H u                (norm partials if `partial`)
 //   JACOBI: out = u + omega (f - D_H u)/diag, Dirichlet rows out = f
 //           (norm partials of f - D_H u, i.e. of the input's residual, if `partial`)
 // Norm partials sum squares over non-Dirichlet rows, one value per block.
-// Each workgroup walks `zc` consecutive z-planes of its 64 x 4 tile, so the
-// z-neighbours a plane needs were read one iteration earlier and are still
-// in L2 (a whole plane of a 128^2 anisotropic level is larger than an XCD's L2).
-// Optional occupancy target of the stencil kernel (waves per SIMD) for
-// tuning builds; by default the compiler's own register budget is used.
-#ifdef EMG_STENCIL_WAVES
-#define EMG_STENCIL_OCC __attribute__((amdgpu_waves_per_eu(EMG_STENCIL_WAVES)))
-#else
-#define EMG_STENCIL_OCC
-#endif
+template <int MODE, int D, typename R, typename TO>
+__device__ __forceinline__ void finish_rows(long long N, long long n, int cls, const R acc[D], const R dg[D],
+                                            const R *__restrict__ u, const R *__restrict__ f, TO *__restrict__ out,
+                                            R omega, double &nrm) {
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const long long q = i * N + n;
+    if constexpr (MODE == MODE_APPLY) {
+      out[q] = TO(acc[i]);
+    } else if constexpr (MODE == MODE_RESID) {
+      const R r = f[q] - acc[i];
+      out[q] = TO(r);
+      if (cls != ROW_DIR) nrm += double(r) * double(r);
+    } else {
+      const R r = f[q] - acc[i];
+      if (cls == ROW_DIR) {
+        out[q] = TO(f[q]);
+      } else {
+        out[q] = TO(u[q] + omega * r / dg[i]);
+        nrm += double(r) * double(r);
+      }
+    }
+  }
+}
+
 template <int D, int K, typename R, int MODE, typename TO>
 __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict__ C, const R *__restrict__ u,
                                              const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                             double *__restrict__ pslot, int tx, int ty, int tz, int zc) {
-  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
-  const int z0 = tz * zc, z1 = min(g.m[2], z0 + zc);
+                                             double *__restrict__ pslot, long long t) {
+  const Split sp = split_of(g);
   double nrm = 0.0;
-  if (x < g.m[0] && y < g.m[1])
-  for (int z = z0; z < z1; z++) {
-    const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
-    const int p[3] = {x, y, z};
-    const int cls = row_class(g, p);
-    R acc[D], dg[D];
-    rows_at<D, K, R>(g, C, PtrU<R>{u, g.N}, n, p, cls, acc, dg);
+  if (t >= sp.sblocks) {
+    const long long it = t - sp.sblocks;
+    const int tx = int(it % sp.ntx), ty = int((it / sp.ntx) % sp.nty), tz = int(it / ((long long)sp.ntx * sp.nty));
+    const int x = sp.lo[0] + tx * BX + threadIdx.x, y = sp.lo[1] + ty * BY + threadIdx.y, z = sp.lo[2] + tz;
+    if (x <= sp.hi[0] && y <= sp.hi[1]) {
+      // 32-bit node indexing (level sizes are checked at creation: N < 2^31)
+      const unsigned m0 = g.m[0], m01 = (unsigned)g.m[0] * g.m[1];
+      const unsigned n = z * m01 + y * m0 + x;
+      const int c[3] = {x, y, z};
+      const unsigned st[3] = {1u, m0, m01};
+      unsigned om[3], op[3];
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      const long long q = i * g.N + n;
-      if constexpr (MODE == MODE_APPLY) {
-        out[q] = TO(acc[i]);
-      } else if constexpr (MODE == MODE_RESID) {
-        const R r = f[q] - acc[i];
-        out[q] = TO(r);
-        if (cls != ROW_DIR) nrm += double(r) * double(r);
-      } else {
-        const R r = f[q] - acc[i];
-        if (cls == ROW_DIR) {
-          out[q] = TO(f[q]);
+      for (int a = 0; a < 3; a++) {   // periodic wrap on the box faces of periodic axes
+        om[a] = a < D ? (c[a] == 0 ? (g.m[a] - 1) * st[a] : 0u - st[a]) : 0u;
+        op[a] = a < D ? (c[a] == g.m[a] - 1 ? 0u - (g.m[a] - 1) * st[a] : st[a]) : 0u;
+      }
+      R i2h[3], ih2[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        i2h[a] = R(0.5 / g.h[a]);
+        ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
+      }
+      R acc[D], dg[D], uc[D], fc[D];
+      interior_rows<D, K, R, PtrU<R>, unsigned>(C, g.N, PtrU<R>{u, g.N}, n, om, op, i2h, ih2, acc, dg,
+                                                MODE == MODE_APPLY ? nullptr : f, fc, uc);
+#pragma unroll
+      for (int i = 0; i < D; i++) {   // interior rows: never Dirichlet
+        TO *__restrict__ oi = (TO *)((char *)(out + i * g.N) + n * (unsigned)sizeof(TO));
+        if constexpr (MODE == MODE_APPLY) {
+          *oi = TO(acc[i]);
         } else {
-          out[q] = TO(u[q] + omega * r / dg[i]);
+          const R r = fc[i] - acc[i];
+          *oi = MODE == MODE_RESID ? TO(r) : TO(uc[i] + omega * r / dg[i]);
           nrm += double(r) * double(r);
         }
       }
+    }
+  } else {
+    const long long s = t * 256 + threadIdx.x + BX * threadIdx.y;
+    if (s < sp.shell) {
+      int p[3];
+      shell_node(g, sp, s, p);
+      const long long n = ((long long)p[2] * g.m[1] + p[1]) * g.m[0] + p[0];
+      const int cls = row_class(g, p);
+      R acc[D], dg[D];
+      rows_at<D, K, R>(g, C, PtrU<R>{u, g.N}, n, p, cls, acc, dg);
+      finish_rows<MODE, D, R, TO>(g.N, n, cls, acc, dg, u, f, out, omega, nrm);
     }
   }
   if (pslot) block_sum_256(nrm, pslot);
 }
 
+// One launch of split_of(g).blocks workgroups (64 x 4 threads); at least
+// two wavefronts per SIMD (the FP64 anisotropic path would otherwise take
+// just over the 256 registers of that occupancy).
 template <int D, int K, typename R, int MODE, typename TO>
-__global__ __launch_bounds__(256) EMG_STENCIL_OCC void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
+__global__ __launch_bounds__(256, 2) void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
                                                  const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl, int zc) {
+                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  int tx_, ty_, tz_;
-  const unsigned L = tile_of(tx_, ty_, tz_);
-  body_stencil<D, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + L : nullptr, tx_, ty_, tz_, zc);
+  const long long t = blockIdx.x;
+  body_stencil<D, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
 }
 
 // u += e (FP32 correction into the FP64 iterate), pointwise.
@@ -828,16 +966,16 @@ __global__ __launch_bounds__(256) void k_batch(const BList *__restrict__ L, R om
     if (E.ctl && E.ctl->done) continue;
     const long long local = t - E.tile0;
     const int tx = int(local % E.gx), ty = int((local / E.gx) % E.gy), tz = int(local / ((long long)E.gx * E.gy));
-    if constexpr (KIND == BK_JACOBI || KIND == BK_JACOBI_NORM) {
+    if constexpr (KIND == BK_JACOBI || KIND == BK_JACOBI_NORM) {   // stencil entries: gx = split blocks
       body_stencil<D, K, R, MODE_JACOBI, R>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (R *)E.out, omega,
-                                           KIND == BK_JACOBI_NORM ? E.partial + local : nullptr, tx, ty, tz, 1);
+                                           KIND == BK_JACOBI_NORM ? E.partial + local : nullptr, local);
     } else if constexpr (KIND == BK_RESID) {
       body_stencil<D, K, R, MODE_RESID, R>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (R *)E.out, R(0),
-                                          nullptr, tx, ty, tz, 1);
+                                          nullptr, local);
     } else if constexpr (KIND == BK_RESID_F32) {
       body_stencil<D, K, double, MODE_RESID, float>(E.g, (const double *)E.C, (const double *)E.a,
-                                                    (const double *)E.b, (float *)E.out, 0.0, E.partial + local, tx,
-                                                    ty, tz, 1);
+                                                    (const double *)E.b, (float *)E.out, 0.0, E.partial + local,
+                                                    local);
     } else if constexpr (KIND == BK_JZERO) {
       body_jacobi_zero<D, K, R>(E.g, (const R *)E.C, (const R *)E.a, (R *)E.out, omega, tx, ty, tz);
     } else if constexpr (KIND == BK_RESTRICT) {
