@@ -99,7 +99,9 @@ const char *emg_last_error(void);
 void emg_default_opts(emg_solve_opts *opts);
 
 /* Context: binds a HIP device and an HBM budget (0 = no limit) checked at
- * problem creation against the problem's device footprint. */
+ * problem creation against the problem's device footprint.  Destroying a
+ * context that still has live problems or servers defers the release to the
+ * last of them; no new problem or server can be created on it meanwhile. */
 emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out);
 emg_status emg_ctx_destroy(emg_ctx *ctx);
 

@@ -85,8 +85,22 @@ struct emg_ctx {
   int device = 0;
   size_t budget = 0;
   size_t in_use = 0;
+  int live = 0;            // problems and servers created on this context and not yet destroyed
+  bool closing = false;    // emg_ctx_destroy called while some were live: freed with the last one
   std::mutex mu;
 };
+
+namespace {
+// Drop one live object of the context; frees it if it was closed meanwhile.
+void ctx_release(emg_ctx *c) {
+  bool last = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    last = --c->live == 0 && c->closing;
+  }
+  if (last) delete c;
+}
+}  // namespace
 
 struct emg_problem {
   emg_ctx *ctx = nullptr;
@@ -107,6 +121,7 @@ struct emg_problem {
   std::vector<void *> allocs;
   size_t bytes = 0;
   size_t accounted = 0;   // bytes charged to the context's HBM budget
+  bool counted = false;   // counted in the context's live objects
   // graph cache: key = (precision, cycles per replay, nu1, nu2, omega)
   struct GraphEntry {
     int prec, k, nu1, nu2;
@@ -159,6 +174,7 @@ Geom coarse_of(const Geom &g) {
     c.h[a] = 2.0 * g.h[a];
   }
   c.N = (long long)c.m[0] * c.m[1] * c.m[2];
+  c.SC = moduli_stride(c.N);
   return c;
 }
 
@@ -254,11 +270,13 @@ emg_status setup(emg_problem *p) {
     const dim3 gr((F.b.hi[0] / 2 - F.b.lo[0] / 2 + BX) / BX, (F.b.hi[1] / 2 - F.b.lo[1] / 2 + BY) / BY,
                   p->D == 3 ? F.b.hi[2] / 2 - F.b.lo[2] / 2 + 1 : 1);
     if (p->D == 2) {
-      hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc);
-      if (Ec && F.eps) hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne);
+      hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc, F.g.SC, gc.SC);
+      if (Ec && F.eps)
+        hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne, F.g.N, gc.N);
     } else {
-      hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc);
-      if (Ec && F.eps) hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne);
+      hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc, F.g.SC, gc.SC);
+      if (Ec && F.eps)
+        hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne, F.g.N, gc.N);
     }
   }
   const int L = (int)p->lv.size();
@@ -298,7 +316,7 @@ emg_status ensure_mixed(emg_problem *p) {
   if (p->mixed_ready) return EMG_OK;
   if (!p->lv[0].C32 && p->ctx) {   // first use: charge the FP32 copies to the context's budget
     size_t extra = 0;
-    for (auto &L : p->lv) extra += (size_t)L.g.N * (p->nc + 4 * p->D) * sizeof(float);
+    for (auto &L : p->lv) extra += ((size_t)L.g.SC * p->nc + (size_t)L.g.N * 4 * p->D) * sizeof(float);
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     if (p->ctx->budget && p->ctx->in_use + extra > p->ctx->budget)
       return fail(EMG_ENOMEM, "HBM budget exceeded by the FP32 copies of mixed precision");
@@ -308,13 +326,13 @@ emg_status ensure_mixed(emg_problem *p) {
   for (auto &L : p->lv) {
     const long long nd = (long long)p->D * L.g.N;
     if (!L.C32) {
-      TRY(dalloc(p, &L.C32, (size_t)p->nc * L.g.N));
+      TRY(dalloc(p, &L.C32, (size_t)p->nc * L.g.SC));
       TRY(dalloc(p, &L.u32[0], nd));
       TRY(dalloc(p, &L.u32[1], nd));
       TRY(dalloc(p, &L.f32, nd));
       TRY(dalloc(p, &L.r32, nd));
     }
-    launch_cast<double, float>(p, (long long)p->nc * L.g.N, L.C64, L.C32, nullptr);
+    launch_cast<double, float>(p, (long long)p->nc * L.g.SC, L.C64, L.C32, nullptr);
   }
   HIPCK(hipGetLastError());
   p->mixed_ready = true;
@@ -602,6 +620,17 @@ emg_status validate_level(emg_problem *p, int level) {
 emg_status copy_in(emg_problem *p, double *dst, const double *src, size_t count, int on_device) {
   HIPCK(hipMemcpyAsync(dst, src, count * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                        p->stream));
+  HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+// ncomp component planes of `count` elements: source planes `src_ld` apart,
+// destination planes `dst_ld` apart (count defaults to src_ld).
+emg_status copy_planes(emg_problem *p, double *dst, long long dst_ld, const double *src, long long src_ld, int ncomp,
+                       hipMemcpyKind kind, long long count = -1) {
+  if (count < 0) count = src_ld;
+  HIPCK(hipMemcpy2DAsync(dst, dst_ld * sizeof(double), src, src_ld * sizeof(double), count * sizeof(double), ncomp,
+                         kind, p->stream));
   HIPCK(hipStreamSynchronize(p->stream));
   return EMG_OK;
 }
@@ -1108,6 +1137,7 @@ emg_status level_chain(const emg_domain *dom, std::vector<Geom> &gs) {
   }
   if (!any_dir) return fail(EMG_EINVAL, "at least one Dirichlet face is required (rigid-body null space)");
   g.N = (long long)g.m[0] * g.m[1] * g.m[2];
+  g.SC = moduli_stride(g.N);
   gs.assign(1, g);
   while (can_coarsen(gs.back())) gs.push_back(coarse_of(gs.back()));
   if (gs.size() < 2) return fail(EMG_EINVAL, "grid does not coarsen (need even cell counts >= 8)");
@@ -1123,8 +1153,8 @@ size_t footprint_of(const std::vector<Geom> &gs, int dim, int kind, bool mixed) 
   const long long nbot = (long long)dim * gs.back().N;
   size_t b = 0;
   for (auto &g : gs) {
-    b += g.N * (nc + 4 * dim) * sizeof(double);
-    if (mixed) b += g.N * (nc + 4 * dim) * sizeof(float);
+    b += (g.SC * nc + g.N * 4 * dim) * sizeof(double);
+    if (mixed) b += (g.SC * nc + g.N * 4 * dim) * sizeof(float);
   }
   return b + gs[0].N * (ne + dim) * sizeof(double) + sizeof(double) * (size_t)nbot * nbot;
 }
@@ -1372,6 +1402,14 @@ emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out
 }
 
 emg_status emg_ctx_destroy(emg_ctx *ctx) {
+  if (!ctx) return EMG_OK;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->live > 0) {   // deferred: the last problem or server frees it
+      ctx->closing = true;
+      return EMG_OK;
+    }
+  }
   delete ctx;
   return EMG_OK;
 }
@@ -1404,9 +1442,12 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
   const size_t need = footprint_of(gs, p->D, p->K, false);
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->closing) return bail(fail(EMG_ESTATE, "context is being destroyed"));
     if (ctx->budget && ctx->in_use + need > ctx->budget) return bail(fail(EMG_ENOMEM, "HBM budget exceeded"));
     ctx->in_use += need;
+    ctx->live += 1;
     p->accounted = need;
+    p->counted = true;
   }
   p->lv.resize(gs.size());
   for (size_t l = 0; l < gs.size(); l++) {
@@ -1414,7 +1455,7 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
     L.g = gs[l];
     const size_t nd = (size_t)p->D * L.g.N;
     emg_status s;
-    if ((s = dalloc(p, &L.C64, (size_t)p->nc * L.g.N)) != EMG_OK) return bail(s);
+    if ((s = dalloc(p, &L.C64, (size_t)p->nc * L.g.SC)) != EMG_OK) return bail(s);
     if ((s = dalloc(p, &L.u64[0], nd)) != EMG_OK) return bail(s);
     if ((s = dalloc(p, &L.u64[1], nd)) != EMG_OK) return bail(s);
     if ((s = dalloc(p, &L.f64, nd)) != EMG_OK) return bail(s);
@@ -1446,7 +1487,9 @@ emg_status emg_problem_destroy(emg_problem *p) {
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     p->ctx->in_use -= std::min(p->ctx->in_use, p->accounted);
   }
+  emg_ctx *c = p->counted ? p->ctx : nullptr;
   delete p;
+  if (c) ctx_release(c);
   return EMG_OK;
 }
 
@@ -1466,7 +1509,8 @@ emg_status emg_footprint(const emg_problem *p, size_t *bytes) {
 
 emg_status emg_set_moduli(emg_problem *p, const double *C, int on_device) {
   if (!p || !C) return fail(EMG_EINVAL, "null argument");
-  TRY(copy_in(p, p->lv[0].C64, C, (size_t)p->nc * p->lv[0].g.N, on_device));
+  TRY(copy_planes(p, p->lv[0].C64, p->lv[0].g.SC, C, p->lv[0].g.N, p->nc, on_device ? hipMemcpyDeviceToDevice
+                                                                                         : hipMemcpyHostToDevice));
   p->moduli_set = true;
   p->setup_done = p->mixed_ready = p->rhs_ready = false;
   return EMG_OK;
@@ -1679,7 +1723,8 @@ emg_status emg_level_moduli(emg_problem *p, int level, double *C_dev) {
   if (!p || !C_dev) return fail(EMG_EINVAL, "null argument");
   TRY(validate_level(p, level));
   TRY(setup(p));
-  return copy_out(p, C_dev, p->lv[level].C64, (size_t)p->nc * p->lv[level].g.N, 1);
+  return copy_planes(p, C_dev, p->lv[level].g.N, p->lv[level].C64, p->lv[level].g.SC, p->nc, hipMemcpyDeviceToDevice,
+                     p->lv[level].g.N);
 }
 
 static emg_status level_prep(emg_problem *p, int level, int precision) {
@@ -1895,6 +1940,15 @@ emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *
     delete S;
     return fail(EMG_EDEVICE, "stream creation failed");
   }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->closing) {
+      (void)hipStreamDestroy(S->stream);
+      delete S;
+      return fail(EMG_ESTATE, "context is being destroyed");
+    }
+    ctx->live += 1;
+  }
   S->th = std::thread(serve_loop, S);
   *out = S;
   return EMG_OK;
@@ -1988,7 +2042,9 @@ emg_status emg_server_destroy(emg_server *S) {
   for (auto &kv : S->all) delete kv.second;
   if (S->dev.buf) (void)hipFree(S->dev.buf);
   if (S->stream) (void)hipStreamDestroy(S->stream);
+  emg_ctx *c = S->ctx;
   delete S;
+  ctx_release(c);
   return EMG_OK;
 }
 
@@ -2026,8 +2082,9 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
     }
   }
   F.g.N = (long long)F.g.m[0] * F.g.m[1] * F.g.m[2];
+  F.g.SC = moduli_stride(F.g.N);
   const size_t nd = (size_t)p->D * F.g.N;
-  TRY(dalloc(p, &F.C, (size_t)p->nc * F.g.N));
+  TRY(dalloc(p, &F.C, (size_t)p->nc * F.g.SC));
   TRY(dalloc(p, &F.f, nd));
   TRY(dalloc(p, &F.u, nd));
   TRY(dalloc(p, &F.rr, nd));
@@ -2077,7 +2134,7 @@ emg_status emg_amr_set_moduli(emg_problem *p, int level, const double *C, int on
   Fine *F;
   TRY(fine_level(p, level, &F));
   if (!C) return fail(EMG_EINVAL, "null moduli");
-  TRY(copy_in(p, F->C, C, (size_t)p->nc * F->g.N, on_device));
+  TRY(copy_planes(p, F->C, F->g.SC, C, F->g.N, p->nc, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
   F->moduli_set = true;
   p->setup_done = p->rhs_ready = p->mixed_ready = false;
   return EMG_OK;

@@ -29,7 +29,16 @@ struct Geom {
   int bc[6];       // face types
   double h[3];     // spacing
   long long N;     // stored nodes
+  long long SC;    // component stride of the moduli arrays (>= N, see moduli_stride)
 };
+
+// Moduli arrays hold their components at a padded stride: with a stride that
+// is a multiple of a large power of two, the 21 component streams a stencil
+// reads together fall on the same HBM channels.  Offsetting each component by
+// 512 elements spreads them.
+__host__ __device__ inline long long moduli_stride(long long N) {
+  return N < 4096 ? N : ((N + 511) / 512) * 512 + 512;
+}
 
 // Convergence control block living in device memory.  Cycle kernels read
 // `done` first and return at once when it is set, so launches queued after
@@ -123,21 +132,22 @@ template <typename R> struct UnitU {   // unit vector e_q
 // Loads are issued in two groups (displacement stencil and centre moduli,
 // then the neighbour moduli), each complete before its arithmetic starts, so
 // a wavefront waits for memory twice per node instead of once per operand.
-// With `f` given, the node's right-hand side (f[i N + n]) is loaded with the
-// first group into fc[], and the centre displacement is returned in uc[].
-// I is the node-index type: long long in general, 32-bit unsigned on the
-// interior fast path (offsets then wrap modulo 2^32 to the true index).
+// N is the component stride of C.  With `f` given, the node's right-hand
+// side (f[i NF + n]) is loaded with the first group into fc[], and the centre
+// displacement is returned in uc[].  I is the node-index type: long long in
+// general, 32-bit unsigned on the interior fast path (offsets then wrap
+// modulo 2^32 to the true index).
 template <int D, int K, typename R, class U, typename I = long long>
 __device__ __forceinline__ void interior_rows(const R *__restrict__ C, long long N, U u, I n, const I om[3],
                                               const I op[3], const R i2h[3], const R ih2[3], R acc[D], R dg[D],
-                                              const R *__restrict__ f = nullptr, R *fc = nullptr,
+                                              const R *__restrict__ f = nullptr, long long NF = 0, R *fc = nullptr,
                                               R *uc_out = nullptr) {
   constexpr int NP = D == 3 ? 3 : 1;   // mixed pairs (j, l), j < l: (0,1) (0,2) (1,2)
   constexpr int PJ[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
   R uc[D], up[D][D], um[D][D], upp[D][NP], upm[D][NP], ump[D][NP], umm[D][NP];
   if (f) {
 #pragma unroll
-    for (int k = 0; k < D; k++) fc[k] = ld(f + k * N, n);
+    for (int k = 0; k < D; k++) fc[k] = ld(f + k * NF, n);
   }
 #pragma unroll
   for (int k = 0; k < D; k++) {
@@ -294,7 +304,7 @@ __device__ __forceinline__ void traction_rows(const Geom &g, const R *__restrict
   constexpr int NC = nmod<D, K>();
   R cc[NC];
 #pragma unroll
-  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
   R Gh[D][D], c0[D];
   int en[D];
 #pragma unroll
@@ -362,7 +372,7 @@ __device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, 
       i2h[a] = R(0.5 / g.h[a]);
       ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
     }
-    interior_rows<D, K, R, U>(C, g.N, u, n, om, op, i2h, ih2, acc, dg);
+    interior_rows<D, K, R, U>(C, g.SC, u, n, om, op, i2h, ih2, acc, dg);
   } else if (cls == ROW_TRAC) {
     traction_rows<D, K, R, U>(g, C, u, n, p, acc, dg);
   } else {
@@ -386,7 +396,7 @@ __device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, 
   constexpr int NC = nmod<D, K>();
   R cc[NC];
 #pragma unroll
-  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
   if (cls == ROW_INT) {
 #pragma unroll
     for (int i = 0; i < D; i++) {

@@ -194,8 +194,8 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
         ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
       }
       R acc[D], dg[D], uc[D], fc[D];
-      interior_rows<D, K, R, PtrU<R>, unsigned>(C, g.N, PtrU<R>{u, g.N}, n, om, op, i2h, ih2, acc, dg,
-                                                MODE == MODE_APPLY ? nullptr : f, fc, uc);
+      interior_rows<D, K, R, PtrU<R>, unsigned>(C, g.SC, PtrU<R>{u, g.N}, n, om, op, i2h, ih2, acc, dg,
+                                                MODE == MODE_APPLY ? nullptr : f, g.N, fc, uc);
 #pragma unroll
       for (int i = 0; i < D; i++) {   // interior rows: never Dirichlet
         TO *__restrict__ oi = (TO *)((char *)(out + i * g.N) + n * (unsigned)sizeof(TO));
@@ -395,9 +395,9 @@ __global__ __launch_bounds__(256) void k_coarsen(Geom gf, Geom gc, int nc, const
           if (hi[0]) w *= (ox == 0) ? R(0.5) : R(0.25);
           if (hi[1]) w *= (oy == 0) ? R(0.5) : R(0.25);
           if (hi[2]) w *= (oz == 0) ? R(0.5) : R(0.25);
-          acc += w * Cf[c * gf.N + nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1]];
+          acc += w * Cf[c * gf.SC + nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1]];
         }
-    Cc[c * gc.N + n] = acc;
+    Cc[c * gc.SC + n] = acc;
   }
 }
 
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
   const int p[3] = {x, y, z};
   const int cls = row_class(g, p);
   double cc[NC], ec[NE];
-  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
   for (int c = 0; c < NE; c++) ec[c] = eps ? eps[c * g.N + n] : 0.0;
   for (int i = 0; i < D; i++) {
     double acc = 0.0;
@@ -461,8 +461,8 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
           const long long sp = shift(g, j, p[j], 1), sm = shift(g, j, p[j], -1);
           double cp[NC], cm[NC], ep[NE], em[NE];
           for (int c = 0; c < NC; c++) {
-            cp[c] = C[c * g.N + n + sp];
-            cm[c] = C[c * g.N + n + sm];
+            cp[c] = C[c * g.SC + n + sp];
+            cm[c] = C[c * g.SC + n + sm];
           }
           for (int c = 0; c < NE; c++) {
             ep[c] = eps[c * g.N + n + sp];
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void k_stress(Geom g, const double *__restrict
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
   double cc[NC];
-  for (int c = 0; c < NC; c++) cc[c] = C[c * g.N + n];
+  for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
   double E[NE];   // strain minus eigenstrain, tensor components in Voigt order
   double Gd[D][D];
   for (int l = 0; l < D; l++) {
@@ -731,9 +731,10 @@ __global__ __launch_bounds__(256) void k_inject(Geom gc, int3 co, Geom gf, Box b
 // Full weighting of a field given on the ghosted box (moduli, eigenstrain)
 // at the covered coarse nodes: coarse levels carry the average of the finer
 // level where it exists (Sec. 1).
+// sf, sc: component strides of af and ac.
 template <int D>
 __global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, Box b, const double *__restrict__ af,
-                                                    double *__restrict__ ac, int ncomp) {
+                                                    double *__restrict__ ac, int ncomp, long long sf, long long sc) {
   const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
   const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
   const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
@@ -746,9 +747,9 @@ __global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, B
       for (int oy = -1; oy <= 1; oy++)
         for (int ox = -1; ox <= 1; ox++) {
           const double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
-          s += w * af[i * gf.N + lin(gf, fx + ox, fy + oy, fz + oz)];
+          s += w * af[i * sf + lin(gf, fx + ox, fy + oy, fz + oz)];
         }
-    ac[i * gc.N + nc] = s;
+    ac[i * sc + nc] = s;
   }
 }
 
