@@ -124,12 +124,14 @@ def serve(emg, torch, ctx, args):
     bad = [i for i in infos if i["status"] != 0 or not i["converged"]]
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
     qwait = np.array([i["t_admit"] - i["t_submit"] for i in infos])
+    prep = np.array([i["t_ready"] - i["t_admit"] for i in infos])
     span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
     dofs = sum(pool[(r.kind, r.n, r.variant)][1] for r in trace)
     return {"requests": len(trace), "rate_req_per_s": args.serve_rate, "slots": args.serve_slots,
             "precision": "mixed", "failed": len(bad),
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
             "mean_ms": 1e3 * float(lat.mean()), "queue_p50_ms": 1e3 * float(np.percentile(qwait, 50)),
+            "prep_mean_ms": 1e3 * float(prep.mean()),
             "solves_per_s": len(trace) / span, "served_dofs_per_s": dofs / span, "span_s": span,
             "offered_span_s": trace[-1].t, "mean_cycles": float(np.mean([i["cycles"] for i in infos])),
             "inputs": f"{len(pool)} pre-generated inputs resident in HBM ({gen_s:.0f} s to generate)"}

@@ -184,12 +184,15 @@ emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, 
 emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *opts, emg_solve_stats *stats);
 
 /* ---- serving: continuous batching of independent solves ----
- * A server owns a scheduler thread and one stream.  Submitted requests wait in
- * a FIFO queue; at every cycle boundary the scheduler admits queued requests
- * while fewer than max_slots are active and the request's device footprint
- * fits the context's HBM budget (idle resident hierarchies are freed to make
- * room), runs one batched launch sequence (as emg_solve_batch) over all
- * active requests for opts->check_every cycles, and retires converged ones:
+ * A server owns a preparation thread and a scheduler thread, each with its own
+ * stream.  Submitted requests wait in a FIFO queue; the preparation thread
+ * takes them in order once the request's device footprint fits the context's
+ * HBM budget (idle resident hierarchies are freed to make room) and builds
+ * hierarchy, right-hand side and lift while the GPU runs the current batch;
+ * at every cycle boundary the scheduler moves prepared requests into free
+ * slots (at most max_slots active), runs one batched launch sequence (as
+ * emg_solve_batch) over all active requests for opts->check_every cycles,
+ * and retires converged ones:
  * the displacement is copied to u_out and the problem's device memory stays
  * resident for the next request with the same domain.  Requests that arrive
  * while others are on the GPU therefore join the running batch, and each
@@ -211,8 +214,8 @@ typedef struct {
 typedef struct {
   int done;
   emg_status status;               /* EMG_OK, EMG_ENOTCONV, EMG_EDIVERGED, or the admission error */
-  emg_solve_stats stats;           /* solve_seconds = admission to completion */
-  double t_submit, t_admit, t_done;
+  emg_solve_stats stats;           /* setup_seconds = preparation, solve_seconds = prepared to completion */
+  double t_submit, t_admit, t_ready, t_done;   /* queued, preparation started, prepared, result copied out */
 } emg_ticket_info;
 emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *opts, emg_server **out);
 emg_status emg_server_submit(emg_server *s, const emg_request *req, uint64_t *ticket);

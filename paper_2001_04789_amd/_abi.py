@@ -53,7 +53,7 @@ class emg_request(ctypes.Structure):
 
 class emg_ticket_info(ctypes.Structure):
     _fields_ = [("done", c_int), ("status", c_int), ("stats", emg_solve_stats), ("t_submit", c_double),
-                ("t_admit", c_double), ("t_done", c_double)]
+                ("t_admit", c_double), ("t_ready", c_double), ("t_done", c_double)]
 
 
 P = ctypes.POINTER
@@ -250,7 +250,7 @@ class Server:
     @staticmethod
     def _info(i: emg_ticket_info) -> dict:
         return {"done": bool(i.done), "status": i.status, "t_submit": i.t_submit, "t_admit": i.t_admit,
-                "t_done": i.t_done, **{k: getattr(i.stats, k) for k, _ in emg_solve_stats._fields_}}
+                "t_ready": i.t_ready, "t_done": i.t_done, **{k: getattr(i.stats, k) for k, _ in emg_solve_stats._fields_}}
 
     def poll(self, ticket: int) -> dict:
         i = emg_ticket_info()

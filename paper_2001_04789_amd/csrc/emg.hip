@@ -1174,7 +1174,7 @@ struct Served {
   double *u_out = nullptr;
   emg_problem *p = nullptr;
   size_t need = 0;
-  double t_submit = 0, t_admit = 0, t_done = 0;
+  double t_submit = 0, t_admit = 0, t_ready = 0, t_done = 0;
   bool done = false;
   emg_status status = EMG_OK;
   emg_solve_stats stats{};
@@ -1196,50 +1196,51 @@ std::vector<long long> dom_key(const emg_domain &d) {
 
 }  // namespace
 
+// Two threads: the preparation thread takes queued requests in order, finds
+// room for them (pooled hierarchy of the same domain, else a new one after
+// freeing idle pooled ones), uploads their inputs and builds hierarchy, RHS
+// and lift on its own stream; the scheduler thread moves prepared requests
+// into free slots at cycle boundaries, replays the batched cycles of the
+// active set and retires converged requests.  Preparation thus overlaps the
+// running batch on the device.
 struct emg_server {
   emg_ctx *ctx = nullptr;
   int slots = 8;
   emg_solve_opts opt{};
-  hipStream_t stream = nullptr;
-  std::thread th;
-  std::mutex mu;
-  std::condition_variable cv, cv_done;
+  hipStream_t stream = nullptr, prep_stream = nullptr;
+  std::thread th, prep;
+  std::mutex mu;                            // guards everything below but `active`
+  std::condition_variable cv, cv_prep, cv_done;
   bool stop = false;
+  int preparing = 0, nactive = 0;
   uint64_t next = 1;
-  std::deque<Served *> pending;
-  std::vector<Served *> active;
+  std::deque<Served *> pending, ready;
+  std::vector<Served *> active;             // scheduler thread only
   std::map<uint64_t, Served *> all;
-  std::multimap<std::vector<long long>, emg_problem *> pool;   // resident hierarchies for reuse
-  std::map<std::vector<int>, hipGraphExec_t> graphs;
-  BatchDev dev;
+  std::multimap<std::vector<long long>, emg_problem *> pool;   // idle resident hierarchies
+  std::map<std::vector<int>, hipGraphExec_t> graphs;          // scheduler thread only
+  BatchDev dev;                                               // scheduler thread only
   std::chrono::steady_clock::time_point t0;
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
 namespace {
 
-// Bring a request onto the device: a pooled problem of the same domain if
-// there is one, else a new one; upload its inputs; prepare it.
-emg_status admit(emg_server *S, Served *r) {
-  emg_problem *p = nullptr;
-  auto it = S->pool.find(dom_key(r->dom));
-  if (it != S->pool.end()) {
-    p = it->second;
-    S->pool.erase(it);
-  } else {
-    TRY(emg_problem_create(S->ctx, &r->dom, &p));
-  }
-  r->p = p;
+// Upload a request's inputs into problem p and prepare it on the
+// preparation stream.
+emg_status admit(emg_server *S, Served *r, emg_problem *p) {
   TRY(emg_set_moduli(p, r->pC, r->on_device));
   TRY(emg_set_eigenstrain(p, r->peps, r->on_device));
   TRY(emg_set_body_force(p, r->pbody, r->on_device));
   for (int f = 0; f < 2 * r->dom.dim; f++)
     if (r->dom.bc[f] != EMG_BC_PERIODIC) TRY(emg_set_face(p, f, r->pface[f], r->on_device));
-  return prepare(p, S->opt, S->stream);
+  TRY(prepare(p, S->opt, S->prep_stream));
+  HIPCK(hipStreamSynchronize(S->prep_stream));
+  return EMG_OK;
 }
 
-// Free pooled problems until `need` more bytes fit the context's budget.
-bool make_room(emg_server *S, size_t need) {
+// With S->mu held: free idle pooled problems until `need` more bytes fit.
+bool make_room_locked(emg_server *S, size_t need) {
   emg_ctx *c = S->ctx;
   auto fits = [&]() {
     std::lock_guard<std::mutex> lk(c->mu);
@@ -1254,32 +1255,89 @@ bool make_room(emg_server *S, size_t need) {
   return true;
 }
 
-void finish(emg_server *S, Served *r, emg_status st) {
-  r->status = st;
-  r->t_done = S->now();
-  if (r->p) {
-    if (st == EMG_OK || st == EMG_ENOTCONV) {
-      if (r->u_out)
-        (void)copy_out(r->p, r->u_out, r->p->lv[0].u64[0], (size_t)r->p->D * r->p->lv[0].g.N, r->on_device);
-      fill_stats(r->p, *r->p->ctl_host, &r->stats);
-      r->stats.solve_seconds = r->t_done - r->t_admit;
-    }
-    S->pool.emplace(dom_key(r->dom), r->p);
-    r->p = nullptr;
-  }
+void release_inputs(Served *r) {
   r->C = std::vector<double>();
   r->eps = std::vector<double>();
   r->body = std::vector<double>();
   for (auto &f : r->face) f = std::vector<double>();
   r->pC = r->peps = r->pbody = nullptr;
   for (auto &f : r->pface) f = nullptr;
-  std::lock_guard<std::mutex> lk(S->mu);
-  r->done = true;
-  S->cv_done.notify_all();
 }
 
-// Scheduler: admit at cycle boundaries (continuous batching), replay the
-// batched cycle graph for the active slot set, retire converged requests.
+// Complete a request: copy its result out, return its hierarchy to the pool.
+void finish(emg_server *S, Served *r, emg_status st) {
+  r->status = st;
+  r->t_done = S->now();
+  if (r->p && (st == EMG_OK || st == EMG_ENOTCONV)) {
+    if (r->u_out)
+      (void)copy_out(r->p, r->u_out, r->p->lv[0].u64[0], (size_t)r->p->D * r->p->lv[0].g.N, r->on_device);
+    fill_stats(r->p, *r->p->ctl_host, &r->stats);
+    r->stats.solve_seconds = r->t_done - r->t_ready;
+    r->stats.setup_seconds = r->t_ready - r->t_admit;
+  }
+  release_inputs(r);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (r->p) S->pool.emplace(dom_key(r->dom), r->p);
+  r->p = nullptr;
+  r->done = true;
+  S->cv_done.notify_all();
+  S->cv_prep.notify_all();
+}
+
+void prep_loop(emg_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  const int cap = S->slots + std::max(1, S->slots / 2);   // prepared or active requests at most
+  for (;;) {
+    Served *r = nullptr;
+    emg_problem *p = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (;;) {
+        if (S->pending.empty()) {
+          if (S->stop) return;
+          S->cv_prep.wait(lk);
+          continue;
+        }
+        if ((int)S->ready.size() + S->nactive >= cap) {
+          S->cv_prep.wait(lk);
+          continue;
+        }
+        r = S->pending.front();
+        auto it = S->pool.find(dom_key(r->dom));
+        if (it != S->pool.end()) {
+          p = it->second;
+          S->pool.erase(it);
+          break;
+        }
+        if (make_room_locked(S, r->need) || ((int)S->ready.size() + S->nactive == 0)) break;
+        S->cv_prep.wait(lk);   // wait for a running request to free memory
+      }
+      S->pending.pop_front();
+      S->preparing = 1;
+    }
+    r->t_admit = S->now();
+    emg_status st = EMG_OK;
+    if (!p) st = emg_problem_create(S->ctx, &r->dom, &p);
+    r->p = p;
+    if (st == EMG_OK) st = admit(S, r, p);
+    r->t_ready = S->now();
+    if (st != EMG_OK) {
+      finish(S, r, st);
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->preparing = 0;
+      S->cv.notify_all();
+      continue;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->ready.push_back(r);
+    S->preparing = 0;
+    S->cv.notify_all();
+  }
+}
+
+// Scheduler: admit prepared requests at cycle boundaries (continuous
+// batching), replay the batched cycle graph for the active slot set, retire
+// converged requests.
 void serve_loop(emg_server *S) {
   (void)hipSetDevice(S->ctx->device);
   hipGraphExec_t exec = nullptr;
@@ -1289,31 +1347,17 @@ void serve_loop(emg_server *S) {
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      while (!S->stop && S->pending.empty() && S->active.empty()) S->cv.wait(lk);
-      if (S->stop && S->pending.empty() && S->active.empty()) break;
-    }
-    // Admit one at a time, so each admission sees the memory the previous one took.
-    for (;;) {
-      Served *r = nullptr;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->pending.empty() || (int)S->active.size() >= S->slots) break;
-        r = S->pending.front();
+      S->cv.wait(lk, [&] {
+        return !S->ready.empty() || !S->active.empty() ||
+               (S->stop && S->pending.empty() && S->preparing == 0);
+      });
+      if (S->active.empty() && S->ready.empty() && S->stop && S->pending.empty() && S->preparing == 0) break;
+      while (!S->ready.empty() && (int)S->active.size() < S->slots) {
+        S->active.push_back(S->ready.front());
+        S->ready.pop_front();
+        changed = true;
       }
-      const bool pooled = S->pool.count(dom_key(r->dom)) > 0;
-      if (!pooled && !make_room(S, r->need) && !S->active.empty()) break;   // wait for memory to free up
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->pending.pop_front();
-      }
-      r->t_admit = S->now();
-      const emg_status st = admit(S, r);
-      if (st != EMG_OK) {
-        finish(S, r, st);
-        continue;
-      }
-      S->active.push_back(r);
-      changed = true;
+      S->nactive = (int)S->active.size();
     }
     if (S->active.empty()) continue;
     if (changed) {
@@ -1326,6 +1370,8 @@ void serve_loop(emg_server *S) {
       if (upload_plan(plan, S->dev, S->stream, S->slots, 256, &grew) != EMG_OK) {
         for (auto *r : S->active) finish(S, r, EMG_EDEVICE);
         S->active.clear();
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->nactive = 0;
         continue;
       }
       if (grew) {
@@ -1361,8 +1407,13 @@ void serve_loop(emg_server *S) {
       else if (d == 0) keep.push_back(r);
       else finish(S, r, d == 1 ? EMG_OK : (d == 2 ? EMG_EDIVERGED : EMG_ENOTCONV));
     }
-    if (keep.size() != S->active.size()) changed = true;
-    S->active.swap(keep);
+    if (keep.size() != S->active.size()) {
+      changed = true;
+      S->active.swap(keep);
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->nactive = (int)S->active.size();
+      S->cv_prep.notify_all();
+    }
   }
   for (auto &g : S->graphs) (void)hipGraphExecDestroy(g.second);
   S->graphs.clear();
@@ -1940,16 +1991,23 @@ emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *
     delete S;
     return fail(EMG_EDEVICE, "stream creation failed");
   }
+  if (hipStreamCreateWithFlags(&S->prep_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return fail(EMG_EDEVICE, "stream creation failed");
+  }
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->closing) {
       (void)hipStreamDestroy(S->stream);
+      (void)hipStreamDestroy(S->prep_stream);
       delete S;
       return fail(EMG_ESTATE, "context is being destroyed");
     }
     ctx->live += 1;
   }
   S->th = std::thread(serve_loop, S);
+  S->prep = std::thread(prep_loop, S);
   *out = S;
   return EMG_OK;
 }
@@ -1990,7 +2048,7 @@ emg_status emg_server_submit(emg_server *S, const emg_request *req, uint64_t *ti
   r->t_submit = S->now();
   S->all[r->ticket] = r;
   S->pending.push_back(r);
-  S->cv.notify_all();
+  S->cv_prep.notify_all();
   *ticket = r->ticket;
   return EMG_OK;
 }
@@ -2001,6 +2059,7 @@ static void ticket_info(const Served *r, emg_ticket_info *info) {
   info->stats = r->stats;
   info->t_submit = r->t_submit;
   info->t_admit = r->t_admit;
+  info->t_ready = r->t_ready;
   info->t_done = r->t_done;
 }
 
@@ -2036,12 +2095,19 @@ emg_status emg_server_destroy(emg_server *S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
     S->cv.notify_all();
+    S->cv_prep.notify_all();
+  }
+  if (S->prep.joinable()) S->prep.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->cv.notify_all();
   }
   if (S->th.joinable()) S->th.join();
   for (auto &kv : S->pool) emg_problem_destroy(kv.second);
   for (auto &kv : S->all) delete kv.second;
   if (S->dev.buf) (void)hipFree(S->dev.buf);
   if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->prep_stream) (void)hipStreamDestroy(S->prep_stream);
   emg_ctx *c = S->ctx;
   delete S;
   ctx_release(c);
