@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Dict, Optional, Sequence, Tuple
 
 import numpy as np
@@ -185,29 +186,29 @@ def inclusion_2d(n: int = 65, width: float = 0.02, radius: float = 0.25, eigen: 
     return p
 
 
-def _voronoi_moduli(p: Problem, centers: np.ndarray, rots: Sequence[np.ndarray], width_cells: float,
-                    base: np.ndarray, scale=None) -> np.ndarray:
-    """Voronoi polycrystal, per-grain rotated moduli, grain boundaries
-    smoothed by tanh of the distance to the bisector plane (transition about
-    two cells), mixture rule C = sum g_n C_n / sum g_n (Sec. 4.3)."""
-    G = len(centers)
-    grainC = np.stack([upper21(rotate_voigt(base, R)) for R in rots])      # [G][21]
-    m = p.m
-    x, y, _ = p.coords()
-    hmin = min(p.h[:p.dim])
-    Lper = [p.hi[a] - p.lo[a] for a in range(3)]
-    out = np.empty((21, m[2], m[1], m[0]))
-    zs = p.lo[2] + p.h[2] * np.arange(m[2])
-    chunk = max(1, int(2 ** 22 // (m[0] * m[1] * max(G, 1))))
-    for z0 in range(0, m[2], chunk):
-        z = zs[z0:z0 + chunk][:, None, None]
+def _voronoi_worker(args):
+    """Process-pool entry: one BLAS thread per worker process."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        return _voronoi_block(args)
+
+
+def _voronoi_block(args):
+    """Moduli of z-planes [z0, z1) of the Voronoi polycrystal (see
+    ``_voronoi_moduli``)."""
+    (z0, z1, zs, x, y, m, centers, periodic, Lper, hmin, width_cells, grainC) = args
+    out = np.empty((21, z1 - z0, m[1], m[0]))
+    chunk = max(1, int(2 ** 22 // (m[0] * m[1] * max(len(centers), 1))))
+    for za in range(z0, z1, chunk):
+        zb = min(z1, za + chunk)
+        z = zs[za:zb][:, None, None]
         pos = [np.broadcast_to(x, (len(z), m[1], m[0])), np.broadcast_to(y, (len(z), m[1], m[0])),
                np.broadcast_to(z, (len(z), m[1], m[0]))]
         # per-seed displacement vectors with the minimum image on periodic axes
         dvec = []
         for a in range(3):
             dv = pos[a][None] - centers[:, a][:, None, None, None]
-            if p.periodic[a]:
+            if periodic[a]:
                 dv = dv - Lper[a] * np.round(dv / Lper[a])
             dvec.append(dv)
         d2 = dvec[0] ** 2 + dvec[1] ** 2 + dvec[2] ** 2                       # [G][...]
@@ -222,10 +223,40 @@ def _voronoi_moduli(p: Problem, centers: np.ndarray, rots: Sequence[np.ndarray],
         delta = np.where(sep2 > 0, (d2 - d2a[None]) / (2.0 * sep), 0.0)
         g = _tanh_step(delta / (0.5 * width_cells * hmin))
         g = g / g.sum(axis=0, keepdims=True)
-        blk = np.einsum("g...,gc->c...", g, grainC, optimize=True)
-        if scale is not None:
-            blk = blk * scale[z0:z0 + chunk][None]
-        out[:, z0:z0 + chunk] = blk
+        out[:, za - z0:zb - z0] = np.einsum("g...,gc->c...", g, grainC, optimize=True)
+    return out
+
+
+def _voronoi_moduli(p: Problem, centers: np.ndarray, rots: Sequence[np.ndarray], width_cells: float,
+                    base: np.ndarray, scale=None, workers: int = 0) -> np.ndarray:
+    """Voronoi polycrystal, per-grain rotated moduli, grain boundaries
+    smoothed by tanh of the distance to the bisector plane (transition about
+    two cells), mixture rule C = sum g_n C_n / sum g_n (Sec. 4.3).  Large
+    grids are split over z-planes across ``workers`` processes (0: up to 16
+    for grids above 4 M nodes); every node's value is the same either way."""
+    grainC = np.stack([upper21(rotate_voigt(base, R)) for R in rots])      # [G][21]
+    m = p.m
+    x, y, _ = p.coords()
+    hmin = min(p.h[:p.dim])
+    Lper = [p.hi[a] - p.lo[a] for a in range(3)]
+    zs = p.lo[2] + p.h[2] * np.arange(m[2])
+    if workers == 0:
+        workers = min(16, os.cpu_count() or 1) if m[0] * m[1] * m[2] > 4_000_000 else 1
+    common = (zs, x, y, m, np.asarray(centers), tuple(p.periodic), Lper, hmin, width_cells, grainC)
+    if workers <= 1:
+        out = _voronoi_block((0, m[2]) + common)
+    else:
+        import concurrent.futures
+        import multiprocessing
+        nj = min(m[2], 4 * workers)
+        bounds = np.linspace(0, m[2], nj + 1).astype(int)
+        jobs = [(int(bounds[i]), int(bounds[i + 1])) + common for i in range(nj) if bounds[i] < bounds[i + 1]]
+        out = np.empty((21, m[2], m[1], m[0]))
+        with concurrent.futures.ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("fork")) as ex:
+            for (z0, z1, *_), blk in zip(jobs, ex.map(_voronoi_worker, jobs)):
+                out[:, z0:z1] = blk
+    if scale is not None:
+        out = out * scale[None]
     return out
 
 

@@ -1,0 +1,135 @@
+"""Full-size checks of the workloads the benchmark and the configurations
+name, through the same C ABI calls and launch configuration as bench.py.
+
+At these sizes the oracle cannot run whole solves in seconds, so it checks:
+  * one operator application / residual / Jacobi sweep of the finest level,
+    element by element, on a random field (config 2, 129^3 polycrystal);
+  * the GPU solutions of FP64 and mixed-precision solves through the
+    oracle's own residual: relative residual <= 1.2e-10 (stopping test
+    1e-10 plus the rounding of the recomputation), and the mixed solution
+    within 1e-8 (relative 2-norm) of a FP64 solution iterated to 1e-13 whose
+    oracle residual is itself checked (configs 2 and 3: 129^3 and 257^3);
+  * the composite residual of the three-level AMR solve on the 65^3 base
+    (config 4, reading of floor and width as in synth.penny_crack).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import amr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def emg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_04789_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(emg):
+    c = emg.Context(0)
+    yield c
+    c.close()
+
+
+def rel_norm(g, u, f, C):
+    """Oracle relative residual of u (reference: the Dirichlet lift)."""
+    lift = np.where(oracle.dirichlet_mask(g), f, 0.0)
+    r0 = oracle.norm(g, oracle.residual(g, C, lift, f))
+    return oracle.norm(g, oracle.residual(g, C, u, f)) / r0
+
+
+def check_solves(emg, ctx, spec, label):
+    g = oracle.Grid.of(spec)
+    print(f"[gpu] {label}: oracle rhs", flush=True)
+    f = oracle.rhs(g, spec.C, spec.eps0, spec.b, spec.face)
+    prob = emg.Problem.from_spec(ctx, spec)
+    assert np.abs(prob.rhs() - f).max() <= 1e-12 * np.abs(f).max()
+    st_ref = prob.solve(rtol=1e-13, max_cycles=400, precision="fp64", raise_on_error=False)
+    u_ref = prob.displacement()
+    rel_ref = rel_norm(g, u_ref, f, spec.C)
+    print(f"[gpu] {label}: reference cycles={st_ref['cycles']} oracle rel residual={rel_ref:.2e}", flush=True)
+    assert rel_ref <= 1e-12
+    out = {}
+    for prec in ("fp64", "mixed"):
+        st = prob.solve(rtol=1e-10, max_cycles=400, precision=prec)
+        u = prob.displacement()
+        rel = rel_norm(g, u, f, spec.C)
+        err = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+        print(f"[gpu] {label}: {prec} cycles={st['cycles']} oracle rel residual={rel:.2e} "
+              f"error vs FP64 reference={err:.2e}", flush=True)
+        assert st["converged"] and rel <= 1.2e-10
+        assert err <= 1e-8
+        out[prec] = (st, u)
+    prob.close()
+    return out
+
+
+def test_config2_finest_level_steps(emg, ctx):
+    """129^3 polycrystal: the finest-level operator, residual and Jacobi
+    sweep (interior tiles and boundary shell) against the oracle, element by
+    element, in FP64 and FP32."""
+    spec = synth.polycrystal_3d(n=129, grains=16, seed=2002)
+    g = oracle.Grid.of(spec)
+    prob = emg.Problem.from_spec(ctx, spec)
+    rng = np.random.default_rng(11)
+    u = 1e-3 * rng.standard_normal(g.shape(3))
+    f = rng.standard_normal(g.shape(3))
+    print("[gpu] config 2 level steps: oracle", flush=True)
+    ref = {"apply": oracle.apply(g, spec.C, u), "residual": oracle.residual(g, spec.C, u, f),
+           "jacobi": oracle.jacobi(g, spec.C, u, f, 2.0 / 3.0)}
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("mixed", torch.float32, 2e-5)):
+        ud = torch.from_numpy(u).to(DEV, dtype=dt)
+        fd = torch.from_numpy(f).to(DEV, dtype=dt)
+        out = torch.empty_like(ud)
+        for step in ("apply", "residual", "jacobi"):
+            if step == "apply":
+                prob.level_apply(0, ud, out, precision=prec)
+            elif step == "residual":
+                prob.level_residual(0, ud, fd, out, precision=prec)
+            else:
+                prob.level_jacobi(0, ud, fd, out, precision=prec)
+            got = out.to("cpu", dtype=torch.float64).numpy()
+            err = np.abs(got - ref[step]).max() / np.abs(ref[step]).max()
+            print(f"[gpu]   {prec} {step}: max rel error {err:.2e}", flush=True)
+            assert err <= tol, (prec, step)
+    prob.close()
+
+
+def test_config2_solves_full_size(emg, ctx):
+    spec = synth.polycrystal_3d(n=129, grains=16, seed=2002)
+    res = check_solves(emg, ctx, spec, "config 2 (129^3 polycrystal)")
+    assert res["mixed"][0]["cycles"] == res["fp64"][0]["cycles"]
+
+
+def test_config3_solves_full_size(emg, ctx):
+    """257^3, 64 grains, stiff eigenstrained sphere: FP32 V-cycles inside
+    FP64 refinement against plain FP64, both checked by the oracle."""
+    print("[gpu] config 3: generating the 257^3 polycrystal", flush=True)
+    spec = synth.polycrystal_3d(n=257, grains=64, seed=2003, inclusion=(3.0, 2e-3))
+    check_solves(emg, ctx, spec, "config 3 (257^3 polycrystal + sphere)")
+
+
+def test_config4_amr_full_size(emg, ctx):
+    """Penny crack, 65^3 base, three levels: the GPU composite solution
+    satisfies the oracle's composite system to 1.2e-10."""
+    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.05)
+    print(f"[gpu] config 4: boxes={ap.boxes}", flush=True)
+    comp = amr.from_problem(ap)
+    prob = emg.Problem.from_amr(ctx, ap)
+    st = prob.solve(rtol=1e-10, max_cycles=400)
+    assert st["converged"]
+    u = [prob.displacement()] + [prob.amr_displacement(k) for k in range(1, len(ap.boxes) + 1)]
+    r0 = comp.norm(comp.residual(comp.initial()))
+    rel = comp.norm(comp.residual(u)) / r0
+    print(f"[gpu]   cycles={st['cycles']} oracle composite rel residual={rel:.2e}", flush=True)
+    assert rel <= 1.2e-10
+    prob.close()
