@@ -17,7 +17,13 @@ reported under "mixed".
 Roofline: the dominant kernel is the finest-level FP64 Jacobi sweep; its
 average duration is measured with HIP events on the problem's stream
 (emg_kernel_time) right after the timed steps; its algorithmic bytes are
-240 B per node (read u 3x8, C 21x8, f 3x8; write u 3x8).
+240 B per node (read u 3x8, C 21x8, f 3x8; write u 3x8).  `traffic` is the
+HBM bytes per launch from the committed rocprofv3 counter summary, reported
+only while the kernel sources are the ones the counters were taken on.
+
+smoothing: the same solve with 4 pre- and 4 post-sweeps per level (the paper
+smooths with eight Jacobi iterations per level and cycle), reported beside
+the V(2,2) headline.
 
 serving: a stream of 512 independent solve requests (3D spherical
 inclusions and 8-32-grain polycrystals, 33^3 to 129^3 nodes, log-uniform
@@ -56,10 +62,32 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512, help="served stream length (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=16, help="concurrent requests on the GPU")
+    ap.add_argument("--serve-nu", type=int, default=2, help="pre/post Jacobi sweeps per level of the served solves")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
                          "(used for hardware-counter runs)")
     return ap.parse_args()
+
+
+def sweep_traffic():
+    """HBM bytes per launch of the finest-level FP64 sweep from the committed
+    rocprofv3 counter summary (FETCH_SIZE/WRITE_SIZE scaled by a 512 MiB copy),
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "jacobi_sweep_polycrystal129_counters.md")
+    h = hashlib.sha256()
+    for f in ("emg_device.hpp", "emg_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2001_04789_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    if os.path.exists(prof):
+        for line in open(prof):
+            k, _, v = line.strip().partition(": ")
+            if k in ("sources_sha256", "fp64_sweep_traffic_bytes"):
+                vals[k] = v
+    if vals.get("sources_sha256") != h.hexdigest() or "fp64_sweep_traffic_bytes" not in vals:
+        return None
+    return int(vals["fp64_sweep_traffic_bytes"])
 
 
 def cpu_baseline(spec, gpu_cycles, ncycles):
@@ -108,7 +136,8 @@ def serve(emg, torch, ctx, args):
 
     outs = [out_for(pool[(r.kind, r.n, r.variant)][0]) for r in trace]
     torch.cuda.synchronize()
-    srv = emg.Server(ctx, max_slots=args.serve_slots, rtol=1e-10, max_cycles=400, precision="mixed")
+    srv = emg.Server(ctx, max_slots=args.serve_slots, rtol=1e-10, max_cycles=400, precision="mixed",
+                     nu1=args.serve_nu, nu2=args.serve_nu)
     # warm-up: one request per pooled input, so hierarchies and graphs are resident
     warm = [srv.submit(d, out=out_for(d)) for d, _ in pool.values()]
     for t in warm:
@@ -128,7 +157,7 @@ def serve(emg, torch, ctx, args):
     span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
     dofs = sum(pool[(r.kind, r.n, r.variant)][1] for r in trace)
     return {"requests": len(trace), "rate_req_per_s": args.serve_rate, "slots": args.serve_slots,
-            "precision": "mixed", "failed": len(bad),
+            "precision": "mixed", "smoothing": f"V({args.serve_nu},{args.serve_nu})", "failed": len(bad),
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
             "mean_ms": 1e3 * float(lat.mean()), "queue_p50_ms": 1e3 * float(np.percentile(qwait, 50)),
             "prep_mean_ms": 1e3 * float(prep.mean()),
@@ -222,7 +251,7 @@ def main():
                  "solve_ms": 1e3 * float(np.mean([s["solve_seconds"] for s in st64])),
                  "setup_ms": 1e3 * float(np.mean([s["setup_seconds"] for s in st64]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(),
                      "kernel": "k_stencil<3,ANISO,double,JACOBI> finest level",
                      "avg_ms": ms_sweep, "bytes_per_launch": bytes_per_launch},
     }
@@ -239,6 +268,16 @@ def main():
             "fp32_sweep_ms": ms_sweep32,
             "fp32_sweep_gbs": 120 * nodes / (ms_sweep32 * 1e-3) / 1e9,
         }
+    # V(4,4): same workload, more smoothing per level
+    alt = {}
+    for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+        sts = []
+        for _ in range(2):
+            prob.set_moduli(C_d)
+            sts.append(prob.solve(rtol=1e-10, max_cycles=400, precision=prec, nu1=4, nu2=4))
+        alt[prec] = {"cycles": sts[-1]["cycles"], "solve_ms": 1e3 * sts[-1]["solve_seconds"],
+                     "solve_only_dofs_per_s": dofs / sts[-1]["solve_seconds"]}
+    out["smoothing_v44"] = alt
     prob.close()
     del C_d, faces_d, sigma_d
     if args.serve_requests > 0:
