@@ -111,7 +111,8 @@ emg_status emg_ctx_destroy(emg_ctx *ctx);
  * node count >= 8; the coarsest level is solved exactly in FP64.
  * EMG_EINVAL for: dim not 2/3, an axis with fewer than 5 nodes, mismatched
  * periodic faces, no Dirichlet face (rigid-body null space), fewer than two
- * levels, or a coarsest level with more than 1536 unknowns.  The device
+ * levels, a coarsest level with more than 1536 unknowns, or 2^29 or more
+ * stored nodes (the interior kernels use 32-bit node offsets).  The device
  * footprint is allocated here (EMG_ENOMEM if it exceeds the budget). */
 emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem **out);
 emg_status emg_problem_destroy(emg_problem *p);
@@ -231,8 +232,9 @@ emg_status emg_server_destroy(emg_server *s);
  * coarse nodes).  It must lie inside level k-1's box (the base grid for
  * k = 1) with at least two coarse cells to spare, off the domain boundary and
  * off periodic axes.  Level-k fields are laid out over the box grown by one
- * ghost node per side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x].
- * Composite system solved by emg_solve (FP64 only):
+ * ghost node per side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x]
+ * (EMG_EINVAL for bounds that break these rules or a box of 2^29 or more
+ * stored nodes).  Composite system solved by emg_solve (FP64 only):
  *   - unknowns: valid nodes of every box plus the coarser nodes not covered by
  *     the next finer box; a covered coarse node takes the coincident fine
  *     value (App. A, phi_c2 = phi_f4);

@@ -47,6 +47,9 @@ emg_status fail(emg_status s, const std::string &msg) {
   } while (0)
 
 constexpr int kMaxBottom = 1536;
+// Stored nodes per level (box) at most: the interior kernels index nodes and
+// form byte offsets of 8-byte values in 32 bits.
+constexpr long long kMaxNodes = 1LL << 29;
 
 template <class F>
 void dispatch(int D, int K, F &&f) {
@@ -1137,6 +1140,7 @@ emg_status level_chain(const emg_domain *dom, std::vector<Geom> &gs) {
   }
   if (!any_dir) return fail(EMG_EINVAL, "at least one Dirichlet face is required (rigid-body null space)");
   g.N = (long long)g.m[0] * g.m[1] * g.m[2];
+  if (g.N >= kMaxNodes) return fail(EMG_EINVAL, "grid too large (2^29 stored nodes per level at most)");
   g.SC = moduli_stride(g.N);
   gs.assign(1, g);
   while (can_coarsen(gs.back())) gs.push_back(coarse_of(gs.back()));
@@ -2148,6 +2152,7 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
     }
   }
   F.g.N = (long long)F.g.m[0] * F.g.m[1] * F.g.m[2];
+  if (F.g.N >= kMaxNodes) return fail(EMG_EINVAL, "box too large (2^29 stored nodes at most)");
   F.g.SC = moduli_stride(F.g.N);
   const size_t nd = (size_t)p->D * F.g.N;
   TRY(dalloc(p, &F.C, (size_t)p->nc * F.g.SC));

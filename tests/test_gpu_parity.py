@@ -238,6 +238,10 @@ def test_error_paths(emg, ctx):
     st = prob.solve(raise_on_error=False)
     assert st["status"] in (emg.EMG_EDIVERGED, emg.EMG_EINVAL)
     prob.close()
+    # more stored nodes than the 32-bit interior indexing allows: rejected before any allocation
+    with pytest.raises(emg.EmgError) as ei:
+        emg.Problem(ctx, 3, (1025, 1025, 1025), (0, 0, 0), (1, 1, 1), ("dirichlet",) * 6, "iso")
+    assert ei.value.status == emg.EMG_EINVAL
     small = emg.Context(0, hbm_budget_bytes=1 << 16)
     with pytest.raises(emg.EmgError) as ei:
         emg.Problem(small, 2, spec.n, spec.lo, spec.hi, spec.bc, "iso")

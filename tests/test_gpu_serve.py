@@ -103,3 +103,30 @@ def test_request_larger_than_budget_fails_cleanly(emg):
     assert info2["status"] in (emg.EMG_OK, emg.EMG_ENOMEM)
     srv.close()
     tiny.close()
+
+
+def test_served_trace_matches_solo_and_oracle(emg, ctx):
+    """A stretch of the served stream (96 requests of the Poisson trace, all
+    sizes and both problem types, submitted at once so they queue and join
+    running batches): every result equals, bit for bit, the solo solve of
+    its input, and one sampled input is checked against the oracle."""
+    import oracle
+    trace = synth.serving_trace(count=96, seed=2005)
+    keys = sorted({(r.kind, r.n, r.variant) for r in trace})
+    print(f"[gpu] served trace: {len(trace)} requests over {len(keys)} inputs", flush=True)
+    specs = {k: synth.serving_problem(*k) for k in keys}
+    opts = dict(rtol=1e-10, max_cycles=400, precision="mixed")
+    solo = {k: u for k, (_, u) in zip(keys, _solo(emg, ctx, [specs[k] for k in keys], **opts))}
+    srv = emg.Server(ctx, max_slots=16, **opts)
+    tickets = [(srv.submit(specs[(r.kind, r.n, r.variant)]), (r.kind, r.n, r.variant)) for r in trace]
+    for t, k in tickets:
+        got, info = srv.wait(t)
+        assert info["status"] == emg.EMG_OK and info["converged"], (k, info)
+        assert np.array_equal(got.reshape(solo[k].shape), solo[k]), k
+    srv.close()
+    small = [k for k in keys if k[1] == 33]
+    k = small[0]
+    ref = oracle.solve(specs[k], tol=1e-13, max_cycles=400)
+    err = float(np.linalg.norm(solo[k] - ref.u) / np.linalg.norm(ref.u))
+    print(f"[gpu] served {k} vs oracle: rel error {err:.2e}", flush=True)
+    assert err <= 1e-8
