@@ -268,6 +268,22 @@ def main():
             "fp32_sweep_ms": ms_sweep32,
             "fp32_sweep_gbs": 120 * nodes / (ms_sweep32 * 1e-3) / 1e9,
         }
+    # the same FP64 step with the inputs handed over from host memory (PCIe-inclusive)
+    def host_step():
+        prob.set_moduli(spec.C)
+        prob.set_eigenstrain(None)
+        for f in (4, 5):
+            prob.set_face(f, spec.face.get(f))
+        st = prob.solve(rtol=1e-10, max_cycles=400, precision="fp64")
+        prob.stress(out=sigma_d)
+        return st
+    host_step()
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(2):
+        host_step()
+    torch.cuda.synchronize()
+    out["fp64"]["host_inputs_ms_per_step"] = 1e3 * (time.perf_counter() - th) / 2
     # V(4,4): same workload, more smoothing per level
     alt = {}
     for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
