@@ -7,11 +7,12 @@ imports this package.  Its inputs come from ``synth`` (problem data only).
 
 What it computes, in the paper's order (arXiv 2001.04789):
   * the discrete operator D_H, its right-hand side -(D(0) + b) with the
-    boundary operators of Sec. 2.1 (Dirichlet u0, traction t0), the stress
+    boundary operators of Sec. 2.1 (Dirichlet u0, traction t0, Neumann
+    normal derivative du0), the stress
     sigma = C(grad u - eps0), the Jacobi relaxation of Sec. 3.1 and the
     transfers of Sec. 3.2 -- in ``emg_oracle.c``, one plain loop each;
   * the multigrid hierarchy (levels -1, -2, ... of Fig. "hierarchy", Sec. 3.1)
-    and the correction-scheme V-cycle, written here step by step;
+    and the correction-scheme V- and F-cycles, written here step by step;
   * the exact solution of the discrete system on tiny grids, by a dense
     solve of the matrix assembled column by column from unit vectors.
 
@@ -33,10 +34,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "emg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-DIRICHLET, TRACTION, PERIODIC = 0, 1, 2
+DIRICHLET, TRACTION, PERIODIC, NEUMANN = 0, 1, 2, 3
 ISO, ANISO = 0, 1
-ROW_INTERIOR, ROW_TRACTION, ROW_DIRICHLET = 0, 1, 2
-_BC = {"dirichlet": DIRICHLET, "traction": TRACTION, "periodic": PERIODIC}
+ROW_INTERIOR, ROW_TRACTION, ROW_DIRICHLET, ROW_NEUMANN = 0, 1, 2, 3
+_BC = {"dirichlet": DIRICHLET, "traction": TRACTION, "periodic": PERIODIC, "neumann": NEUMANN}
 
 
 def build(force: bool = False) -> str:
@@ -271,11 +272,12 @@ class Hierarchy:
         return scipy.linalg.lu_solve(self.bottom, f.ravel()).reshape(gb.shape(gb.dim))
 
 
-def vcycle(H: Hierarchy, ell: int, x, f, nu1=2, nu2=2, omega=2.0 / 3.0):
+def vcycle(H: Hierarchy, ell: int, x, f, nu1=2, nu2=2, omega=2.0 / 3.0, counts=None):
     """One correction-scheme V-cycle on level ell (Sec. 3.1): nu1 damped
     Jacobi sweeps, residual, full-weighting restriction, recursive solve of
     the coarse correction from zero, interpolation, nu2 sweeps.  The coarsest
-    level is solved exactly.  Returns the new x."""
+    level is solved exactly.  Returns the new x.  `counts[l]`, if given,
+    gathers the Jacobi sweeps run on each level."""
     g, C = H.grids[ell], H.C[ell]
     if ell == len(H.grids) - 1:
         return H.bottom_solve(f)
@@ -284,10 +286,37 @@ def vcycle(H: Hierarchy, ell: int, x, f, nu1=2, nu2=2, omega=2.0 / 3.0):
     r = residual(g, C, x, f)
     gc = H.grids[ell + 1]
     fc = restrict(g, gc, r)
-    ec = vcycle(H, ell + 1, np.zeros(gc.shape(g.dim)), fc, nu1, nu2, omega)
+    ec = vcycle(H, ell + 1, np.zeros(gc.shape(g.dim)), fc, nu1, nu2, omega, counts)
     x = prolong_add(gc, g, ec, x)
     for _ in range(nu2):
         x = jacobi(g, C, x, f, omega)
+    if counts is not None:
+        counts[ell] += nu1 + nu2
+    return x
+
+
+def fcycle(H: Hierarchy, ell: int, x, f, nu1=2, nu2=2, omega=2.0 / 3.0, counts=None):
+    """One F-cycle on level ell (Sec. 3.1 names F-cycles as the solver's
+    cycle; the recursive form of the multigrid literature it cites): nu1
+    sweeps, residual, restriction, then on the coarse level an F-cycle from
+    zero followed by a V-cycle from that result, interpolation, nu2 sweeps.
+    The coarsest level is solved exactly.  `counts[l]`, if given, gathers
+    the Jacobi sweeps run on each level."""
+    g, C = H.grids[ell], H.C[ell]
+    if ell == len(H.grids) - 1:
+        return H.bottom_solve(f)
+    for _ in range(nu1):
+        x = jacobi(g, C, x, f, omega)
+    r = residual(g, C, x, f)
+    gc = H.grids[ell + 1]
+    fc = restrict(g, gc, r)
+    ec = fcycle(H, ell + 1, np.zeros(gc.shape(g.dim)), fc, nu1, nu2, omega, counts)
+    ec = vcycle(H, ell + 1, ec, fc, nu1, nu2, omega, counts)
+    x = prolong_add(gc, g, ec, x)
+    for _ in range(nu2):
+        x = jacobi(g, C, x, f, omega)
+    if counts is not None:
+        counts[ell] += nu1 + nu2
     return x
 
 
@@ -302,11 +331,13 @@ class SolveResult:
 
 
 def solve(prob, tol: float = 1e-13, max_cycles: int = 200, nu1: int = 2, nu2: int = 2,
-          omega: float = 2.0 / 3.0, H: Optional[Hierarchy] = None, stagnation: float = 0.95) -> SolveResult:
-    """V-cycles from the Dirichlet lift until the relative residual (2-norm
-    over non-Dirichlet rows, relative to the lift's residual) is <= tol, or
-    until it stops decreasing (ratio > stagnation over 3 cycles once below
-    1e-11, i.e. at rounding level)."""
+          omega: float = 2.0 / 3.0, H: Optional[Hierarchy] = None, stagnation: float = 0.95,
+          cycle: str = "V") -> SolveResult:
+    """V-cycles (or F-cycles, cycle="F") from the Dirichlet lift until the
+    relative residual (2-norm over non-Dirichlet rows, relative to the lift's
+    residual) is <= tol, or until it stops decreasing (ratio > stagnation
+    over 3 cycles once below 1e-11, i.e. at rounding level)."""
+    step = {"V": vcycle, "F": fcycle}[cycle]
     g = Grid.of(prob)
     t0 = time.perf_counter()
     if H is None:
@@ -321,7 +352,7 @@ def solve(prob, tol: float = 1e-13, max_cycles: int = 200, nu1: int = 2, nu2: in
     cycles = 0
     converged = False
     while cycles < max_cycles:
-        u = vcycle(H, 0, u, f, nu1, nu2, omega)
+        u = step(H, 0, u, f, nu1, nu2, omega)
         cycles += 1
         rel = norm(g, residual(g, H.C[0], u, f)) / r0
         hist.append(rel)

@@ -31,7 +31,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import (DIRICHLET, Grid, Hierarchy, ROW_DIRICHLET, apply, dirichlet_mask, jacobi, norm, residual, restrict,
-               rhs, row_class, vcycle)
+               rhs, row_class, vcycle, fcycle)
 
 
 class FineLevel:
@@ -265,13 +265,14 @@ class Composite:
         return self.sync(unpack(x, zero))
 
     # ---- composite correction cycle ----
-    def cycle(self, u: List[np.ndarray], nu1=2, nu2=2, omega=2.0 / 3.0) -> List[np.ndarray]:
+    def cycle(self, u: List[np.ndarray], nu1=2, nu2=2, omega=2.0 / 3.0, base="V") -> List[np.ndarray]:
         """One composite correction cycle (Sec. 3.2): fine corrections relaxed
         with zero ghosts (the coarse/fine boundary acting as Dirichlet), fine
         residual restricted onto the covered coarse nodes, coarse residual at
-        uncovered nodes updated for the injected fine correction, V-cycle on
-        the base grid, then interpolation back to the fine nodes and ghosts
-        and relaxation with the interpolated ghosts as Dirichlet values."""
+        uncovered nodes updated for the injected fine correction, V-cycle (or
+        F-cycle, base="F") on the base grid, then interpolation back to the
+        fine nodes and ghosts and relaxation with the interpolated ghosts as
+        Dirichlet values."""
         L = len(self.fines)
         u = self.sync(u)
         r = self.residual(u)
@@ -296,8 +297,9 @@ class Composite:
             rc = np.where(masks[k - 1], rr[k - 1] - Ainj, 0.0)
             rc[cs] = self._restrict_valid(fl, rk)
             rr[k - 1] = rc
-        # base grid: one V-cycle for the correction
-        e[0] = vcycle(self.H, 0, np.zeros(self.g0.shape(self.dim)), rr[0], nu1, nu2, omega)
+        # base grid: one V- (or F-) cycle for the correction
+        step = {"V": vcycle, "F": fcycle}[base]
+        e[0] = step(self.H, 0, np.zeros(self.g0.shape(self.dim)), rr[0], nu1, nu2, omega)
         for k in range(1, L + 1):
             fl = self.fines[k - 1]
             g, C = fl.grid, fl.C
@@ -343,12 +345,12 @@ class Composite:
         _, fs = covered_slices(fl, (0, 0, 0))
         return num[fs] / den[fs[1:]]
 
-    def solve(self, tol=1e-12, max_cycles=300, nu1=2, nu2=2, omega=2.0 / 3.0):
+    def solve(self, tol=1e-12, max_cycles=300, nu1=2, nu2=2, omega=2.0 / 3.0, base="V"):
         u = self.initial()
         r0 = self.norm(self.residual(u))
         hist = [1.0]
         for c in range(max_cycles):
-            u = self.cycle(u, nu1, nu2, omega)
+            u = self.cycle(u, nu1, nu2, omega, base)
             rel = self.norm(self.residual(u)) / r0
             hist.append(rel)
             if rel <= tol:

@@ -21,6 +21,8 @@
  *   traction rows   sum over the traction faces f of the node of
  *                   sum_jkl C_ijkl dhat_l(u_k) n^f_j
  *   Dirichlet rows  u_i
+ *   Neumann rows    sum over the Neumann faces f of the node of
+ *                   n^f_a dhat_a(u_i), a the normal axis of f (eq. elastic_b3)
  * d_j is the central difference, d_jj the 3-point second difference, d_jl
  * (j != l) the 4-corner mixed difference, dhat_l the 3-point one-sided
  * difference pointing into the domain along an axis on whose end the node
@@ -33,9 +35,9 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORA_DIRICHLET = 0, ORA_TRACTION = 1, ORA_PERIODIC = 2 };
+enum { ORA_DIRICHLET = 0, ORA_TRACTION = 1, ORA_PERIODIC = 2, ORA_NEUMANN = 3 };
 enum { ORA_ISO = 0, ORA_ANISO = 1 };
-enum { ROW_INTERIOR = 0, ROW_TRACTION = 1, ROW_DIRICHLET = 2 };
+enum { ROW_INTERIOR = 0, ROW_TRACTION = 1, ROW_DIRICHLET = 2, ROW_NEUMANN = 3 };
 
 typedef struct {
   int dim;       /* 2 or 3 */
@@ -109,14 +111,22 @@ static double sym2(const ora_grid *g, const double *E, long n, int k, int l) {
 static int at_low(const ora_grid *g, const int p[3], int a) { return !periodic(g, a) && p[a] == 0; }
 static int at_high(const ora_grid *g, const int p[3], int a) { return !periodic(g, a) && p[a] == g->m[a] - 1; }
 
-/* Row class of node p and, for traction rows, the faces it lies on. */
+/* 1 if p lies on face f (2a = low end of axis a, 2a+1 = high end) */
+static int on_face(const ora_grid *g, const int p[3], int f) {
+  return (f % 2 == 0) ? at_low(g, p, f / 2) : at_high(g, p, f / 2);
+}
+
+/* Row class of node p: a Dirichlet face of the node decides first, then a
+ * Neumann face, then a traction face; nodes on no face are interior. */
 static int row_class(const ora_grid *g, const int p[3]) {
-  int on_face = 0;
-  for (int a = 0; a < g->dim; a++) {
-    if (at_low(g, p, a)) { on_face = 1; if (g->bc[2 * a] == ORA_DIRICHLET) return ROW_DIRICHLET; }
-    if (at_high(g, p, a)) { on_face = 1; if (g->bc[2 * a + 1] == ORA_DIRICHLET) return ROW_DIRICHLET; }
+  int face = 0, neu = 0;
+  for (int f = 0; f < 2 * g->dim; f++) {
+    if (!on_face(g, p, f)) continue;
+    if (g->bc[f] == ORA_DIRICHLET) return ROW_DIRICHLET;
+    face = 1;
+    if (g->bc[f] == ORA_NEUMANN) neu = 1;
   }
-  return on_face ? ROW_TRACTION : ROW_INTERIOR;
+  return neu ? ROW_NEUMANN : (face ? ROW_TRACTION : ROW_INTERIOR);
 }
 
 /* ---- finite differences of a stored scalar field f (component already offset) ---- */
@@ -207,6 +217,13 @@ static double row_value(const ora_grid *g, const double *C, const double *u, lon
         }
     return acc;
   }
+  if (cls == ROW_NEUMANN) {
+    /* normal derivative of u_i summed over the node's Neumann faces */
+    for (int f = 0; f < 2 * d; f++)
+      if (on_face(g, p, f) && g->bc[f] == ORA_NEUMANN)
+        acc += normal(g, p, f / 2) * dhat(g, u + (long)i * N, p, f / 2);
+    return acc;
+  }
   /* traction row: sum over the faces the node lies on */
   for (int a = 0; a < d; a++) {
     double na = normal(g, p, a);
@@ -234,6 +251,11 @@ static double diag_value(const ora_grid *g, const double *C, long n, int i) {
   double acc = 0.0;
   if (cls == ROW_INTERIOR) {
     for (int j = 0; j < g->dim; j++) acc += Cijkl(g, C, n, i, j, i, j) * (-2.0 / (g->h[j] * g->h[j]));
+    return acc;
+  }
+  if (cls == ROW_NEUMANN) {
+    for (int f = 0; f < 2 * g->dim; f++)
+      if (on_face(g, p, f) && g->bc[f] == ORA_NEUMANN) acc += normal(g, p, f / 2) * dhat_centre(g, p, f / 2);
     return acc;
   }
   for (int a = 0; a < g->dim; a++) {
@@ -264,7 +286,8 @@ void ora_row_class(const ora_grid *g, int *out) {
  * eps0: tensor components in Voigt order (d(d+1)/2 per node) or NULL;
  * b: d per node or NULL; face[f]: d components per node of face f, stored
  * [comp][z][y][x] with the face's normal axis of extent 1, or NULL (= 0).
- * For Dirichlet faces face[f] holds u0, for traction faces t0.           */
+ * For Dirichlet faces face[f] holds u0, for traction faces t0, for
+ * Neumann faces the prescribed normal derivative du0.                     */
 static double face_value(const ora_grid *g, const double *F, const int p[3], int a, int i) {
   if (!F) return 0.0;
   int q[3] = {p[0], p[1], p[2]};
@@ -293,6 +316,9 @@ void ora_rhs(const ora_grid *g, const double *C, const double *eps0, const doubl
           int on = (f % 2 == 0) ? at_low(g, p, a) : at_high(g, p, a);
           if (on && g->bc[f] == ORA_DIRICHLET) { acc = face_value(g, face[f], p, a, i); break; }
         }
+      } else if (cls == ROW_NEUMANN) {
+        for (int f = 0; f < 2 * d; f++)
+          if (on_face(g, p, f) && g->bc[f] == ORA_NEUMANN) acc += face_value(g, face[f], p, f / 2, i);
       } else if (cls == ROW_INTERIOR) {
         if (b) acc -= b[(long)i * N + n];
         if (eps0)

@@ -19,7 +19,8 @@ Layout conventions (shared input format):
   * Face data (face ``2*axis + side``): ``d`` components over the face's
     nodes, shaped like a field with the face's normal axis of extent 1;
     prescribed displacement on Dirichlet faces, prescribed traction on
-    traction faces.
+    traction faces, prescribed normal derivative of the displacement on
+    Neumann faces.
 """
 from __future__ import annotations
 
@@ -33,6 +34,7 @@ import numpy as np
 DIRICHLET = "dirichlet"
 TRACTION = "traction"
 PERIODIC = "periodic"
+NEUMANN = "neumann"
 
 
 @dataclasses.dataclass

@@ -149,14 +149,15 @@ def _smooth_composite_2d(levels=1):
     return amr.Composite(p, fines)
 
 
-@pytest.mark.parametrize("levels", [1, 2])
-def test_composite_cycle_reaches_dense_solution(levels):
+@pytest.mark.parametrize("levels,base", [(1, "V"), (2, "V"), (2, "F")])
+def test_composite_cycle_reaches_dense_solution(levels, base):
     """The composite cycle's fixed point is the dense solution of the
-    composite system (variable moduli, traction faces, 2 and 3 levels)."""
+    composite system (variable moduli, traction faces, 2 and 3 levels; base
+    grid corrected by a V- or an F-cycle)."""
     comp = _smooth_composite_2d(levels)
     ud = comp.dense_solve()
     assert comp.norm(comp.residual(ud)) <= 1e-10 * comp.norm(comp.residual(comp.initial()))
-    u, hist = comp.solve(tol=1e-13, max_cycles=200)
+    u, hist = comp.solve(tol=1e-13, max_cycles=200, base=base)
     for a, b in zip(u, ud):
         assert np.abs(a - b).max() <= 1e-10 * np.abs(ud[0]).max()
 

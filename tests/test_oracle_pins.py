@@ -110,6 +110,9 @@ def polynomial_problem(dim, bc, seed, n=(7, 6, 5), lo=(0.1, -0.4, 0.2), hi=(1.3,
             t = [sum(_eval(sig[i][j], x, y, z, shp)[sl] * (nsign if j == a else 0.0) for j in range(d))
                  for i in range(d)]
             p.face[f] = np.stack(t)
+        elif bc[f] == synth.NEUMANN:   # du_i/dx_j n_j (eq. elastic_b3)
+            nsign = -1.0 if f % 2 == 0 else 1.0
+            p.face[f] = np.stack([nsign * _eval(sp.diff(u[i], X[a]), x, y, z, shp)[sl] for i in range(d)])
     return p, u_nodal, sig_nodal
 
 
@@ -118,10 +121,14 @@ BC2 = ("traction", "traction", "dirichlet", "traction", "periodic", "periodic")
 
 
 @pytest.mark.parametrize("dim,bc,seed", [(3, BC3, 1), (2, BC2, 2),
-                                         (3, ("traction", "dirichlet", "dirichlet", "traction", "traction", "traction"), 3)])
+                                         (3, ("traction", "dirichlet", "dirichlet", "traction", "traction", "traction"), 3),
+                                         (3, ("neumann", "traction", "dirichlet", "neumann", "traction", "neumann"), 4),
+                                         (2, ("neumann", "neumann", "dirichlet", "traction", "periodic", "periodic"), 5),
+                                         (3, ("dirichlet", "neumann", "neumann", "neumann", "traction", "neumann"), 6)])
 def test_polynomial_exactness(dim, bc, seed):
-    """P1: on Q2 fields every row (interior, traction incl. edges and
-    corners, Dirichlet) equals the analytic operator at the node, so
+    """P1: on Q2 fields every row (interior, traction and Neumann incl.
+    edges and corners, Dirichlet) equals the analytic operator or boundary
+    condition at the node, so
     rhs - D_H(u) vanishes to rounding; the dense solve returns the nodal u;
     the stress equals the analytic stress at every node."""
     p, u, sig = polynomial_problem(dim, bc, seed)
@@ -291,14 +298,16 @@ def test_diag_is_operator_diagonal():
     applying it to unit vectors (interior, faces, edges, corners)."""
     for dim, bc in [(3, ("traction", "traction", "traction", "traction", "dirichlet", "traction")),
                     (2, ("traction", "traction", "dirichlet", "traction", "periodic", "periodic")),
-                    (3, ("periodic", "periodic", "traction", "traction", "dirichlet", "dirichlet"))]:
+                    (3, ("periodic", "periodic", "traction", "traction", "dirichlet", "dirichlet")),
+                    (3, ("neumann", "traction", "neumann", "neumann", "dirichlet", "traction")),
+                    (2, ("neumann", "traction", "dirichlet", "neumann", "periodic", "periodic"))]:
         p = synth.random_problem(dim, (8, 6, 5)[:dim], bc, "aniso", seed=12, smooth=False)
         g = _grid(p)
         A = oracle.dense_matrix(g, p.C)
         np.testing.assert_allclose(oracle.diag(g, p.C).ravel(), np.diag(A), rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("case", ["2d", "3d", "3d_periodic", "2d_iso_traction"])
+@pytest.mark.parametrize("case", ["2d", "3d", "3d_periodic", "2d_iso_traction", "3d_neumann", "2d_neumann"])
 def test_vcycle_reaches_dense_solution(case):
     """P7: the V-cycle's fixed point is the dense solution; Jacobi leaves the
     exact solution unchanged."""
@@ -311,9 +320,15 @@ def test_vcycle_reaches_dense_solution(case):
     elif case == "3d_periodic":
         p = synth.random_problem(3, (9, 9, 9), ("periodic", "periodic", "periodic", "periodic", "dirichlet", "dirichlet"),
                                  "aniso", seed=43)
-    else:
+    elif case == "2d_iso_traction":
         p = synth.random_problem(2, (17, 17), ("dirichlet", "traction", "traction", "traction", "periodic", "periodic"),
                                  "iso", seed=44, with_body=True)
+    elif case == "3d_neumann":
+        p = synth.random_problem(3, (9, 9, 9), ("neumann", "traction", "periodic", "periodic", "dirichlet", "neumann"),
+                                 "aniso", seed=45)
+    else:
+        p = synth.random_problem(2, (17, 17), ("neumann", "neumann", "dirichlet", "traction", "periodic", "periodic"),
+                                 "iso", seed=46, with_body=True)
     ud = oracle.dense_solve(p)
     res = oracle.solve(p, tol=1e-14, max_cycles=300)
     assert np.abs(res.u - ud).max() <= 1e-11 * np.abs(ud).max()
@@ -428,3 +443,101 @@ def test_eshelby_disc_closed_form():
         errs.append(np.abs(res.u - uex)[far].max() / np.abs(uex).max())
     assert errs[1] < 0.6 * errs[0]
     assert errs[1] < 0.03
+
+
+# --------------------------------------------------------------------------
+# F-cycle (Sec. 3.1: the paper's solver runs F-cycles)
+# --------------------------------------------------------------------------
+
+def _tiny_3level():
+    """2D problem whose hierarchy has exactly three levels (17 -> 9 -> 5)."""
+    p = synth.random_problem(2, (17, 17), ("neumann", "traction", "dirichlet", "traction", "periodic", "periodic"),
+                             "aniso", seed=61)
+    H = oracle.Hierarchy(_grid(p), p.C)
+    assert len(H.grids) == 3
+    return p, H
+
+
+def _dense_of(fn, n_in, shape_in):
+    """Matrix of a linear map given as a function of an array, by unit vectors."""
+    cols = []
+    e = np.zeros(n_in)
+    for q in range(n_in):
+        e[q] = 1.0
+        cols.append(np.asarray(fn(e.reshape(shape_in))).ravel())
+        e[q] = 0.0
+    return np.array(cols).T
+
+
+def test_fcycle_equals_vcycle_on_two_levels():
+    """With two levels the coarse F-cycle is the exact coarse solve and the
+    V-cycle after it solves the same coarse system again, so an F-cycle is a
+    V-cycle bit for bit."""
+    p = synth.random_problem(2, (9, 9), ("traction", "traction", "dirichlet", "neumann", "periodic", "periodic"),
+                             "iso", seed=62)
+    g = _grid(p)
+    H = oracle.Hierarchy(g, p.C)
+    assert len(H.grids) == 2
+    f = oracle.rhs(g, p.C, p.eps0, p.b, p.face)
+    x = np.random.default_rng(3).standard_normal(g.shape(2))
+    np.testing.assert_array_equal(oracle.fcycle(H, 0, x, f), oracle.vcycle(H, 0, x, f))
+
+
+def test_fcycle_sweep_counts():
+    """Level k (0 = finest, above the bottom) is visited k + 1 times per
+    F-cycle (the F-cycle on level l adds one visit of level l to the visits
+    of F and V on level l + 1); each visit runs nu1 + nu2 sweeps.  A V-cycle
+    visits each level once."""
+    p = synth.random_problem(2, (65, 65), ("dirichlet", "traction", "traction", "traction", "periodic", "periodic"),
+                             "iso", seed=63)
+    g = _grid(p)
+    H = oracle.Hierarchy(g, p.C)
+    L = len(H.grids)
+    assert L >= 4
+    f = oracle.rhs(g, p.C, p.eps0, p.b, p.face)
+    for nu1, nu2 in ((2, 2), (1, 3)):
+        cf, cv = [0] * L, [0] * L
+        oracle.fcycle(H, 0, np.zeros(g.shape(2)), f, nu1, nu2, counts=cf)
+        oracle.vcycle(H, 0, np.zeros(g.shape(2)), f, nu1, nu2, counts=cv)
+        assert cf[:-1] == [(k + 1) * (nu1 + nu2) for k in range(L - 1)]
+        assert cv[:-1] == [nu1 + nu2] * (L - 1)
+
+
+def test_fcycle_without_smoothing_matches_matrix_form():
+    """With no smoothing, a 3-level F-cycle from zero is x = P01 (B + B (I -
+    A1 B)) R10 f with B = P12 A2^-1 R21: the coarse F-cycle gives B f1 and
+    the V-cycle from it adds the coarse correction of its residual.  The
+    transfer and operator matrices are read off the oracle's primitives by
+    unit vectors; the composition is the textbook one."""
+    p, H = _tiny_3level()
+    g0, g1, g2 = H.grids
+    d = 2
+    A1 = oracle.dense_matrix(g1, H.C[1])
+    A2 = oracle.dense_matrix(g2, H.C[2])
+    R10 = _dense_of(lambda r: oracle.restrict(g0, g1, r), d * g0.N, g0.shape(d))
+    R21 = _dense_of(lambda r: oracle.restrict(g1, g2, r), d * g1.N, g1.shape(d))
+    P01 = _dense_of(lambda e: oracle.prolong_add(g1, g0, e, np.zeros(g0.shape(d))), d * g1.N, g1.shape(d))
+    P12 = _dense_of(lambda e: oracle.prolong_add(g2, g1, e, np.zeros(g1.shape(d))), d * g2.N, g2.shape(d))
+    B = P12 @ np.linalg.solve(A2, R21)
+    M = P01 @ (B + B @ (np.eye(B.shape[0]) - A1 @ B)) @ R10
+    f = np.random.default_rng(5).standard_normal(d * g0.N)
+    got = oracle.fcycle(H, 0, np.zeros(g0.shape(d)), f.reshape(g0.shape(d)), 0, 0).ravel()
+    ref = M @ f
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # and the V-cycle without smoothing is P01 B R10 f
+    gotv = oracle.vcycle(H, 0, np.zeros(g0.shape(d)), f.reshape(g0.shape(d)), 0, 0).ravel()
+    refv = P01 @ B @ R10 @ f
+    assert np.abs(gotv - refv).max() <= 1e-12 * np.abs(refv).max()
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_fcycle_reaches_dense_solution(case):
+    """The F-cycle's fixed point is the dense solution."""
+    if case == "2d":
+        p, _ = _tiny_3level()
+    else:
+        p = synth.random_problem(3, (9, 9, 9), ("dirichlet", "neumann", "traction", "traction", "periodic", "periodic"),
+                                 "aniso", seed=64)
+    ud = oracle.dense_solve(p)
+    res = oracle.solve(p, tol=1e-14, max_cycles=300, cycle="F")
+    assert np.abs(res.u - ud).max() <= 1e-11 * np.abs(ud).max()
