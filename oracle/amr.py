@@ -311,7 +311,7 @@ class Composite:
             ghost[(slice(None),) + fl.valid()] = False
             ek = e[k] + np.where(ghost, 0.0, pe)
             ek = np.where(ghost, pe, ek)
-            fk = np.where(ghost, pe, r[k])
+            fk = np.where(ghost, pe, rr[k])
             for _ in range(nu2):
                 ek = jacobi(g, C, ek, fk, omega)
             e[k] = ek
