@@ -44,12 +44,15 @@ typedef enum {
   EMG_ESTATE = -6      /* call order, e.g. solve before the moduli are set */
 } emg_status;
 
-/* Face boundary types (Sec. 2.1, eqs. elastic_b1 and elastic_b2; periodic
- * faces of representative volume elements, Sec. 1).  Face f = 2*axis + side
- * (side 0 = low end, 1 = high end).  Both faces of an axis are periodic or
- * neither is.  A node on a Dirichlet face has the Dirichlet row; a node on
- * traction faces only has the sum over those faces of the traction rows. */
-typedef enum { EMG_BC_DIRICHLET = 0, EMG_BC_TRACTION = 1, EMG_BC_PERIODIC = 2 } emg_bc_type;
+/* Face boundary types (Sec. 2.1, eqs. elastic_b1, elastic_b2 and
+ * elastic_b3; periodic faces of representative volume elements, Sec. 1).
+ * Face f = 2*axis + side (side 0 = low end, 1 = high end).  Both faces of an
+ * axis are periodic or neither is.  A node on a Dirichlet face has the
+ * Dirichlet row; otherwise a node on a Neumann face has the Neumann row
+ * (normal derivative of each displacement component, 3-point one-sided,
+ * summed over its Neumann faces); otherwise a node on traction faces has the
+ * sum over those faces of the traction rows. */
+typedef enum { EMG_BC_DIRICHLET = 0, EMG_BC_TRACTION = 1, EMG_BC_PERIODIC = 2, EMG_BC_NEUMANN = 3 } emg_bc_type;
 
 /* Stored moduli per node (Sec. 2.1.1 reduced constants; Sec. 4.3 Voigt form):
  *   EMG_MOD_ISO:   2 components, lambda then mu.
@@ -59,6 +62,13 @@ typedef enum { EMG_BC_DIRICHLET = 0, EMG_BC_TRACTION = 1, EMG_BC_PERIODIC = 2 } 
 typedef enum { EMG_MOD_ISO = 0, EMG_MOD_ANISO = 1 } emg_moduli_kind;
 
 typedef enum { EMG_FP64 = 0, EMG_MIXED = 1 } emg_precision;
+
+/* Multigrid cycle (Sec. 3.1).  EMG_VCYCLE: nu1 sweeps, residual,
+ * restriction, coarse correction by one V-cycle from zero, interpolation,
+ * nu2 sweeps.  EMG_FCYCLE: the same, with the coarse correction given by an
+ * F-cycle from zero followed by a V-cycle from its result (level k below the
+ * finest is then smoothed k + 1 times per cycle). */
+typedef enum { EMG_VCYCLE = 0, EMG_FCYCLE = 1 } emg_cycle;
 
 typedef struct emg_ctx emg_ctx;
 typedef struct emg_problem emg_problem;
@@ -83,6 +93,8 @@ typedef struct {
   int check_every;   /* cycles per device-side launch between host convergence reads (default 4);
                         cycles after convergence inside a launch are skipped on the device */
   int use_graph;     /* 1 (default): replay captured HIP graphs; 0: launch kernels eagerly */
+  int cycle;         /* emg_cycle (default EMG_VCYCLE); emg_solve_batch and the server take
+                        EMG_VCYCLE only (EMG_EINVAL otherwise) */
 } emg_solve_opts;
 
 typedef struct {
@@ -131,8 +143,10 @@ emg_status emg_set_body_force(emg_problem *p, const double *b, int on_device);
 /* Face data: d components over the face's stored nodes, laid out like a
  * field whose normal axis has extent 1.  Prescribed displacement u0 on a
  * Dirichlet face (eq. elastic_b1), prescribed traction t0 on a traction face
- * (eq. elastic_b2).  NULL = 0.  At a node on several Dirichlet faces the
- * lowest-numbered face supplies u0. */
+ * (eq. elastic_b2), prescribed normal derivative du0_i = (du_i/dx_j) n_j on a
+ * Neumann face (eq. elastic_b3; n the outward normal).  NULL = 0.  At a node
+ * on several Dirichlet faces the lowest-numbered face supplies u0; at a node
+ * on several Neumann faces the row and its right-hand side sum over them. */
 emg_status emg_set_face(emg_problem *p, int face, const double *values, int on_device);
 
 /* Solve D_H(u) = -(D(0) + b) with the boundary operators (Sec. 2.1.1) by

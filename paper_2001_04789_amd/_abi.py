@@ -22,11 +22,14 @@ lib = ctypes.CDLL(LIB_PATH)
 c_int, c_int64, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 
 EMG_OK, EMG_EINVAL, EMG_ENOMEM, EMG_EDEVICE, EMG_ENOTCONV, EMG_EDIVERGED, EMG_ESTATE = 0, -1, -2, -3, -4, -5, -6
-EMG_BC_DIRICHLET, EMG_BC_TRACTION, EMG_BC_PERIODIC = 0, 1, 2
+EMG_BC_DIRICHLET, EMG_BC_TRACTION, EMG_BC_PERIODIC, EMG_BC_NEUMANN = 0, 1, 2, 3
 EMG_MOD_ISO, EMG_MOD_ANISO = 0, 1
 EMG_FP64, EMG_MIXED = 0, 1
+EMG_VCYCLE, EMG_FCYCLE = 0, 1
 
-_BC = {"dirichlet": EMG_BC_DIRICHLET, "traction": EMG_BC_TRACTION, "periodic": EMG_BC_PERIODIC}
+_BC = {"dirichlet": EMG_BC_DIRICHLET, "traction": EMG_BC_TRACTION, "periodic": EMG_BC_PERIODIC,
+       "neumann": EMG_BC_NEUMANN}
+_CYCLE = {"V": EMG_VCYCLE, "F": EMG_FCYCLE, EMG_VCYCLE: EMG_VCYCLE, EMG_FCYCLE: EMG_FCYCLE}
 _KIND = {"iso": EMG_MOD_ISO, "aniso": EMG_MOD_ANISO}
 _PREC = {"fp64": EMG_FP64, "mixed": EMG_MIXED, EMG_FP64: EMG_FP64, EMG_MIXED: EMG_MIXED}
 
@@ -38,7 +41,8 @@ class emg_domain(ctypes.Structure):
 
 class emg_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("max_cycles", c_int), ("precision", c_int), ("nu1", c_int), ("nu2", c_int),
-                ("omega", c_double), ("warm_start", c_int), ("check_every", c_int), ("use_graph", c_int)]
+                ("omega", c_double), ("warm_start", c_int), ("check_every", c_int), ("use_graph", c_int),
+                ("cycle", c_int)]
 
 
 class emg_solve_stats(ctypes.Structure):
@@ -165,9 +169,14 @@ class Context:
 def default_opts(**kw) -> emg_solve_opts:
     o = emg_solve_opts()
     lib.emg_default_opts(ctypes.byref(o))
+    names = {f[0] for f in emg_solve_opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solve option {k!r}")
         if k == "precision":
             v = _PREC[v]
+        elif k == "cycle":
+            v = _CYCLE[v]
         setattr(o, k, v)
     return o
 
@@ -495,5 +504,6 @@ class Problem:
 __all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch",
            "emg_domain", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
            "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE",
-           "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_MOD_ISO", "EMG_MOD_ANISO",
+           "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_BC_NEUMANN", "EMG_VCYCLE", "EMG_FCYCLE",
+           "EMG_MOD_ISO", "EMG_MOD_ANISO",
            "EMG_FP64", "EMG_MIXED"] + list(SYMBOLS)

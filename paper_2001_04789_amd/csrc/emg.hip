@@ -125,9 +125,9 @@ struct emg_problem {
   size_t bytes = 0;
   size_t accounted = 0;   // bytes charged to the context's HBM budget
   bool counted = false;   // counted in the context's live objects
-  // graph cache: key = (precision, cycles per replay, nu1, nu2, omega)
+  // graph cache: key = (precision, cycles per replay, nu1, nu2, cycle type, omega)
   struct GraphEntry {
-    int prec, k, nu1, nu2;
+    int prec, k, nu1, nu2, fcyc;
     double omega;
     hipGraphExec_t exec;
   };
@@ -363,8 +363,6 @@ emg_status assemble_rhs(emg_problem *p) {
 
 // ---- cycles ----
 
-// V-cycle on coarse level l >= 1 for the correction, starting from zero;
-// returns the ping-pong buffer holding the result.
 template <typename R>
 R *vbuf(Level &L, int b) {
   if constexpr (std::is_same<R, double>::value) return L.u64[b];
@@ -382,22 +380,35 @@ R *rbuf(Level &L) {
 }
 
 template <typename R>
-int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega) {
+int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc);
+
+// Cycle on level l for the correction of the right-hand side f_l: from zero
+// (cur < 0; the first sweep is the zero-start sweep) or from the iterate in
+// ping-pong buffer cur.  The coarse correction is a V-cycle from zero, or
+// with fcyc an F-cycle from zero followed by a V-cycle from its result, so
+// with fcyc and cur < 0 this is the F-cycle on level l.  The bottom level is
+// solved exactly whatever the start.  Returns the buffer holding the result.
+template <typename R>
+int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, int cur = -1) {
   const int L = (int)p->lv.size();
   Level &Lv = p->lv[l];
   if (l == L - 1) {
     launch_bottom<R, R>(p, fbuf<R>(Lv), vbuf<R>(Lv, 0), p->ctl);
     return 0;
   }
-  int cur = 0;
-  launch_jacobi_zero<R>(p, Lv, fbuf<R>(Lv), vbuf<R>(Lv, 0), omega, p->ctl);
-  for (int s = 1; s < nu1; s++) {
+  int s0 = 0;
+  if (cur < 0) {
+    launch_jacobi_zero<R>(p, Lv, fbuf<R>(Lv), vbuf<R>(Lv, 0), omega, p->ctl);
+    cur = 0;
+    s0 = 1;
+  }
+  for (int s = s0; s < nu1; s++) {
     launch_stencil<R, MODE_JACOBI, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1), omega, nullptr, p->ctl);
     cur ^= 1;
   }
   launch_stencil<R, MODE_RESID, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), rbuf<R>(Lv), omega, nullptr, p->ctl);
   launch_restrict<R, R>(p, Lv, p->lv[l + 1], rbuf<R>(Lv), fbuf<R>(p->lv[l + 1]), p->ctl);
-  const int cb = coarse_cycle<R>(p, l + 1, nu1, nu2, omega);
+  const int cb = coarse_correction<R>(p, l + 1, nu1, nu2, omega, fcyc);
   launch_prolong<R, R>(p, p->lv[l + 1], Lv, vbuf<R>(p->lv[l + 1], cb), vbuf<R>(Lv, cur), p->ctl);
   for (int s = 0; s < nu2; s++) {
     launch_stencil<R, MODE_JACOBI, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1), omega, nullptr, p->ctl);
@@ -406,10 +417,22 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega) {
   return cur;
 }
 
+// Correction on level l >= 1 for the restricted residual in f_l: a V-cycle
+// from zero, or an F-cycle from zero then a V-cycle from its result (the
+// V-cycle's restriction overwrites f_{l+1}, which the F-cycle no longer
+// needs; f_l itself is only read).
+template <typename R>
+int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc) {
+  if (!fcyc) return coarse_cycle<R>(p, l, nu1, nu2, omega, false);
+  const int b = coarse_cycle<R>(p, l, nu1, nu2, omega, true);
+  if (l == (int)p->lv.size() - 1) return b;   // exact bottom solve: the V-cycle would repeat it
+  return coarse_cycle<R>(p, l, nu1, nu2, omega, false, b);
+}
+
 // One FP64 V-cycle on level 0 for u (buffer 0 in and out).  The first sweep
 // also sums the squared residual of the incoming iterate; the check kernel
 // stops the solve before the cycle changes anything if it has converged.
-void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
+void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc) {
   Level &L0 = p->lv[0];
   int cur = 0;
   launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[0], L0.f64, L0.u64[1], omega, p->partial, p->ctl);
@@ -421,7 +444,7 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
   }
   launch_stencil<double, MODE_RESID, double>(p, L0, L0.u64[cur], L0.f64, L0.r64, omega, nullptr, p->ctl);
   launch_restrict<double, double>(p, L0, p->lv[1], L0.r64, p->lv[1].f64, p->ctl);
-  const int cb = coarse_cycle<double>(p, 1, nu1, nu2, omega);
+  const int cb = coarse_correction<double>(p, 1, nu1, nu2, omega, fcyc);
   launch_prolong<double, double>(p, p->lv[1], L0, p->lv[1].u64[cb], L0.u64[cur], p->ctl);
   for (int s = 0; s < nu2; s++) {
     launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
@@ -433,15 +456,16 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega) {
 // One mixed-precision refinement step: u += e (the previous FP32
 // correction, zero at the start), FP64 residual written as FP32 to the
 // level-0 FP32 right-hand side with its norm, convergence check, then one
-// FP32 V-cycle for the new correction e (left in u32[0] of level 0).
-void record_mixed_iter(emg_problem *p, int, int nu1, int nu2, float omega) {
+// FP32 V-cycle (F-cycle with fcyc) for the new correction e (left in u32[0]
+// of level 0).
+void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc) {
   Level &L0 = p->lv[0];
   const long long nd0 = (long long)p->D * L0.g.N;
   hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
                      p->stream, nd0, L0.u64[0], L0.u32[0], p->ctl);
   launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
   launch_check(p, stencil_blocks(L0.g), 0);
-  const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega);
+  const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc);
   if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
 }
 
@@ -526,7 +550,7 @@ void amr_residual(emg_problem *p, const Ctl *ctl) {
 // interpolation onto valid and ghost nodes, relaxation with the
 // interpolated ghosts as Dirichlet values; update.
 template <int D>
-void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega) {
+void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc) {
   Level &L0 = p->lv[0];
   const int Lf = (int)p->fine.size();
   amr_sync<D>(p, p->amr_u0, p->ctl);
@@ -557,7 +581,7 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega) {
     hipLaunchKernelGGL((k_restrict_cf<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b,
                        (const double *)F.t, gc, co, rrc, p->ctl);
   }
-  const int cb = coarse_cycle<double>(p, 0, nu1, nu2, omega);
+  const int cb = coarse_cycle<double>(p, 0, nu1, nu2, omega, fcyc);
   for (int k = 1; k <= Lf; k++) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
@@ -582,35 +606,36 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega) {
   }
 }
 
-void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double omega) {
+void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, bool fcyc) {
   if (!p->fine.empty()) {
     for (int c = 0; c < k; c++) {
-      if (p->D == 2) record_amr_cycle<2>(p, nu1, nu2, omega);
-      else record_amr_cycle<3>(p, nu1, nu2, omega);
+      if (p->D == 2) record_amr_cycle<2>(p, nu1, nu2, omega, fcyc);
+      else record_amr_cycle<3>(p, nu1, nu2, omega, fcyc);
     }
     return;
   }
   if (prec == EMG_FP64) {
-    for (int c = 0; c < k; c++) record_fp64_cycle(p, nu1, nu2, omega);
+    for (int c = 0; c < k; c++) record_fp64_cycle(p, nu1, nu2, omega, fcyc);
   } else {
-    for (int c = 0; c < k; c++) record_mixed_iter(p, c & 1, nu1, nu2, (float)omega);
+    for (int c = 0; c < k; c++) record_mixed_iter(p, nu1, nu2, (float)omega, fcyc);
   }
 }
 
-emg_status get_graph(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, hipGraphExec_t *out) {
+emg_status get_graph(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, bool fcyc,
+                     hipGraphExec_t *out) {
   for (auto &g : p->graphs)
-    if (g.prec == prec && g.k == k && g.nu1 == nu1 && g.nu2 == nu2 && g.omega == omega) {
+    if (g.prec == prec && g.k == k && g.nu1 == nu1 && g.nu2 == nu2 && g.omega == omega && g.fcyc == (int)fcyc) {
       *out = g.exec;
       return EMG_OK;
     }
   hipGraph_t graph;
   HIPCK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  record_cycles(p, prec, k, nu1, nu2, omega);
+  record_cycles(p, prec, k, nu1, nu2, omega, fcyc);
   HIPCK(hipStreamEndCapture(p->stream, &graph));
   hipGraphExec_t exec;
   HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   HIPCK(hipGraphDestroy(graph));
-  p->graphs.push_back({prec, k, nu1, nu2, omega, exec});
+  p->graphs.push_back({prec, k, nu1, nu2, (int)fcyc, omega, exec});
   *out = exec;
   return EMG_OK;
 }
@@ -1118,7 +1143,7 @@ emg_status level_chain(const emg_domain *dom, std::vector<Geom> &gs) {
     if (a < dom->dim) {
       const int b0 = dom->bc[2 * a], b1 = dom->bc[2 * a + 1];
       for (int b : {b0, b1})
-        if (b != EMG_BC_DIRICHLET && b != EMG_BC_TRACTION && b != EMG_BC_PERIODIC)
+        if (b != EMG_BC_DIRICHLET && b != EMG_BC_TRACTION && b != EMG_BC_PERIODIC && b != EMG_BC_NEUMANN)
           return fail(EMG_EINVAL, "bad boundary type");
       if ((b0 == EMG_BC_PERIODIC) != (b1 == EMG_BC_PERIODIC))
         return fail(EMG_EINVAL, "both faces of a periodic axis must be periodic");
@@ -1441,6 +1466,7 @@ void emg_default_opts(emg_solve_opts *o) {
   o->warm_start = 0;
   o->check_every = 4;
   o->use_graph = 1;
+  o->cycle = EMG_VCYCLE;
 }
 
 emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out) {
@@ -1620,6 +1646,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
   if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
   if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
+  if (opt.cycle != EMG_VCYCLE && opt.cycle != EMG_FCYCLE) return fail(EMG_EINVAL, "bad cycle type");
   const int k = std::max(1, opt.check_every);
   const auto t0 = std::chrono::steady_clock::now();
   TRY(setup(p));
@@ -1672,13 +1699,14 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   HIPCK(hipStreamSynchronize(p->stream));
   const auto t1 = std::chrono::steady_clock::now();
   hipGraphExec_t exec = nullptr;
-  if (opt.use_graph) TRY(get_graph(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, &exec));
+  const bool fcyc = opt.cycle == EMG_FCYCLE;
+  if (opt.use_graph) TRY(get_graph(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, fcyc, &exec));
   const auto t2 = std::chrono::steady_clock::now();
   for (;;) {
     if (exec)
       HIPCK(hipGraphLaunch(exec, p->stream));
     else
-      record_cycles(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega);
+      record_cycles(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, fcyc);
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
     HIPCK(hipStreamSynchronize(p->stream));
@@ -1910,6 +1938,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
   if (!(opt.omega > 0.0 && opt.omega < 2.0) || opt.warm_start) return fail(EMG_EINVAL, "bad omega or warm start");
+  if (opt.cycle != EMG_VCYCLE) return fail(EMG_EINVAL, "batched solves run V-cycles only");
   std::vector<emg_problem *> ps(probs, probs + n);
   for (auto *p : ps)
     if (!p || p->ctx != ps[0]->ctx) return fail(EMG_EINVAL, "null problem or problems of different contexts");
@@ -1986,7 +2015,8 @@ emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *
   emg_default_opts(&S->opt);
   if (o) S->opt = *o;
   if ((S->opt.precision != EMG_FP64 && S->opt.precision != EMG_MIXED) || S->opt.nu1 < 1 || S->opt.nu2 < 0 ||
-      !(S->opt.omega > 0.0 && S->opt.omega < 2.0) || S->opt.warm_start) {
+      S->opt.nu1 > 16 || S->opt.nu2 > 16 || !(S->opt.omega > 0.0 && S->opt.omega < 2.0) || S->opt.warm_start ||
+      S->opt.cycle != EMG_VCYCLE) {
     delete S;
     return fail(EMG_EINVAL, "bad solve options");
   }

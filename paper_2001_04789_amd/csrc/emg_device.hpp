@@ -1,12 +1,15 @@
 // Device-side building blocks of the gfx950 multigrid elasticity solver:
 // grid geometry, row classification, the finite-difference rows of the
-// operator D_H (product-rule interior rows, traction boundary rows,
-// Dirichlet rows) and wavefront reductions.
+// operator D_H (product-rule interior rows, traction and Neumann boundary
+// rows, Dirichlet rows) and wavefront reductions.
 //
 // Operator (Sec. 2.1, Sec. 2.1.1 product rule):
 //   interior row i:  sum_jkl d_j(C_ijkl) d_l(u_k) + C_ijkl d_jl(u_k)
 //   traction row i:  sum over the node's faces of  n_a sum_kl C_iakl dhat_l(u_k)
+//   Neumann row i:   sum over the node's Neumann faces of  n_a dhat_a(u_i)
 //   Dirichlet row i: u_i
+// A node on faces of several kinds takes the Dirichlet row if any of its
+// faces is Dirichlet, else the Neumann row if any is Neumann.
 // The interior rows are evaluated in "flux form": with e the engineering
 // strain of the centre gradient, sum_kl C_ijkl(q) d_l u_k = (C(q) e)_{V(i,j)},
 // so the modulus-derivative term is a difference of two neighbour
@@ -17,8 +20,8 @@
 
 namespace emg {
 
-enum { BC_DIR = 0, BC_TRAC = 1, BC_PER = 2 };
-enum { ROW_INT = 0, ROW_TRAC = 1, ROW_DIR = 2 };
+enum { BC_DIR = 0, BC_TRAC = 1, BC_PER = 2, BC_NEU = 3 };
+enum { ROW_INT = 0, ROW_TRAC = 1, ROW_DIR = 2, ROW_NEU = 3 };
 enum { MOD_ISO = 0, MOD_ANISO = 1 };
 
 // Geometry of one level, passed by value to every kernel.
@@ -82,16 +85,25 @@ __device__ __forceinline__ int end_of(const Geom &g, int a, int c) {
 }
 
 __device__ __forceinline__ int row_class(const Geom &g, const int p[3]) {
-  int on = 0, dir = 0;
+  int on = 0, dir = 0, neu = 0;
 #pragma unroll
   for (int a = 0; a < 3; a++) {
     const int e = a < g.dim ? end_of(g, a, p[a]) : 0;
     if (e) {
       on = 1;
-      if (g.bc[2 * a + (e > 0)] == BC_DIR) dir = 1;
+      const int b = g.bc[2 * a + (e > 0)];
+      if (b == BC_DIR) dir = 1;
+      if (b == BC_NEU) neu = 1;
     }
   }
-  return dir ? ROW_DIR : (on ? ROW_TRAC : ROW_INT);
+  return dir ? ROW_DIR : (neu ? ROW_NEU : (on ? ROW_TRAC : ROW_INT));
+}
+
+// Normal component of the Neumann face of node p on axis a (0 if p is not
+// on a Neumann face of that axis).
+__device__ __forceinline__ int neumann_normal(const Geom &g, int a, const int p[3]) {
+  const int e = end_of(g, a, p[a]);
+  return (e && g.bc[2 * a + (e > 0)] == BC_NEU) ? e : 0;
 }
 
 __device__ __forceinline__ long long stride_of(const Geom &g, int a) {
@@ -346,6 +358,27 @@ __device__ __forceinline__ void traction_rows(const Geom &g, const R *__restrict
   }
 }
 
+// ---- boundary rows on Neumann faces: normal derivative of each component ----
+template <int D, typename R, class U>
+__device__ __forceinline__ void neumann_rows(const Geom &g, U u, long long n, const int p[3], R acc[D], R dg[D]) {
+#pragma unroll
+  for (int i = 0; i < D; i++) { acc[i] = R(0); dg[i] = R(0); }
+#pragma unroll
+  for (int a = 0; a < D; a++) {
+    const int na = neumann_normal(g, a, p);
+    if (!na) continue;
+    const R hl = R(g.h[a]);
+    const int s = -na;   // inward direction
+    const long long s1 = shift(g, a, p[a], s), s2 = shift(g, a, p[a], 2 * s);
+    // n_a dhat_a(u) with dhat_a = s (-3 u0 + 4 u1 - u2) / (2h) and n_a s = -1
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      acc[i] += (R(3) * u(i, n) - R(4) * u(i, n + s1) + u(i, n + s2)) / (R(2) * hl);
+      dg[i] += R(3) / (R(2) * hl);
+    }
+  }
+}
+
 // Neighbour offsets (with periodic wrap) of node p for the interior rows.
 __device__ __forceinline__ void neighbour_offsets(const Geom &g, const int p[3], long long om[3], long long op[3]) {
 #pragma unroll
@@ -375,6 +408,8 @@ __device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, 
     interior_rows<D, K, R, U>(C, g.SC, u, n, om, op, i2h, ih2, acc, dg);
   } else if (cls == ROW_TRAC) {
     traction_rows<D, K, R, U>(g, C, u, n, p, acc, dg);
+  } else if (cls == ROW_NEU) {
+    neumann_rows<D, R, U>(g, u, n, p, acc, dg);
   } else {
 #pragma unroll
     for (int i = 0; i < D; i++) {
@@ -391,6 +426,15 @@ __device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, 
   if (cls == ROW_DIR) {
 #pragma unroll
     for (int i = 0; i < D; i++) dg[i] = R(1);
+    return;
+  }
+  if (cls == ROW_NEU) {
+    R s = R(0);
+#pragma unroll
+    for (int a = 0; a < D; a++)
+      if (neumann_normal(g, a, p)) s += R(3) / R(2.0 * g.h[a]);
+#pragma unroll
+    for (int i = 0; i < D; i++) dg[i] = s;
     return;
   }
   constexpr int NC = nmod<D, K>();

@@ -430,7 +430,8 @@ __device__ __forceinline__ double c_dot_e(const double *c, const double *E, int 
 
 // Right-hand side: interior -b + d_j(C_ijkl eps0_kl) by the product rule
 // (= -(D(0) + b), Sec. 2.1.1); traction rows sum_f t0_f + C eps0 n_f;
-// Dirichlet rows u0 of the lowest-numbered Dirichlet face.
+// Neumann rows the sum of the prescribed normal derivatives of the node's
+// Neumann faces; Dirichlet rows u0 of the lowest-numbered Dirichlet face.
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ C, const double *__restrict__ eps,
                                              const double *__restrict__ b, Faces F, double *__restrict__ f) {
@@ -454,6 +455,11 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
           acc = face_val(g, F, fc, p, i);
           break;
         }
+      }
+    } else if (cls == ROW_NEU) {
+      for (int a = 0; a < D; a++) {
+        const int na = neumann_normal(g, a, p);
+        if (na) acc += face_val(g, F, 2 * a + (na > 0), p, i);
       }
     } else if (cls == ROW_INT) {
       if (b) acc -= b[i * g.N + n];

@@ -7,7 +7,12 @@ grids that span several 64 x 4 tiles with ragged tails in x and y.  FP64
 steps must agree to 1e-12 of the output's magnitude (different summation
 order and fused multiply-adds only); FP32 steps to 2e-5.  Whole solves must
 reach relative residual 1e-10 and agree with the oracle's solution (iterated
-to 1e-13) to 1e-8 in relative 2-norm.
+to 1e-13) to 1e-8 in relative 2-norm; the FP64 iterate must also equal the
+oracle's own iterate at the same tolerance (same cycle count) to 1e-10.
+Problems with Neumann faces are held to the 1e-8 distance at residual 1e-11:
+their boundary rows scale as 1/h against 1/h^2 inside, so the residual norm
+weighs them little and residual 1e-10 leaves errors near 2e-8 in the oracle's
+own iterate as well.
 """
 import numpy as np
 import pytest
@@ -58,6 +63,10 @@ CASES = {
     "2d_iso": dict(dim=2, n=(129, 97), bc=("traction", "traction", "dirichlet", "traction", "periodic", "periodic"), kind="iso"),
     "2d_aniso_periodic": dict(dim=2, n=(129, 97), bc=("periodic", "periodic", "dirichlet", "traction", "periodic", "periodic"),
                               kind="aniso"),
+    "3d_aniso_neumann": dict(dim=3, n=(65, 81, 33), bc=("neumann", "traction", "periodic", "periodic", "dirichlet", "neumann"),
+                             kind="aniso"),
+    "2d_iso_neumann": dict(dim=2, n=(129, 97), bc=("neumann", "neumann", "dirichlet", "traction", "periodic", "periodic"),
+                           kind="iso"),
 }
 
 
@@ -142,7 +151,12 @@ SOLVES = {
                                                                             "traction", "traction"), "iso", seed=9),
     "random2d_aniso": lambda: synth.random_problem(2, (65, 33), ("dirichlet", "dirichlet", "traction", "traction",
                                                                  "periodic", "periodic"), "aniso", seed=10, with_body=True),
+    "random3d_neumann": lambda: synth.random_problem(3, (17, 17, 17), ("neumann", "traction", "dirichlet", "neumann",
+                                                                       "traction", "neumann"), "aniso", seed=11),
+    "random2d_neumann": lambda: synth.random_problem(2, (65, 65), ("neumann", "neumann", "dirichlet", "traction",
+                                                                   "periodic", "periodic"), "iso", seed=12, with_body=True),
 }
+RTOL = {"random2d_neumann": 1e-11, "random3d_neumann": 1e-11}
 
 _ORACLE_CACHE = {}
 
@@ -150,29 +164,40 @@ _ORACLE_CACHE = {}
 def oracle_solution(name):
     if name not in _ORACLE_CACHE:
         spec = SOLVES[name]()
-        _ORACLE_CACHE[name] = (spec, oracle.solve(spec, tol=1e-13, max_cycles=400))
+        _ORACLE_CACHE[name] = (spec, oracle.solve(spec, tol=1e-13, max_cycles=400),
+                               oracle.solve(spec, tol=1e-10, max_cycles=400))
     return _ORACLE_CACHE[name]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(SOLVES))
 def test_solve_matches_oracle(emg, ctx, name, precision):
-    spec, ref = oracle_solution(name)
+    spec, ref, ref10 = oracle_solution(name)
     print(f"[gpu] solve {name} {precision} m={spec.m}", flush=True)
     prob = emg.Problem.from_spec(ctx, spec)
+    g = oracle.Grid.of(spec)
+    C = spec.C
+    lift = np.where(oracle.dirichlet_mask(g), ref.rhs, 0.0)
+    r0 = oracle.residual(g, C, lift, ref.rhs)
     st = prob.solve(rtol=1e-10, max_cycles=400, precision=precision)
     assert st["converged"] and st["rel_res"] <= 1e-10
     u = prob.displacement()
-    err = np.linalg.norm(u - ref.u) / np.linalg.norm(ref.u)
-    print(f"[gpu]   cycles={st['cycles']} rel_res={st['rel_res']:.2e} rel_err={err:.2e}", flush=True)
-    assert err <= 1e-8
     # the oracle's own residual of the GPU iterate confirms the tolerance
-    g = oracle.Grid.of(spec)
-    C = spec.C
-    r = oracle.residual(g, C, u, ref.rhs)
-    lift = np.where(oracle.dirichlet_mask(g), ref.rhs, 0.0)
-    r0 = oracle.residual(g, C, lift, ref.rhs)
-    assert oracle.norm(g, r) / oracle.norm(g, r0) <= 1.2e-10
+    assert oracle.norm(g, oracle.residual(g, C, u, ref.rhs)) / oracle.norm(g, r0) <= 1.2e-10
+    if precision == "fp64":
+        # same algorithm, same stopping rule: the oracle's iterate at 1e-10
+        assert st["cycles"] == ref10.cycles
+        it = np.linalg.norm(u - ref10.u) / np.linalg.norm(ref10.u)
+        print(f"[gpu]   iterate vs oracle iterate (cycles {ref10.cycles}): {it:.2e}", flush=True)
+        assert it <= 1e-10
+    rtol = RTOL.get(name, 1e-10)
+    if rtol < 1e-10:
+        st = prob.solve(rtol=rtol, max_cycles=400, precision=precision)
+        assert st["converged"] and st["rel_res"] <= rtol
+        u = prob.displacement()
+    err = np.linalg.norm(u - ref.u) / np.linalg.norm(ref.u)
+    print(f"[gpu]   rtol={rtol:.0e} cycles={st['cycles']} rel_res={st['rel_res']:.2e} rel_err={err:.2e}", flush=True)
+    assert err <= 1e-8
     s = prob.stress()
     s_ref = oracle.stress(g, C, spec.eps0, ref.u)
     assert np.linalg.norm(s - s_ref) / np.linalg.norm(s_ref) <= 1e-7
