@@ -196,9 +196,31 @@ const R *moduli(const Level &L) {
   else return L.C32;
 }
 
+// Chunks per column of the z-marching pass for a level (0: tile kernel).  It
+// takes 3D anisotropic levels with enough columns x chunks of >= 8 planes to
+// give every CU a workgroup (FP64: one per CU, FP32: two); smaller levels
+// keep the tile kernel, which spreads them over more workgroups.
+template <typename R>
+int zm_plan(const emg_problem *p, const Geom &g) {
+  if (p->D != 3 || p->K != MOD_ANISO) return 0;
+  const int target = sizeof(R) == 8 ? 256 : 512;
+  const int nzc = zm_chunks(g, target);
+  if (nzc == 0) return 0;
+  const Split sp = split_of(g);
+  return (long long)sp.ntx * sp.nty * nzc >= target / 2 ? nzc : 0;
+}
+
 template <typename R, int MODE, typename TO>
 void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *out, R omega, double *partial,
                     const Ctl *ctl) {
+  const int nzc = zm_plan<R>(p, L.g);
+  if (nzc > 0) {
+    const Split sp = split_of(L.g);
+    const unsigned blocks = (unsigned)((long long)sp.ntx * sp.nty * nzc + sp.sblocks);
+    hipLaunchKernelGGL((k_stencil_zm<R, MODE, TO>), dim3(blocks), kBlock, 0, p->stream, L.g, moduli<R>(L), u, f, out,
+                       omega, partial, ctl, nzc);
+    return;
+  }
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
     hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0, p->stream, L.g,

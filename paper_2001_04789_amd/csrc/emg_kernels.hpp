@@ -2,6 +2,7 @@
 // 64 x 4 thread blocks (one wavefront per x-row of a tile), x fastest so
 // every load of a field component is a coalesced row of 64 nodes.
 #pragma once
+#include <algorithm>
 #include "emg_device.hpp"
 
 namespace emg {
@@ -234,6 +235,347 @@ __global__ __launch_bounds__(256, 2) void k_stencil(Geom g, const R *__restrict_
   if (skip(ctl)) return;
   const long long t = blockIdx.x;
   body_stencil<D, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
+}
+
+// ---- z-marching interior pass (3D, anisotropic moduli) ----
+// A workgroup of 64 x 4 threads walks one column of interior tiles (the
+// tiles of body_stencil) through a run of planes.  The moduli of the current
+// plane and the displacement of three consecutive planes sit in LDS with a
+// one-node halo in x and y, so every neighbour value of the 19-point stencil
+// and every x/y neighbour modulus row comes from LDS: per node the pass
+// issues about 40 global loads (each value once, plus the halo) instead of
+// about 170, which on this GPU are bound by the vector-memory address rate,
+// not by HBM.  The -z modulus rows are the previous plane's centre moduli,
+// kept in registers; the +z rows of plane z are applied one step later, when
+// plane z+1's moduli are the LDS centre, so the next plane's loads are only
+// consumed by the LDS store at the end of a step and are issued in four
+// groups spread over its compute phases.  Arithmetic, its order, and the
+// norm partial of each 64 x 4 tile (its slot and summation order) are those
+// of the interior tiles of body_stencil, bit for bit.
+constexpr int ZM_HX = BX + 2, ZM_HY = BY + 2, ZM_HP = ZM_HX * ZM_HY, ZM_NH = ZM_HP - BX * BY;
+
+// Workgroups of a z-marching pass: columns x chunks, or 0 if the level is
+// better served by body_stencil (fewer than 8 planes per chunk).
+__host__ inline int zm_chunks(const Geom &g, int target_wg) {
+  if (g.dim != 3) return 0;
+  const Split sp = split_of(g);
+  if (sp.inner == 0) return 0;
+  const long long cols = (long long)sp.ntx * sp.nty;
+  int nzc = (int)std::max<long long>(1, (target_wg + cols / 2) / cols);
+  nzc = std::min(nzc, sp.ntz / 8);
+  return nzc >= 1 ? nzc : 0;
+}
+
+template <typename R, int MODE, typename TO>
+__device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const R *__restrict__ C, const R *__restrict__ u,
+                                          const R *__restrict__ f, TO *__restrict__ out, R omega,
+                                          double *__restrict__ partial, int nzc, unsigned w, R *__restrict__ sC,
+                                          R *__restrict__ sU) {
+  constexpr int TX = BX, TY = BY, HX = ZM_HX, HY = ZM_HY, HP = ZM_HP, NH = ZM_NH, NC = 21, NV = 6;
+  constexpr int HW = (NH + 63) / 64;   // wavefronts holding a halo position
+  const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TX + tx;
+  const int wave = __builtin_amdgcn_readfirstlane(ty);
+  const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
+  // XCD x (workgroups x, x+8, ...) takes a contiguous run of columns, so the
+  // halo rows shared by neighbouring columns are fetched into one L2
+  const unsigned L = nwg % kXCD == 0 ? (w % kXCD) * (nwg / kXCD) + w / kXCD : w;
+  const int chunk = L % nzc, col = L / nzc;
+  const int cx = col % sp.ntx, cy = col / sp.ntx;
+  const int x0 = sp.lo[0] + cx * TX, y0 = sp.lo[1] + cy * TY;
+  const int nz = sp.hi[2] - sp.lo[2] + 1;
+  const int zs = sp.lo[2] + (int)((long long)nz * chunk / nzc);
+  const int ze = sp.lo[2] + (int)((long long)nz * (chunk + 1) / nzc);
+  const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
+  // coordinates of a tile or halo position: wrapped on periodic axes,
+  // clamped otherwise (clamped positions only feed lanes outside the box)
+  auto fix = [](int c, int m, int per) {
+    if (per) {
+      c %= m;
+      return c < 0 ? c + m : c;
+    }
+    return c < 0 ? 0 : (c > m - 1 ? m - 1 : c);
+  };
+  const bool inbox = x0 + tx <= sp.hi[0] && y0 + ty <= sp.hi[1];
+  const int p0 = (ty + 1) * HX + tx + 1;
+  const unsigned r0 = (unsigned)fix(y0 + ty, m1, g.per[1]) * m0 + fix(x0 + tx, m0, g.per[0]);
+  int p1 = p0;   // lanes of halo wavefronts without a halo position repeat their own node
+  unsigned r1 = r0;
+  if (t < NH) {
+    int hx, hy;
+    if (t < HX) {
+      hy = 0;
+      hx = t;
+    } else if (t < 2 * HX) {
+      hy = HY - 1;
+      hx = t - HX;
+    } else {
+      const int q = t - 2 * HX;
+      hy = 1 + q / 2;
+      hx = (q & 1) ? HX - 1 : 0;
+    }
+    p1 = hy * HX + hx;
+    r1 = (unsigned)fix(y0 + hy - 1, m1, g.per[1]) * m0 + fix(x0 + hx - 1, m0, g.per[0]);
+  }
+  const bool halo = wave < HW;
+  // component bases in 64-bit arithmetic, node offsets in 32 bits (N < 2^29)
+  const unsigned P = (unsigned)m0 * m1;
+  const long long N = g.N, SC = g.SC;
+  auto plane = [&](int z) {
+    if (g.per[2]) z = z < 0 ? z + m2 : (z >= m2 ? z - m2 : z);
+    return (unsigned)z * P;
+  };
+  R i2h[3], ih2[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    i2h[a] = R(0.5 / g.h[a]);
+    ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
+  }
+  // next plane's values in flight: moduli (own node, halo node), displacement, right-hand side
+  R xc0[NC], xc1[NC], xu0[3], xu1[3], xf[3];
+  auto issue = [&](int zc, int zu, int zf, int q) {
+    const unsigned oc = plane(zc), ou = plane(zu);
+    if (q == 0) {
+#pragma unroll
+      for (int c = 0; c < 11; c++) xc0[c] = ld(C + c * SC, oc + r0);
+    } else if (q == 1) {
+#pragma unroll
+      for (int c = 11; c < NC; c++) xc0[c] = ld(C + c * SC, oc + r0);
+    } else if (q == 2) {
+      if (halo) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) xc1[c] = ld(C + c * SC, oc + r1);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; k++) xu0[k] = ld(u + k * N, ou + r0);
+      if (halo) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) xu1[k] = ld(u + k * N, ou + r1);
+      }
+      if constexpr (MODE != MODE_APPLY) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) xf[k] = ld(f + k * N, plane(zf) + r0);
+      }
+    }
+  };
+  auto store_c = [&]() {
+#pragma unroll
+    for (int c = 0; c < NC; c++) sC[c * HP + p0] = xc0[c];
+    if (halo) {
+#pragma unroll
+      for (int c = 0; c < NC; c++) sC[c * HP + p1] = xc1[c];
+    }
+  };
+  auto store_u = [&](int slot) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) sU[(slot * 3 + k) * HP + p0] = xu0[k];
+    if (halo) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) sU[(slot * 3 + k) * HP + p1] = xu1[k];
+    }
+  };
+  // -z modulus rows: centre moduli of the previous plane
+  R cprev[NC];
+  {
+    const unsigned o = plane(zs - 1);
+#pragma unroll
+    for (int c = 0; c < NC; c++) cprev[c] = ld(C + c * SC, o + r0);
+  }
+  int sm = 0, s0 = 1, sp1 = 2;   // LDS slots of the displacement planes z-1, z, z+1
+  issue(zs, zs - 1, zs, 3);
+  store_u(sm);
+  issue(zs, zs, zs, 3);
+  store_u(s0);
+  issue(zs, zs + 1, zs, 3);
+  store_u(sp1);
+  for (int q = 0; q < 3; q++) issue(zs, zs, zs, q);
+  store_c();
+  __syncthreads();
+  // carried to the next step: rows through the y terms, the -z term, centre
+  // displacement, diagonal, strain, right-hand side
+  R cA[3], cM[3], cu[3], cd[3], ce[NV], cf[3];
+  auto finish = [&](int zp, const R *cz) {   // cz: moduli of plane zp + 1 at the node
+    const unsigned o = plane(zp) + r0;
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const int Iv = vslot<3>(i, 2);
+      R sg = R(0);
+#pragma unroll
+      for (int J = 0; J < NV; J++) sg += cz[utri(NV, Iv, J)] * ce[J];
+      R a = cA[i];
+      a += sg * i2h[2];
+      a += -cM[i] * i2h[2];
+      if (inbox) {
+        TO *__restrict__ oi = (TO *)((char *)(out + i * N) + o * (unsigned)sizeof(TO));
+        if constexpr (MODE == MODE_APPLY) {
+          *oi = TO(a);
+        } else {
+          const R r = cf[i] - a;
+          *oi = MODE == MODE_RESID ? TO(r) : TO(cu[i] + omega * r / cd[i]);
+          nrm += double(r) * double(r);
+        }
+      }
+    }
+    if (partial)
+      block_sum_256(nrm, partial + sp.sblocks + ((long long)(zp - sp.lo[2]) * sp.nty + cy) * sp.ntx + cx);
+  };
+  for (int z = zs; z < ze; z++) {
+    const int zc = z + 1, zu = z + 2 <= ze ? z + 2 : ze;
+    issue(zc, zu, z, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    R uc[3], up[3][3], um[3][3], upp[3][3], upm[3][3], ump[3][3], umm[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const R *U0 = sU + (s0 * 3 + k) * HP, *Um = sU + (sm * 3 + k) * HP, *Up = sU + (sp1 * 3 + k) * HP;
+      uc[k] = U0[p0];
+      up[k][0] = U0[p0 + 1];
+      um[k][0] = U0[p0 - 1];
+      up[k][1] = U0[p0 + HX];
+      um[k][1] = U0[p0 - HX];
+      up[k][2] = Up[p0];
+      um[k][2] = Um[p0];
+      // mixed pairs (0,1) (0,2) (1,2)
+      upp[k][0] = U0[p0 + 1 + HX];
+      upm[k][0] = U0[p0 + 1 - HX];
+      ump[k][0] = U0[p0 - 1 + HX];
+      umm[k][0] = U0[p0 - 1 - HX];
+      upp[k][1] = Up[p0 + 1];
+      upm[k][1] = Um[p0 + 1];
+      ump[k][1] = Up[p0 - 1];
+      umm[k][1] = Um[p0 - 1];
+      upp[k][2] = Up[p0 + HX];
+      upm[k][2] = Um[p0 + HX];
+      ump[k][2] = Up[p0 - HX];
+      umm[k][2] = Um[p0 - HX];
+    }
+    R G[3][3], H[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        G[k][j] = (up[k][j] - um[k][j]) * i2h[j];
+        H[k][j][j] = (up[k][j] - R(2) * uc[k] + um[k][j]) * ih2[j];
+      }
+      constexpr int PJ[3] = {0, 0, 1}, PL[3] = {1, 2, 2};
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int j = PJ[q], l = PL[q];
+        R v = ((upp[k][q] - upm[k][q]) - (ump[k][q] - umm[k][q])) * (i2h[j] * i2h[l]);
+        H[k][j][l] = v;
+        H[k][l][j] = v;
+      }
+    }
+    R e[NV];
+#pragma unroll
+    for (int a = 0; a < 3; a++) e[a] = G[a][a];
+    e[3] = G[1][2] + G[2][1];
+    e[4] = G[0][2] + G[2][0];
+    e[5] = G[0][1] + G[1][0];
+    __builtin_amdgcn_sched_barrier(0);
+    issue(zc, zu, z, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    R cc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) cc[c] = sC[c * HP + p0];
+    if (z > zs) finish(z - 1, cc);
+    R acc[3], dg[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      R a2 = R(0), d2 = R(0);
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+          for (int l = 0; l < 3; l++) a2 += cc[utri(NV, vslot<3>(i, j), vslot<3>(k, l))] * H[k][j][l];
+        d2 += cc[utri(NV, vslot<3>(i, j), vslot<3>(i, j))] * ih2[j];
+      }
+      acc[i] = a2;
+      dg[i] = R(-2) * d2;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    issue(zc, zu, z, 2);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 2; j++) {   // x and y modulus rows of the LDS neighbours
+      if (j == 1) {
+        __builtin_amdgcn_sched_barrier(0);
+        issue(zc, zu, z, 3);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int s = 0; s < 2; s++) {
+        const int dp = j == 0 ? (s == 0 ? 1 : -1) : (s == 0 ? HX : -HX);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+          const int Iv = vslot<3>(i, j);
+          R sg = R(0);
+#pragma unroll
+          for (int J = 0; J < NV; J++) sg += sC[utri(NV, Iv, J) * HP + p0 + dp] * e[J];
+          acc[i] += (s == 0 ? sg : -sg) * i2h[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const int Iv = vslot<3>(i, 2);
+      R sg = R(0);
+#pragma unroll
+      for (int J = 0; J < NV; J++) sg += cprev[utri(NV, Iv, J)] * e[J];
+      cM[i] = sg;
+      cA[i] = acc[i];
+      cu[i] = uc[i];
+      cd[i] = dg[i];
+    }
+#pragma unroll
+    for (int a = 0; a < NV; a++) ce[a] = e[a];
+#pragma unroll
+    for (int c = 0; c < NC; c++) cprev[c] = cc[c];
+    __syncthreads();
+    if constexpr (MODE != MODE_APPLY) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) cf[k] = xf[k];
+    }
+    if (z + 1 < ze) {
+      store_c();
+      store_u(sm);
+      const int t0 = sm;
+      sm = s0;
+      s0 = sp1;
+      sp1 = t0;
+    }
+    __syncthreads();
+  }
+  R cz[NC];
+  const unsigned o = plane(ze);
+#pragma unroll
+  for (int c = 0; c < NC; c++) cz[c] = ld(C + c * SC, o + r0);
+  finish(ze - 1, cz);
+}
+
+// z-marching interior workgroups first (nwg of them), then the shell blocks
+// of body_stencil; one launch covers the level.  FP64 needs more than 256
+// registers (one workgroup per CU, which its 95 KB of LDS implies anyway);
+// FP32 fits two workgroups per CU.
+template <typename R, int MODE, typename TO>
+__global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom g, const R *__restrict__ C,
+                                                                           const R *__restrict__ u,
+                                                                           const R *__restrict__ f,
+                                                                           TO *__restrict__ out, R omega,
+                                                                           double *__restrict__ partial,
+                                                                           const Ctl *__restrict__ ctl, int nzc) {
+  if (skip(ctl)) return;
+  __shared__ R sC[21 * ZM_HP];
+  __shared__ R sU[9 * ZM_HP];
+  const Split sp = split_of(g);
+  const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
+  if (blockIdx.x < nwg) {
+    zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU);
+  } else {
+    const long long t = blockIdx.x - nwg;
+    body_stencil<3, MOD_ANISO, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
+  }
 }
 
 // u += e (FP32 correction into the FP64 iterate), pointwise.
