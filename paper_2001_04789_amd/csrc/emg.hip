@@ -305,28 +305,30 @@ emg_status setup(emg_problem *p) {
     }
   }
   const int L = (int)p->lv.size();
-  for (int l = 1; l < L; l++)
-    hipLaunchKernelGGL((k_coarsen<double>), grid_of(p->lv[l].g), kBlock, 0, p->stream, p->lv[l - 1].g, p->lv[l].g,
-                       p->nc, p->lv[l - 1].C64, p->lv[l].C64);
+  for (int l = 1; l < L; l++) {
+    const Geom &gc = p->lv[l].g;
+    const dim3 gr((gc.m[0] + BX - 1) / BX, (gc.m[1] + BY - 1) / BY, (unsigned)(gc.m[2] * p->nc));
+    hipLaunchKernelGGL((k_coarsen<double>), gr, kBlock, 0, p->stream, p->lv[l - 1].g, gc, p->nc, p->lv[l - 1].C64,
+                       p->lv[l].C64);
+  }
   HIPCK(hipGetLastError());
   // coarsest operator: assemble [A | I], invert by Gauss-Jordan with partial pivoting
   const Level &B = p->lv[L - 1];
   const int n = p->nbot;
-  double *M = nullptr;
-  HIPCK(hipMallocAsync((void **)&M, sizeof(double) * 2 * (size_t)n * n, p->stream));
+  double *M = nullptr;   // two n x 2n buffers: Gauss-Jordan steps go back and forth
+  HIPCK(hipMallocAsync((void **)&M, sizeof(double) * 4 * (size_t)n * n, p->stream));
+  double *Mb[2] = {M, M + 2 * (size_t)n * n};
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_bottom_assemble<D, K>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, B.g, B.C64, M, n);
+    hipLaunchKernelGGL((k_bottom_assemble<D, K>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, B.g, B.C64, Mb[0],
+                       n);
   });
   hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, p->stream, 1LL, p->status, 0);
-  for (int k = 0; k < n; k++) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, p->stream, M, n, k, p->status);
-    const long long cols = 2LL * n - k - 1;
-    if (cols > 0)
-      hipLaunchKernelGGL(k_gj_elim, dim3((unsigned)((cols + 255) / 256), n), dim3(256), 0, p->stream, M, n, k);
-  }
-  hipLaunchKernelGGL(k_gj_extract, dim3((unsigned)(((long long)n * n + 255) / 256)), dim3(256), 0, p->stream, M, n,
-                     p->Ainv);
+  for (int k = 0; k < n; k++)
+    hipLaunchKernelGGL(k_gj_step, dim3(n), dim3(256), 0, p->stream, (const double *)Mb[k & 1], Mb[(k + 1) & 1], n, k,
+                       p->status);
+  hipLaunchKernelGGL(k_gj_extract, dim3((unsigned)(((long long)n * n + 255) / 256)), dim3(256), 0, p->stream,
+                     Mb[n & 1], n, p->Ainv);
   HIPCK(hipGetLastError());
   int st = 0;
   HIPCK(hipMemcpyAsync(&st, p->status, sizeof(int), hipMemcpyDeviceToHost, p->stream));

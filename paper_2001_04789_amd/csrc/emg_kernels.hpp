@@ -616,6 +616,28 @@ __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict
 // Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
 // axis on whose end the coarse node sits only the coincident fine node
 // enters; Dirichlet coarse rows get 0.
+// Per-axis full-weighting weights and fine offsets of coarse node P (fine
+// node pf = 2P): [1/4, 1/2, 1/4] on an axis along which P is not on an end,
+// else (0, 1, 0) (only the coincident fine node).  Every 3^D stencil point is
+// then summed, the excluded ones with weight 0 and offset 0, so all loads
+// issue at once; the sum over the included points is unchanged (exact zeros).
+template <typename R>
+__device__ __forceinline__ void fw_weights(const Geom &gc, const Geom &gf, const int P[3], const int pf[3], int dim,
+                                           R wt[3][3], long long off[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    off[a][0] = off[a][1] = off[a][2] = 0;
+    wt[a][0] = wt[a][2] = R(0);
+    wt[a][1] = R(1);
+    if (a < dim && end_of(gc, a, P[a]) == 0) {
+      wt[a][0] = wt[a][2] = R(0.25);
+      wt[a][1] = R(0.5);
+      off[a][0] = shift(gf, a, pf[a], -1);
+      off[a][2] = shift(gf, a, pf[a], 1);
+    }
+  }
+}
+
 template <int D, typename RI, typename RO>
 __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, const RI *__restrict__ rf,
                                               RO *__restrict__ fc, int tx, int ty, int tz) {
@@ -630,29 +652,25 @@ __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, co
   }
   const int pf[3] = {2 * x, 2 * y, 2 * z};
   const long long nf = ((long long)pf[2] * gf.m[1] + pf[1]) * gf.m[0] + pf[0];
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  RI wt[3][3];
   long long off[3][3];
-  for (int a = 0; a < 3; a++) {
-    off[a][0] = off[a][1] = off[a][2] = 0;
-    if (a < D && end_of(gc, a, P[a]) == 0) {
-      lo[a] = -1;
-      hi[a] = 1;
-      off[a][0] = shift(gf, a, pf[a], -1);
-      off[a][2] = shift(gf, a, pf[a], 1);
-    }
-  }
+  fw_weights<RI>(gc, gf, P, pf, D, wt, off);
   RI acc[D];
+#pragma unroll
   for (int i = 0; i < D; i++) acc[i] = RI(0);
-  for (int oz = lo[2]; oz <= hi[2]; oz++)
-    for (int oy = lo[1]; oy <= hi[1]; oy++)
-      for (int ox = lo[0]; ox <= hi[0]; ox++) {
-        RI w = RI(1);
-        if (hi[0]) w *= (ox == 0) ? RI(0.5) : RI(0.25);
-        if (hi[1]) w *= (oy == 0) ? RI(0.5) : RI(0.25);
-        if (hi[2]) w *= (oz == 0) ? RI(0.5) : RI(0.25);
+  constexpr int ZR = D == 3 ? 1 : 0;
+#pragma unroll
+  for (int oz = -ZR; oz <= ZR; oz++)
+#pragma unroll
+    for (int oy = -1; oy <= 1; oy++)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ox++) {
+        const RI w = wt[0][ox + 1] * wt[1][oy + 1] * wt[2][oz + 1];
         const long long q = nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1];
+#pragma unroll
         for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + q];
       }
+#pragma unroll
   for (int i = 0; i < D; i++) fc[i * gc.N + nc] = RO(acc[i]);
 }
 
@@ -677,24 +695,33 @@ __device__ __forceinline__ void body_prolong(const Geom &gc, const Geom &gf, con
   if (row_class(gf, p) == ROW_DIR) return;
   const int b[3] = {x >> 1, y >> 1, z >> 1};
   const long long nb = ((long long)b[2] * gc.m[1] + b[1]) * gc.m[0] + b[0];
-  int cnt[3];
+  // per axis: (1/2, 1/2) at b, b+1 for an odd fine coordinate, else (1, 0);
+  // all 2^D corners are summed (weight 0 and offset 0 for the unused ones)
+  RC wt[3][2];
   long long o1[3];
+#pragma unroll
   for (int a = 0; a < 3; a++) {
-    cnt[a] = (a < D && (p[a] & 1)) ? 2 : 1;
-    o1[a] = cnt[a] == 2 ? shift(gc, a, b[a], 1) : 0;
+    const bool odd = a < D && (p[a] & 1);
+    wt[a][0] = odd ? RC(0.5) : RC(1);
+    wt[a][1] = odd ? RC(0.5) : RC(0);
+    o1[a] = odd ? shift(gc, a, b[a], 1) : 0;
   }
   RC acc[D];
+#pragma unroll
   for (int i = 0; i < D; i++) acc[i] = RC(0);
-  for (int cz = 0; cz < cnt[2]; cz++)
-    for (int cy = 0; cy < cnt[1]; cy++)
-      for (int cx = 0; cx < cnt[0]; cx++) {
-        RC w = RC(1);
-        if (cnt[0] == 2) w *= RC(0.5);
-        if (cnt[1] == 2) w *= RC(0.5);
-        if (cnt[2] == 2) w *= RC(0.5);
+  constexpr int ZC = D == 3 ? 2 : 1;
+#pragma unroll
+  for (int cz = 0; cz < ZC; cz++)
+#pragma unroll
+    for (int cy = 0; cy < 2; cy++)
+#pragma unroll
+      for (int cx = 0; cx < 2; cx++) {
+        const RC w = wt[0][cx] * wt[1][cy] * wt[2][cz];
         const long long q = nb + (cx ? o1[0] : 0) + (cy ? o1[1] : 0) + (cz ? o1[2] : 0);
+#pragma unroll
         for (int i = 0; i < D; i++) acc[i] += w * ec[i * gc.N + q];
       }
+#pragma unroll
   for (int i = 0; i < D; i++) uf[i * gf.N + n] += RF(acc[i]);
 }
 
@@ -709,39 +736,31 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC 
 
 // Coarse-level moduli: full weighting of each stored component, injection
 // along an axis on whose end the coarse node sits.
+// Grid: x and y tiles of the coarse level, blockIdx.z = plane + m2 * component.
 template <typename R>
 __global__ __launch_bounds__(256) void k_coarsen(Geom gf, Geom gc, int nc, const R *__restrict__ Cf, R *__restrict__ Cc) {
-  int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
-  if (x >= gc.m[0] || y >= gc.m[1]) return;
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y;
+  const int z = blockIdx.z % gc.m[2], c = blockIdx.z / gc.m[2];
+  if (x >= gc.m[0] || y >= gc.m[1] || c >= nc) return;
   const long long n = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
   const int pf[3] = {2 * x, 2 * y, 2 * z};
   const long long nf = ((long long)pf[2] * gf.m[1] + pf[1]) * gf.m[0] + pf[0];
-  int hi[3] = {0, 0, 0};
+  R wt[3][3];
   long long off[3][3];
-  for (int a = 0; a < 3; a++) {
-    off[a][0] = off[a][1] = off[a][2] = 0;
-    if (a < gc.dim && end_of(gc, a, P[a]) == 0) {
-      hi[a] = 1;
-      off[a][0] = shift(gf, a, pf[a], -1);
-      off[a][2] = shift(gf, a, pf[a], 1);
-    }
-  }
-  for (int c = 0; c < nc; c++) {
-    R acc = R(0);
-    for (int oz = -hi[2]; oz <= hi[2]; oz++)
-      for (int oy = -hi[1]; oy <= hi[1]; oy++)
-        for (int ox = -hi[0]; ox <= hi[0]; ox++) {
-          R w = R(1);
-          if (hi[0]) w *= (ox == 0) ? R(0.5) : R(0.25);
-          if (hi[1]) w *= (oy == 0) ? R(0.5) : R(0.25);
-          if (hi[2]) w *= (oz == 0) ? R(0.5) : R(0.25);
-          acc += w * Cf[c * gf.SC + nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1]];
-        }
-    Cc[c * gc.SC + n] = acc;
-  }
+  fw_weights<R>(gc, gf, P, pf, gc.dim, wt, off);
+  const R *__restrict__ F = Cf + c * gf.SC + nf;
+  R acc = R(0);
+#pragma unroll
+  for (int oz = -1; oz <= 1; oz++)
+#pragma unroll
+    for (int oy = -1; oy <= 1; oy++)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ox++) {
+        const R w = wt[0][ox + 1] * wt[1][oy + 1] * wt[2][oz + 1];
+        acc += w * F[off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1]];
+      }
+  Cc[c * gc.SC + n] = acc;
 }
 
 // Face data of all faces (d components per face node, normal axis extent 1).
@@ -965,13 +984,19 @@ __global__ __launch_bounds__(256) void k_bottom_assemble(Geom g, const double *_
   M[r * w + nunk + q] = (r == q) ? 1.0 : 0.0;
 }
 
-// Pivot step k: choose the largest |M[i][k]|, i >= k, swap it into row k,
-// scale row k to a unit pivot.  status[0] = 1 if the pivot is zero.
-__global__ __launch_bounds__(256) void k_gj_pivot(double *__restrict__ M, int n, int k, int *status) {
+// Gauss-Jordan step k in one launch, out of place (M -> Mo, so no row is
+// read after another workgroup rewrote it): one workgroup per row finds the
+// pivot row pr of column k (largest |M[i][k]|, i >= k, lowest index on ties),
+// then writes its row of the swapped, scaled and eliminated matrix: row k =
+// M[pr] / M[pr][k]; row pr (if pr != k) and every other row i: M[i][j] -
+// M[i][k] (M[pr][j] / M[pr][k]) for j > k, column k and the columns left of it
+// unchanged (the right half ends as the inverse).  status[0] = 1 on a zero
+// pivot.
+__global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ M, double *__restrict__ Mo, int n, int k,
+                                                 int *status) {
   __shared__ double bv[256];
   __shared__ int bi[256];
-  __shared__ double piv;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, row = blockIdx.x;
   const long long w = 2LL * n;
   double best = -1.0;
   int arg = k;
@@ -989,29 +1014,18 @@ __global__ __launch_bounds__(256) void k_gj_pivot(double *__restrict__ M, int n,
     __syncthreads();
   }
   const int pr = bi[0];
-  if (pr != k)
-    for (long long j = t; j < w; j += 256) {
-      const double a = M[k * w + j];
-      M[k * w + j] = M[pr * w + j];
-      M[pr * w + j] = a;
-    }
-  __syncthreads();
-  if (t == 0) {
-    piv = M[k * w + k];
-    if (piv == 0.0) status[0] = 1;
-  }
-  __syncthreads();
+  const double piv = M[pr * w + k];
+  if (row == 0 && t == 0 && piv == 0.0) status[0] = 1;
   const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
-  for (long long j = k + t; j < w; j += 256) M[k * w + j] *= inv;
-}
-
-// Elimination step k: M[i][j] -= M[i][k] M[k][j] for i != k, j > k.
-__global__ __launch_bounds__(256) void k_gj_elim(double *__restrict__ M, int n, int k) {
-  const long long w = 2LL * n;
-  const long long j = (long long)k + 1 + (long long)blockIdx.x * 256 + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= w || i == k) return;
-  M[i * w + j] -= M[i * w + k] * M[k * w + j];
+  const int src = row == k ? pr : (row == pr ? k : row);   // row of M that lands in this row
+  const double mik = M[src * w + k];
+  for (long long j = t; j < w; j += 256) {
+    const double a = M[src * w + j];
+    double v;
+    if (row == k) v = j >= k ? a * inv : a;
+    else v = j > k ? a - mik * (M[pr * w + j] * inv) : a;
+    Mo[row * w + j] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gj_extract(const double *__restrict__ M, int n, double *__restrict__ Ainv) {
