@@ -250,7 +250,7 @@ void launch_prolong(emg_problem *p, const Level &Lc, const Level &Lf, const RC *
   if (p->D == 2)
     hipLaunchKernelGGL((k_prolong_add<2, RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
   else
-    hipLaunchKernelGGL((k_prolong_add<3, RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
+    hipLaunchKernelGGL((k_prolong3_lds<RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
 }
 
 template <typename RI, typename RO>

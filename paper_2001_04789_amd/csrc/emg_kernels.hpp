@@ -734,6 +734,70 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC 
   body_prolong<D, RC, RF>(gc, gf, ec, uf, tx_, ty_, tz_);
 }
 
+// 3D interpolation with the coarse values of a fine 64 x 4 tile staged in
+// LDS: the tile needs coarse x in [x0/2, x0/2 + 32], y in [y0/2, y0/2 + 2]
+// and planes z/2, z/2 + 1 (198 nodes), loaded once by the first 198 threads
+// instead of 8 loads per component by every fine node.  Coarse coordinates
+// wrap on periodic axes and clamp otherwise (clamped values only enter with
+// weight 0 or for fine nodes outside the grid).  The sum per fine node is
+// that of body_prolong, term by term.
+template <typename RC, typename RF>
+__global__ __launch_bounds__(256) void k_prolong3_lds(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
+                                                      const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  constexpr int CX = BX / 2 + 1, CY = BY / 2 + 1, CP = CX * CY * 2;
+  __shared__ RC sE[3][CP];
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x0 = tx_ * BX, y0 = ty_ * BY, z = tz_;
+  const int t = threadIdx.x + BX * threadIdx.y;
+  if (t < CP) {
+    const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+    int c[3] = {x0 / 2 + cx, y0 / 2 + cy, z / 2 + cz};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (gc.per[a]) c[a] %= gc.m[a];
+      else c[a] = c[a] > gc.m[a] - 1 ? gc.m[a] - 1 : c[a];
+    }
+    const long long q = ((long long)c[2] * gc.m[1] + c[1]) * gc.m[0] + c[0];
+#pragma unroll
+    for (int i = 0; i < 3; i++) sE[i][t] = ec[i * gc.N + q];
+  }
+  __syncthreads();
+  const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+  if (x >= gf.m[0] || y >= gf.m[1]) return;
+  const int p[3] = {x, y, z};
+  if (row_class(gf, p) == ROW_DIR) return;
+  const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
+  // local coarse base (threadIdx.x >> 1, threadIdx.y >> 1, 0); per axis the
+  // weights (1/2, 1/2) for an odd fine coordinate, else (1, 0)
+  RC wt[3][2];
+  int o1[3];
+  const int st[3] = {1, CX, CX * CY};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const bool odd = p[a] & 1;
+    wt[a][0] = odd ? RC(0.5) : RC(1);
+    wt[a][1] = odd ? RC(0.5) : RC(0);
+    o1[a] = odd ? st[a] : 0;
+  }
+  const int lb = (threadIdx.x >> 1) + CX * (threadIdx.y >> 1);
+  RC acc[3] = {RC(0), RC(0), RC(0)};
+#pragma unroll
+  for (int cz = 0; cz < 2; cz++)
+#pragma unroll
+    for (int cy = 0; cy < 2; cy++)
+#pragma unroll
+      for (int cx = 0; cx < 2; cx++) {
+        const RC w = wt[0][cx] * wt[1][cy] * wt[2][cz];
+        const int q = lb + (cx ? o1[0] : 0) + (cy ? o1[1] : 0) + (cz ? o1[2] : 0);
+#pragma unroll
+        for (int i = 0; i < 3; i++) acc[i] += w * sE[i][q];
+      }
+#pragma unroll
+  for (int i = 0; i < 3; i++) uf[i * gf.N + n] += RF(acc[i]);
+}
+
 // Coarse-level moduli: full weighting of each stored component, injection
 // along an axis on whose end the coarse node sits.
 // Grid: x and y tiles of the coarse level, blockIdx.z = plane + m2 * component.
