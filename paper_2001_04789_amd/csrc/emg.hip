@@ -710,6 +710,7 @@ struct Step {
   int kind, D, K;
   bool f32;
   int list;
+  bool zm = false;   // list of z-marching entries (k_batch_zm)
 };
 
 struct BatchPlan {
@@ -742,30 +743,45 @@ struct Planner {
     std::sort(groups.begin(), groups.end());
   }
 
-  // one launch per group, entries from `make(p)` for the problems it returns true for
+  // one launch per group, entries from `make(p)` for the problems it returns true for;
+  // stencil passes over levels the z-marching pass takes go to a second list
+  // of the step, launched with k_batch_zm
   template <class F>
   void step(int kind, bool f32, F make) {
+    const bool stencil = kind == BK_JACOBI || kind == BK_JACOBI_NORM || kind == BK_RESID || kind == BK_RESID_F32;
     for (auto &gr : groups) {
-      std::vector<BEnt> es;
+      std::vector<BEnt> es, zs;
       for (auto *p : probs) {
         if (p->D != gr.first || p->K != gr.second) continue;
         BEnt e{};
         if (!make(p, e)) continue;
-        if (kind == BK_JACOBI || kind == BK_JACOBI_NORM || kind == BK_RESID || kind == BK_RESID_F32) {
+        if (stencil) {
+          const int nzc = (f32 && kind != BK_RESID_F32) ? zm_plan<float>(p, e.g) : zm_plan<double>(p, e.g);
+          if (nzc > 0) {
+            const Split sp = split_of(e.g);
+            e.nzc = nzc;
+            e.gx = (int)((long long)sp.ntx * sp.nty * nzc + sp.sblocks);   // tasks
+            e.gy = e.gz = 1;
+            zs.push_back(e);
+            continue;
+          }
           e.gx = (int)stencil_blocks(e.g);   // stencil passes walk the interior/shell split
           e.gy = e.gz = 1;
         }
         es.push_back(e);
       }
-      if (es.empty()) continue;
-      long long t = 0;
-      for (auto &e : es) {
-        e.tile0 = t;
-        t += (long long)e.gx * e.gy * e.gz;
+      for (int z = 0; z < 2; z++) {
+        auto &v = z ? zs : es;
+        if (v.empty()) continue;
+        long long t = 0;
+        for (auto &e : v) {
+          e.tile0 = t;
+          t += (long long)e.gx * e.gy * e.gz;
+        }
+        plan.steps.push_back({kind, gr.first, gr.second, f32, (int)plan.lists.size(), z == 1});
+        plan.lists.push_back(std::move(v));
+        plan.sig.push_back((kind * 64 + gr.first * 8 + gr.second * 2 + (f32 ? 1 : 0)) * 2 + z);
       }
-      plan.steps.push_back({kind, gr.first, gr.second, f32, (int)plan.lists.size()});
-      plan.lists.push_back(std::move(es));
-      plan.sig.push_back(kind * 64 + gr.first * 8 + gr.second * 2 + (f32 ? 1 : 0));
     }
   }
 
@@ -1049,6 +1065,26 @@ void launch_batch_kind(hipStream_t st, int kind, bool f32, const BList *L, doubl
 #undef EMG_BK
 }
 
+// Batched z-marching pass: FP64 fills the CUs with one workgroup each, FP32
+// with two (LDS and registers); tasks are taken grid-strided.
+void launch_batch_zm(hipStream_t st, int kind, bool f32, const BList *L, double omega) {
+  const dim3 g64(256), g32(512), blk(BX, BY, 1);
+  switch (kind) {
+    case BK_JACOBI:
+    case BK_JACOBI_NORM:
+      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_JACOBI, float>), g32, blk, 0, st, L, (float)omega);
+      else hipLaunchKernelGGL((k_batch_zm<double, MODE_JACOBI, double>), g64, blk, 0, st, L, omega);
+      break;
+    case BK_RESID:
+      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_RESID, float>), g32, blk, 0, st, L, 0.0f);
+      else hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, double>), g64, blk, 0, st, L, 0.0);
+      break;
+    case BK_RESID_F32:
+      hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, float>), g64, blk, 0, st, L, 0.0);
+      break;
+  }
+}
+
 // Device copy of a plan's work lists (capacity-sized, fixed addresses).
 struct BatchDev {
   char *buf = nullptr;
@@ -1100,6 +1136,10 @@ void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, dou
     const BList *L = dev.list(s.list);
     if (s.kind < 0) {
       hipLaunchKernelGGL(k_batch_check, dim3((unsigned)std::max(check_grid, 1)), dim3(1024), 0, st, L);
+      continue;
+    }
+    if (s.zm) {
+      launch_batch_zm(st, s.kind, s.f32, L, omega);
       continue;
     }
     if (s.D == 2 && s.K == MOD_ISO) launch_batch_kind<2, MOD_ISO>(st, s.kind, s.f32, L, omega);

@@ -1369,6 +1369,7 @@ struct BEnt {
   int gx, gy, gz;        // tiles of this entry
   long long tile0;       // first global tile
   long long nparts;      // norm partials of the problem (check entries)
+  int nzc, pad2;         // z-marching entries: chunks per column (tasks = columns x nzc + shell blocks)
 };
 
 struct BList {
@@ -1423,6 +1424,39 @@ __global__ __launch_bounds__(256) void k_batch(const BList *__restrict__ L, R om
         }
       }
     }
+  }
+}
+
+// Batched z-marching stencil pass over 3D anisotropic levels of several
+// problems: tasks are the column chunks and shell blocks of each entry
+// (k_stencil_zm's workgroups), taken grid-strided by a fixed grid so one
+// captured graph serves any batch.  A workgroup finishes a task before it
+// takes the next, and no task reads LDS after its last barrier, so tasks
+// can reuse the LDS arrays.
+template <typename R, int MODE, typename TO>
+__global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_batch_zm(const BList *__restrict__ L, R omega) {
+  __shared__ R sC[21 * ZM_HP];
+  __shared__ R sU[9 * ZM_HP];
+  const int n = L->n;
+  const long long total = L->total;
+  for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L->e[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BEnt &E = L->e[lo];
+    if (E.ctl && E.ctl->done) continue;
+    const long long local = t - E.tile0;
+    const Split sp = split_of(E.g);
+    const long long nwg = (long long)sp.ntx * sp.nty * E.nzc;
+    if (local < nwg)
+      zm_column<R, MODE, TO>(E.g, sp, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega, E.partial,
+                             E.nzc, (unsigned)local, sC, sU);
+    else
+      body_stencil<3, MOD_ANISO, R, MODE, TO>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
+                                              E.partial ? E.partial + (local - nwg) : nullptr, local - nwg);
   }
 }
 
