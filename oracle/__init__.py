@@ -188,6 +188,25 @@ def stress(g: Grid, C, eps0, u):
     return out
 
 
+def von_mises(sigma):
+    """Von Mises stress sqrt(3/2 S_ij S_ij), S the deviator of the stress
+    (Sec. 4.3, von Mises definition), per node from the 3D Voigt-ordered
+    stress [11, 22, 33, 23, 31, 12] (shape (6, ...)): the full symmetric
+    tensor is rebuilt and its trace removed, written out as the definition."""
+    s = np.asarray(sigma, dtype=np.float64)
+    assert s.shape[0] == 6, "3D Voigt stress expected"
+    T = np.empty((3, 3) + s.shape[1:])
+    T[0, 0], T[1, 1], T[2, 2] = s[0], s[1], s[2]
+    T[1, 2] = T[2, 1] = s[3]
+    T[2, 0] = T[0, 2] = s[4]
+    T[0, 1] = T[1, 0] = s[5]
+    tr = T[0, 0] + T[1, 1] + T[2, 2]
+    S = T.copy()
+    for i in range(3):
+        S[i, i] = S[i, i] - tr / 3.0
+    return np.sqrt(1.5 * np.sum(S * S, axis=(0, 1)))
+
+
 def residual(g: Grid, C, u, f):
     C, u, f = _c(C), _c(u), _c(f)
     out = np.empty(g.shape(g.dim))

@@ -541,3 +541,32 @@ def test_fcycle_reaches_dense_solution(case):
     ud = oracle.dense_solve(p)
     res = oracle.solve(p, tol=1e-14, max_cycles=300, cycle="F")
     assert np.abs(res.u - ud).max() <= 1e-11 * np.abs(ud).max()
+
+
+# --------------------------------------------------------------------------
+# von Mises stress (Sec. 4.3)
+# --------------------------------------------------------------------------
+
+def test_von_mises_closed_forms():
+    """Uniaxial stress s gives |s|; pure shear t gives sqrt(3)|t|; a
+    hydrostatic state gives 0; equal and opposite normal stresses s, -s give
+    sqrt(3)|s|; the value is invariant under rotations of the stress."""
+    z = np.zeros(1)
+    def voigt(s11=0.0, s22=0.0, s33=0.0, s23=0.0, s31=0.0, s12=0.0):
+        return np.array([[s11], [s22], [s33], [s23], [s31], [s12]])
+    assert np.isclose(oracle.von_mises(voigt(s11=2.5))[0], 2.5, rtol=1e-15)
+    assert np.isclose(oracle.von_mises(voigt(s22=-1.5))[0], 1.5, rtol=1e-15)
+    for comp in ("s23", "s31", "s12"):
+        assert np.isclose(oracle.von_mises(voigt(**{comp: 0.7}))[0], np.sqrt(3) * 0.7, rtol=1e-15)
+    assert abs(oracle.von_mises(voigt(s11=3.0, s22=3.0, s33=3.0))[0]) <= 1e-15
+    assert np.isclose(oracle.von_mises(voigt(s11=1.2, s22=-1.2))[0], np.sqrt(3) * 1.2, rtol=1e-15)
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((3, 3)); T = A + A.T
+    R = synth.shoemake_rotation(rng.random(3))
+    TR = R @ T @ R.T
+    v = lambda M: np.array([[M[0, 0]], [M[1, 1]], [M[2, 2]], [M[1, 2]], [M[2, 0]], [M[0, 1]]])
+    assert np.isclose(oracle.von_mises(v(T))[0], oracle.von_mises(v(TR))[0], rtol=1e-13)
+    # the second invariant form: sqrt(1/2 [(s1-s2)^2 + (s2-s3)^2 + (s3-s1)^2]) with principal stresses
+    w = np.linalg.eigvalsh(T)
+    ref = np.sqrt(0.5 * ((w[0] - w[1]) ** 2 + (w[1] - w[2]) ** 2 + (w[2] - w[0]) ** 2))
+    assert np.isclose(oracle.von_mises(v(T))[0], ref, rtol=1e-13)
