@@ -294,6 +294,31 @@ def main():
         alt[prec] = {"cycles": sts[-1]["cycles"], "solve_ms": 1e3 * sts[-1]["solve_seconds"],
                      "solve_only_dofs_per_s": dofs / sts[-1]["solve_seconds"]}
     out["smoothing_v44"] = alt
+    # phase-field style coupling loop: a precipitate grows over 6 steps; each
+    # step re-sets moduli and eigenstrain and solves warm-started from the
+    # previous displacement, beside a cold solve of the same step
+    loop = {"steps": 6, "precision": "fp64", "warm_cycles": [], "cold_cycles": [], "warm_ms": 0.0, "cold_ms": 0.0,
+            "von_mises_max": []}
+    vm_d = torch.empty((1,) + spec.C.shape[1:], dtype=torch.float64, device=dev)
+    for t in range(6):
+        sp = synth.precipitate_step(spec, t, 6)
+        Ct = torch.from_numpy(sp.C).to(dev)
+        Et = torch.from_numpy(sp.eps0).to(dev)
+        for warm in (0, 1):
+            if warm and t:
+                prob.set_displacement(u_prev)
+            prob.set_moduli(Ct)
+            prob.set_eigenstrain(Et)
+            st = prob.solve(rtol=1e-10, max_cycles=400, warm_start=warm if t else 0)
+            key = "warm" if warm else "cold"
+            loop[key + "_cycles"].append(st["cycles"])
+            loop[key + "_ms"] += 1e3 * st["solve_seconds"]
+        u_prev = torch.from_numpy(prob.displacement()).to(dev)
+        prob.von_mises(out=vm_d)
+        loop["von_mises_max"].append(float(vm_d.max()))
+        del Ct, Et
+    loop["warm_over_cold_time"] = loop["warm_ms"] / loop["cold_ms"]
+    out["coupling_loop"] = loop
     prob.close()
     del C_d, faces_d, sigma_d
     if args.serve_requests > 0:

@@ -161,6 +161,11 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *opts, emg_solve_stats
 emg_status emg_get_displacement(emg_problem *p, double *u, int on_device);
 emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device);
 emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device);
+/* Von Mises stress sqrt(3/2 S_ij S_ij), S the deviator of the stress that
+ * emg_get_stress returns (Sec. 4.3), one value per stored node of level 0.
+ * 3D problems only (EMG_EINVAL in 2D: plane strain does not store the moduli
+ * that give sigma_33).  svm: N doubles, host or device (on_device). */
+emg_status emg_get_von_mises(emg_problem *p, double *svm, int on_device);
 emg_status emg_get_rhs(emg_problem *p, double *f, int on_device);
 
 /* ---- level-wise steps of the cycle, for verification and timing ----

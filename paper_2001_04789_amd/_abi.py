@@ -78,6 +78,7 @@ _SIGS = {
     "emg_get_displacement": ([c_void_p, c_void_p, c_int], c_int),
     "emg_set_displacement": ([c_void_p, c_void_p, c_int], c_int),
     "emg_get_stress": ([c_void_p, c_void_p, c_int], c_int),
+    "emg_get_von_mises": ([c_void_p, c_void_p, c_int], c_int),
     "emg_get_rhs": ([c_void_p, c_void_p, c_int], c_int),
     "emg_num_levels": ([c_void_p, P(c_int)], c_int),
     "emg_level_shape": ([c_void_p, c_int, P(c_int64), P(c_double)], c_int),
@@ -386,6 +387,10 @@ class Problem:
 
     def stress(self, out=None):
         return self._get(lib.emg_get_stress, 6 if self.dim == 3 else 3, out)
+
+    def von_mises(self, out=None):
+        """Von Mises stress per node (3D), shape (1, mz, my, mx) on the host."""
+        return self._get(lib.emg_get_von_mises, 1, out)
 
     def rhs(self, out=None):
         return self._get(lib.emg_get_rhs, self.dim, out)

@@ -118,7 +118,7 @@ struct emg_problem {
   Ctl *ctl = nullptr;
   Ctl *ctl_host = nullptr;
   int *status = nullptr;
-  double *sig = nullptr;
+  double *sig = nullptr, *svm = nullptr;   // stress (Voigt) and von Mises output buffers
   hipStream_t own = nullptr, stream = nullptr;
   bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
   std::vector<void *> allocs;
@@ -477,20 +477,28 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc
   if (cur != 0) launch_cast<double, double>(p, (long long)p->D * L0.g.N, L0.u64[cur], L0.u64[0], p->ctl);
 }
 
+// Level-0 buffer (u32[b]) in which the FP32 correction cycle from zero
+// leaves its result: the zero-start sweep writes buffer 0 and every further
+// sweep flips the buffer (a one-level hierarchy is solved exactly into 0).
+int mixed_result_buf(const emg_problem *p, int nu1, int nu2) {
+  return p->lv.size() == 1 ? 0 : (nu1 - 1 + nu2) & 1;
+}
+
 // One mixed-precision refinement step: u += e (the previous FP32
 // correction, zero at the start), FP64 residual written as FP32 to the
 // level-0 FP32 right-hand side with its norm, convergence check, then one
-// FP32 V-cycle (F-cycle with fcyc) for the new correction e (left in u32[0]
-// of level 0).
+// FP32 V-cycle (F-cycle with fcyc) for the new correction e, left in
+// u32[mixed_result_buf()] of level 0 where the next step reads it.
 void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc) {
   Level &L0 = p->lv[0];
   const long long nd0 = (long long)p->D * L0.g.N;
+  const int eb = mixed_result_buf(p, nu1, nu2);
   hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
-                     p->stream, nd0, L0.u64[0], L0.u32[0], p->ctl);
+                     p->stream, nd0, L0.u64[0], L0.u32[eb], p->ctl);
   launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
   launch_check(p, stencil_blocks(L0.g), 0);
   const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc);
-  if (cb != 0) launch_cast<float, float>(p, (long long)p->D * L0.g.N, L0.u32[cb], L0.u32[0], p->ctl);
+  if (cb != eb) launch_cast<float, float>(p, nd0, L0.u32[cb], L0.u32[eb], p->ctl);   // equal by construction
 }
 
 // ---- AMR helpers ----
@@ -1758,7 +1766,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
     hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, stencil_blocks(L0.g), p->ctl);
   }
-  if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[0], 0.0f);
+  if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[mixed_result_buf(p, opt.nu1, opt.nu2)], 0.0f);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(p->stream));
   const auto t1 = std::chrono::steady_clock::now();
@@ -1848,6 +1856,24 @@ emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device) {
   });
   HIPCK(hipGetLastError());
   return copy_out(p, sigma, p->sig, (size_t)p->ne * L0.g.N, on_device);
+}
+
+emg_status emg_get_von_mises(emg_problem *p, double *svm, int on_device) {
+  if (!p || !svm) return fail(EMG_EINVAL, "null argument");
+  if (p->D != 3) return fail(EMG_EINVAL, "von Mises stress is defined for 3D problems");
+  if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
+  const Level &L0 = p->lv[0];
+  const long long N = L0.g.N;
+  if (!p->sig) TRY(dalloc(p, &p->sig, (size_t)p->ne * N));
+  if (!p->svm) TRY(dalloc(p, &p->svm, (size_t)N));
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, base_u(p), p->sig);
+  });
+  hipLaunchKernelGGL(k_von_mises, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, p->stream, N, (const double *)p->sig,
+                     p->svm);
+  HIPCK(hipGetLastError());
+  return copy_out(p, svm, p->svm, (size_t)N, on_device);
 }
 
 emg_status emg_num_levels(emg_problem *p, int *levels) {

@@ -918,6 +918,20 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
   }
 }
 
+// Von Mises stress sqrt(3/2 S:S) of a 3D Voigt stress [11,22,33,23,31,12]
+// (Sec. 4.3), S the deviator: the off-diagonal entries appear twice in S:S.
+__global__ __launch_bounds__(256) void k_von_mises(long long n, const double *__restrict__ sig,
+                                                   double *__restrict__ svm) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double s11 = sig[i], s22 = sig[n + i], s33 = sig[2 * n + i];
+  const double s23 = sig[3 * n + i], s31 = sig[4 * n + i], s12 = sig[5 * n + i];
+  const double p = (s11 + s22 + s33) / 3.0;
+  const double d1 = s11 - p, d2 = s22 - p, d3 = s33 - p;
+  const double ss = d1 * d1 + d2 * d2 + d3 * d3 + 2.0 * (s23 * s23 + s31 * s31 + s12 * s12);
+  svm[i] = sqrt(1.5 * ss);
+}
+
 // Stress sigma_ij = C_ijkl (du_k/dx_l - eps0_kl): central differences, 3-point
 // one-sided on non-periodic ends; Voigt output.
 template <int D, int K>

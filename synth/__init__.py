@@ -561,29 +561,29 @@ def inclusion_3d(n: int = 33, seed: int = 0, radius: float = 0.25, eigen: float 
     return p
 
 
-def growing_precipitate(base: Problem, steps: int = 6, r0: float = 0.12, r1: float = 0.3, stiff: float = 3.0,
-                        eigen: float = 2e-3, center=(0.5, 0.5, 0.5)):
-    """Inputs of a phase-field coupling loop: a stiff, eigenstrained
-    spherical precipitate (moduli x stiff, isotropic eigenstrain `eigen`
-    inside, tanh profile of width 2h) growing from radius r0 to r1 in `steps`
-    equal increments inside the moduli of `base` (3D).  Returns one Problem
-    per step, sharing the grid, boundary conditions and face data of base."""
+def precipitate_step(base: Problem, t: int, steps: int = 6, r0: float = 0.12, r1: float = 0.3, stiff: float = 3.0,
+                     eigen: float = 2e-3, center=(0.5, 0.5, 0.5)) -> Problem:
+    """Step t of a phase-field coupling loop: a stiff, eigenstrained spherical
+    precipitate (moduli x stiff, isotropic eigenstrain `eigen` inside, tanh
+    profile of width 2h) of radius r0 + (r1 - r0) t / (steps - 1) inside the
+    moduli of `base` (3D); grid, boundary conditions and face data are base's."""
     assert base.dim == 3
     x, y, z = base.coords()
     r = np.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2 + (z - center[2]) ** 2)
-    w = 2.0 * base.h[0]
-    out = []
-    for t in range(steps):
-        rad = r0 + (r1 - r0) * t / max(1, steps - 1)
-        eta = _tanh_step((r - rad) / w)
-        q = dataclasses.replace(base, name=f"{base.name}_precipitate{t}")
-        q.C = (base.C * (1.0 + (stiff - 1.0) * eta)[None]).astype(np.float64)
-        e = eigen * eta
-        zz = np.zeros_like(e)
-        eps = np.stack([e, e, e, zz, zz, zz]).astype(np.float64)
-        q.eps0 = eps if base.eps0 is None else base.eps0 + eps
-        out.append(q)
-    return out
+    rad = r0 + (r1 - r0) * t / max(1, steps - 1)
+    eta = _tanh_step((r - rad) / (2.0 * base.h[0]))
+    q = dataclasses.replace(base, name=f"{base.name}_precipitate{t}")
+    q.C = (base.C * (1.0 + (stiff - 1.0) * eta)[None]).astype(np.float64)
+    e = eigen * eta
+    zz = np.zeros_like(e)
+    eps = np.stack([e, e, e, zz, zz, zz]).astype(np.float64)
+    q.eps0 = eps if base.eps0 is None else base.eps0 + eps
+    return q
+
+
+def growing_precipitate(base: Problem, steps: int = 6, **kw):
+    """All steps of the growing-precipitate loop (see precipitate_step)."""
+    return [precipitate_step(base, t, steps, **kw) for t in range(steps)]
 
 
 SERVE_SIZES = (33, 49, 65, 97, 129)
