@@ -540,6 +540,78 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> Amr
     return amr
 
 
+def _disc_fields(radius, width, eigen, center=(0.5, 0.5)):
+    """Moduli (lambda, mu) and eigenstrain of config 1's plane-strain disc:
+    matrix mu=1, lambda=1.5, inclusion mu=2, lambda=3, blended by a tanh
+    profile of the given width, isotropic eigenstrain `eigen` inside."""
+    def fields(x, y, z):
+        r = np.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2) + 0 * z
+        eta = _tanh_step((r - radius) / width)
+        C = np.stack([1.5 + 1.5 * eta, 1.0 + 1.0 * eta])
+        e = eigen * eta
+        return C, np.stack([e, e, np.zeros_like(e)])
+    return fields
+
+
+def eshelby_amr_2d(n0: int = 129, levels: int = 3, radius: float = 0.1, width_cells: float = 2.0,
+                   eigen: float = 1e-3) -> AmrProblem:
+    """AMR-efficiency input (the paper's 2D Eshelby example, Sec. 4.1 / the
+    AMR performance study of Sec. 5): config 1's disc (radius `radius`,
+    centre (0.5, 0.5)) on [0,1]^2 with a base grid of n0 nodes per axis and
+    levels - 1 refined boxes around the disc (one per level, ratio 2).  The
+    tanh width is width_cells cells of the finest level, so the finest level
+    resolves the interface; box k spans the disc plus a margin of two widths
+    and 4 cells of level k, which nests it in box k-1 with 2 coarse cells to
+    spare.  y = 0 clamped, other faces traction-free."""
+    h0 = 1.0 / (n0 - 1)
+    hf = h0 / 2 ** (levels - 1)
+    fields = _disc_fields(radius, width_cells * hf, eigen)
+    base = Problem(dim=2, n=(n0, n0, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+                   bc=(TRACTION, TRACTION, DIRICHLET, TRACTION, PERIODIC, PERIODIC), kind="iso", C=np.zeros(0),
+                   name=f"eshelby_amr_2d_{n0}_{levels}L")
+    x, y, z = base.coords()
+    shp = (base.m[2], base.m[1], base.m[0])
+    C, e = fields(x, y, z)
+    base.C = np.ascontiguousarray(np.broadcast_to(C, (2,) + shp)).astype(np.float64)
+    base.eps0 = np.ascontiguousarray(np.broadcast_to(e, (3,) + shp)).astype(np.float64)
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    for k in range(1, levels):
+        hk = h0 / 2 ** k
+        margin = 2.0 * width_cells * hf + 4.0 * hk
+        lo = _even_floor((0.5 - radius - margin) / hk)
+        hi = _even_ceil((0.5 + radius + margin) / hk)
+        amr.boxes.append(((lo, lo, 0), (hi, hi, 0)))
+        X, Y, Z = amr.box_coords(k)
+        mshape = (1, Y.size, X.size)
+        Ck, ek = fields(X, Y, Z)
+        amr.C.append(np.ascontiguousarray(np.broadcast_to(Ck, (2,) + mshape)).astype(np.float64))
+        amr.eps0.append(np.ascontiguousarray(np.broadcast_to(ek, (3,) + mshape)).astype(np.float64))
+        amr.b.append(None)
+    return amr
+
+
+def eshelby_uniform_2d(n0: int = 129, levels: int = 3, **kw) -> Problem:
+    """The same disc on one uniform grid at the finest resolution of
+    eshelby_amr_2d(n0, levels): (n0 - 1) 2^(levels - 1) + 1 nodes per axis."""
+    amr = eshelby_amr_2d(n0, 1, **kw) if levels == 1 else None
+    radius = kw.get("radius", 0.1)
+    width_cells = kw.get("width_cells", 2.0)
+    eigen = kw.get("eigen", 1e-3)
+    n = (n0 - 1) * 2 ** (levels - 1) + 1
+    hf = 1.0 / (n - 1)
+    fields = _disc_fields(radius, width_cells * hf, eigen)
+    p = Problem(dim=2, n=(n, n, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+                bc=(TRACTION, TRACTION, DIRICHLET, TRACTION, PERIODIC, PERIODIC), kind="iso", C=np.zeros(0),
+                name=f"eshelby_uniform_2d_{n}")
+    x, y, z = p.coords()
+    shp = (p.m[2], p.m[1], p.m[0])
+    C, e = fields(x, y, z)
+    p.C = np.ascontiguousarray(np.broadcast_to(C, (2,) + shp)).astype(np.float64)
+    p.eps0 = np.ascontiguousarray(np.broadcast_to(e, (3,) + shp)).astype(np.float64)
+    del amr
+    return p
+
+
 def inclusion_3d(n: int = 33, seed: int = 0, radius: float = 0.25, eigen: float = 1e-3) -> Problem:
     """3D spherical inclusion in an isotropic matrix (matrix mu=1, lambda=1.5;
     inclusion mu=2, lambda=3), centre jittered by up to 0.05 per axis, tanh

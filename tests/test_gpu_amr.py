@@ -168,3 +168,29 @@ def test_composite_cycle_iterates_match_oracle(emg, ctx, case, base):
         diff = max(float(np.abs(np.where(m, a - b, 0.0)).max()) for a, b, m in zip(ug, u, masks)) / scale
         print(f"[gpu] composite iterate {case} base {base} after {ncyc} cycles: max rel diff {diff:.2e}", flush=True)
         assert diff <= 1e-11
+
+
+def test_eshelby_amr_efficiency_case(emg, ctx):
+    """AMR-efficiency input (2D disc, base 33^2, two refined boxes; finest
+    resolution that of a uniform 129^2 grid): the GPU composite solution
+    satisfies the oracle's composite system, in the oracle's cycle count, and
+    its base-grid values match the uniform finest-grid GPU solution to 2 %
+    while solving 5x fewer nodes."""
+    ap = synth.eshelby_amr_2d(n0=33, levels=3)
+    comp = amr.from_problem(ap)
+    _, hist = comp.solve(tol=1e-10, max_cycles=300)
+    prob = emg.Problem.from_amr(ctx, ap)
+    st = prob.solve(rtol=1e-10, max_cycles=300)
+    u = _gpu_solution(prob, len(ap.boxes) + 1)
+    prob.close()
+    rel = comp.norm(comp.residual(u)) / comp.norm(comp.residual(comp.initial()))
+    assert st["converged"] and rel <= 1.2e-10 and abs(st["cycles"] - (len(hist) - 1)) <= 1
+    pu = synth.eshelby_uniform_2d(n0=33, levels=3)
+    pf = emg.Problem.from_spec(ctx, pu)
+    pf.solve(rtol=1e-10, max_cycles=300)
+    uf = pf.displacement()[:, :, ::4, ::4]
+    pf.close()
+    diff = float(np.abs(u[0] - uf).max() / np.abs(uf).max())
+    print(f"[gpu] eshelby AMR: cycles {st['cycles']} composite nodes {ap.composite_nodes()} vs {pu.nodes}, "
+          f"base diff vs uniform {diff:.3e}", flush=True)
+    assert diff <= 2e-2 and 5 * ap.composite_nodes() <= pu.nodes
