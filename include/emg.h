@@ -174,6 +174,12 @@ emg_status emg_get_rhs(emg_problem *p, double *f, int on_device);
  * `precision` selects double (EMG_FP64) or float (EMG_MIXED) vectors and
  * moduli.  Setup (coarsened moduli, coarsest inverse) runs on first use. */
 emg_status emg_num_levels(emg_problem *p, int *levels);
+/* Stencil pass used on a level (introspection, e.g. for tests and profiles):
+ * *chunks > 0 if stencil passes of that level in that precision (EMG_FP64
+ * for FP64 passes, EMG_MIXED for the FP32 ones) run the z-marching kernel
+ * (3D anisotropic levels large enough to give every CU a workgroup), with
+ * that many plane runs per column; 0 if they run the tile kernel. */
+emg_status emg_level_zmarch(emg_problem *p, int level, int precision, int *chunks);
 emg_status emg_level_shape(emg_problem *p, int level, int64_t m[3], double h[3]);
 /* moduli of a level (FP64, layout of emg_set_moduli), device pointer out */
 emg_status emg_level_moduli(emg_problem *p, int level, double *C_dev);

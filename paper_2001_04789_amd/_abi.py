@@ -79,6 +79,7 @@ _SIGS = {
     "emg_set_displacement": ([c_void_p, c_void_p, c_int], c_int),
     "emg_get_stress": ([c_void_p, c_void_p, c_int], c_int),
     "emg_get_von_mises": ([c_void_p, c_void_p, c_int], c_int),
+    "emg_level_zmarch": ([c_void_p, c_int, c_int, P(c_int)], c_int),
     "emg_get_rhs": ([c_void_p, c_void_p, c_int], c_int),
     "emg_num_levels": ([c_void_p, P(c_int)], c_int),
     "emg_level_shape": ([c_void_p, c_int, P(c_int64), P(c_double)], c_int),
@@ -396,6 +397,12 @@ class Problem:
         return self._get(lib.emg_get_rhs, self.dim, out)
 
     # ---- level-wise steps (device tensors) ----
+    def level_zmarch(self, level: int = 0, precision="fp64") -> int:
+        """Plane runs per column of the z-marching pass on a level (0: tile kernel)."""
+        c = c_int()
+        check(lib.emg_level_zmarch(self.handle, level, _PREC[precision], ctypes.byref(c)), "emg_level_zmarch")
+        return c.value
+
     def num_levels(self) -> int:
         n = c_int()
         check(lib.emg_num_levels(self.handle, ctypes.byref(n)), "emg_num_levels")

@@ -1876,6 +1876,15 @@ emg_status emg_get_von_mises(emg_problem *p, double *svm, int on_device) {
   return copy_out(p, svm, p->svm, (size_t)N, on_device);
 }
 
+emg_status emg_level_zmarch(emg_problem *p, int level, int precision, int *chunks) {
+  if (!p || !chunks) return fail(EMG_EINVAL, "null argument");
+  TRY(validate_level(p, level));
+  if (precision != EMG_FP64 && precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  const Geom &g = p->lv[level].g;
+  *chunks = precision == EMG_FP64 ? zm_plan<double>(p, g) : zm_plan<float>(p, g);
+  return EMG_OK;
+}
+
 emg_status emg_num_levels(emg_problem *p, int *levels) {
   if (!p || !levels) return fail(EMG_EINVAL, "null argument");
   *levels = (int)p->lv.size();
