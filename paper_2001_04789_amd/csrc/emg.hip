@@ -404,7 +404,26 @@ R *rbuf(Level &L) {
 }
 
 template <typename R>
-int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc);
+int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, bool jz_done = false);
+
+// Restriction of level l's residual to f_{l+1}; when level l+1 is not the
+// bottom, fused with its first Jacobi sweep from zero (into buffer 0), and
+// the callee's cycle from zero starts after that sweep.  Returns whether it
+// was fused.
+template <typename R>
+bool restrict_down(emg_problem *p, int l, R omega) {
+  Level &Lv = p->lv[l], &Lc = p->lv[l + 1];
+  if (l + 1 == (int)p->lv.size() - 1) {
+    launch_restrict<R, R>(p, Lv, Lc, rbuf<R>(Lv), fbuf<R>(Lc), p->ctl);
+    return false;
+  }
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_restrict_jz<D, K, R>), grid_of(Lc.g), kBlock, 0, p->stream, Lv.g, Lc.g,
+                       (const R *)rbuf<R>(Lv), fbuf<R>(Lc), moduli<R>(Lc), vbuf<R>(Lc, 0), omega, p->ctl);
+  });
+  return true;
+}
 
 // Cycle on level l for the correction of the right-hand side f_l: from zero
 // (cur < 0; the first sweep is the zero-start sweep) or from the iterate in
@@ -413,7 +432,7 @@ int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcy
 // with fcyc and cur < 0 this is the F-cycle on level l.  The bottom level is
 // solved exactly whatever the start.  Returns the buffer holding the result.
 template <typename R>
-int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, int cur = -1) {
+int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, int cur = -1, bool jz_done = false) {
   const int L = (int)p->lv.size();
   Level &Lv = p->lv[l];
   if (l == L - 1) {
@@ -422,7 +441,7 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, in
   }
   int s0 = 0;
   if (cur < 0) {
-    launch_jacobi_zero<R>(p, Lv, fbuf<R>(Lv), vbuf<R>(Lv, 0), omega, p->ctl);
+    if (!jz_done) launch_jacobi_zero<R>(p, Lv, fbuf<R>(Lv), vbuf<R>(Lv, 0), omega, p->ctl);
     cur = 0;
     s0 = 1;
   }
@@ -431,8 +450,8 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, in
     cur ^= 1;
   }
   launch_stencil<R, MODE_RESID, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), rbuf<R>(Lv), omega, nullptr, p->ctl);
-  launch_restrict<R, R>(p, Lv, p->lv[l + 1], rbuf<R>(Lv), fbuf<R>(p->lv[l + 1]), p->ctl);
-  const int cb = coarse_correction<R>(p, l + 1, nu1, nu2, omega, fcyc);
+  const bool jz = restrict_down<R>(p, l, omega);
+  const int cb = coarse_correction<R>(p, l + 1, nu1, nu2, omega, fcyc, jz);
   launch_prolong<R, R>(p, p->lv[l + 1], Lv, vbuf<R>(p->lv[l + 1], cb), vbuf<R>(Lv, cur), p->ctl);
   for (int s = 0; s < nu2; s++) {
     launch_stencil<R, MODE_JACOBI, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1), omega, nullptr, p->ctl);
@@ -446,9 +465,9 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, in
 // V-cycle's restriction overwrites f_{l+1}, which the F-cycle no longer
 // needs; f_l itself is only read).
 template <typename R>
-int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc) {
-  if (!fcyc) return coarse_cycle<R>(p, l, nu1, nu2, omega, false);
-  const int b = coarse_cycle<R>(p, l, nu1, nu2, omega, true);
+int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, bool jz_done) {
+  if (!fcyc) return coarse_cycle<R>(p, l, nu1, nu2, omega, false, -1, jz_done);
+  const int b = coarse_cycle<R>(p, l, nu1, nu2, omega, true, -1, jz_done);
   if (l == (int)p->lv.size() - 1) return b;   // exact bottom solve: the V-cycle would repeat it
   return coarse_cycle<R>(p, l, nu1, nu2, omega, false, b);
 }
@@ -467,8 +486,8 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc
     cur ^= 1;
   }
   launch_stencil<double, MODE_RESID, double>(p, L0, L0.u64[cur], L0.f64, L0.r64, omega, nullptr, p->ctl);
-  launch_restrict<double, double>(p, L0, p->lv[1], L0.r64, p->lv[1].f64, p->ctl);
-  const int cb = coarse_correction<double>(p, 1, nu1, nu2, omega, fcyc);
+  const bool jz = restrict_down<double>(p, 0, omega);
+  const int cb = coarse_correction<double>(p, 1, nu1, nu2, omega, fcyc, jz);
   launch_prolong<double, double>(p, p->lv[1], L0, p->lv[1].u64[cb], L0.u64[cur], p->ctl);
   for (int s = 0; s < nu2; s++) {
     launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);

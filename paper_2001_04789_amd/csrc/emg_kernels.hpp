@@ -613,9 +613,6 @@ __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict
   body_jacobi_zero<D, K, R>(g, C, f, out, omega, tx_, ty_, tz_);
 }
 
-// Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
-// axis on whose end the coarse node sits only the coincident fine node
-// enters; Dirichlet coarse rows get 0.
 // Per-axis full-weighting weights and fine offsets of coarse node P (fine
 // node pf = 2P): [1/4, 1/2, 1/4] on an axis along which P is not on an end,
 // else (0, 1, 0) (only the coincident fine node).  Every 3^D stencil point is
@@ -638,6 +635,9 @@ __device__ __forceinline__ void fw_weights(const Geom &gc, const Geom &gf, const
   }
 }
 
+// Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
+// axis on whose end the coarse node sits only the coincident fine node
+// enters; Dirichlet coarse rows get 0.
 template <int D, typename RI, typename RO>
 __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, const RI *__restrict__ rf,
                                               RO *__restrict__ fc, int tx, int ty, int tz) {
@@ -681,6 +681,60 @@ __global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
   body_restrict<D, RI, RO>(gf, gc, rf, fc, tx_, ty_, tz_);
+}
+
+// Restriction fused with the coarse level's first Jacobi sweep from zero
+// (x = omega f / diag, Dirichlet rows x = f = 0): the same values as
+// k_restrict followed by k_jacobi_zero, one launch instead of two.  The
+// diagonal's moduli loads are issued with the fine residual's, so the two
+// latencies overlap.
+template <int D, int K, typename R>
+__global__ __launch_bounds__(256) void k_restrict_jz(Geom gf, Geom gc, const R *__restrict__ rf, R *__restrict__ fc,
+                                                     const R *__restrict__ Cc, R *__restrict__ xc, R omega,
+                                                     const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  int tx_, ty_, tz_;
+  tile_of(tx_, ty_, tz_);
+  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  if (x >= gc.m[0] || y >= gc.m[1]) return;
+  const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
+  const int P[3] = {x, y, z};
+  const int cls = row_class(gc, P);
+  if (cls == ROW_DIR) {
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      fc[i * gc.N + nc] = R(0);
+      xc[i * gc.N + nc] = R(0);
+    }
+    return;
+  }
+  R dg[D];
+  diag_at<D, K, R>(gc, Cc, nc, P, cls, dg);
+  const int pf[3] = {2 * x, 2 * y, 2 * z};
+  const long long nf = ((long long)pf[2] * gf.m[1] + pf[1]) * gf.m[0] + pf[0];
+  R wt[3][3];
+  long long off[3][3];
+  fw_weights<R>(gc, gf, P, pf, D, wt, off);
+  R acc[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) acc[i] = R(0);
+  constexpr int ZR = D == 3 ? 1 : 0;
+#pragma unroll
+  for (int oz = -ZR; oz <= ZR; oz++)
+#pragma unroll
+    for (int oy = -1; oy <= 1; oy++)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ox++) {
+        const R w = wt[0][ox + 1] * wt[1][oy + 1] * wt[2][oz + 1];
+        const long long q = nf + off[0][ox + 1] + off[1][oy + 1] + off[2][oz + 1];
+#pragma unroll
+        for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + q];
+      }
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    fc[i * gc.N + nc] = acc[i];
+    xc[i * gc.N + nc] = omega * acc[i] / dg[i];
+  }
 }
 
 // u_fine += bilinear/trilinear interpolation of the coarse correction;
