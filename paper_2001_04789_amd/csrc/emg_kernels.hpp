@@ -925,6 +925,37 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
   double cc[NC], ec[NE];
   for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
   for (int c = 0; c < NE; c++) ec[c] = eps ? eps[c * g.N + n] : 0.0;
+  if (cls == ROW_INT) {   // neighbour moduli and eigenstrain loaded once per axis for all rows
+    double acc[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) acc[i] = b ? 0.0 - b[i * g.N + n] : 0.0;
+    if (eps) {
+#pragma unroll
+      for (int j = 0; j < D; j++) {
+        const long long sp = shift(g, j, p[j], 1), sm = shift(g, j, p[j], -1);
+        double cp[NC], cm[NC], ep[NE], em[NE];
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          cp[c] = C[c * g.SC + n + sp];
+          cm[c] = C[c * g.SC + n + sm];
+        }
+#pragma unroll
+        for (int c = 0; c < NE; c++) {
+          ep[c] = eps[c * g.N + n + sp];
+          em[c] = eps[c * g.N + n + sm];
+        }
+        const double inv2h = 0.5 / g.h[j];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          acc[i] += (c_dot_e<D, K>(cp, ec, i, j) - c_dot_e<D, K>(cm, ec, i, j)) * inv2h;
+          acc[i] += (c_dot_e<D, K>(cc, ep, i, j) - c_dot_e<D, K>(cc, em, i, j)) * inv2h;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) f[i * g.N + n] = acc[i];
+    return;
+  }
   for (int i = 0; i < D; i++) {
     double acc = 0.0;
     if (cls == ROW_DIR) {
@@ -939,25 +970,6 @@ __global__ __launch_bounds__(256) void k_rhs(Geom g, const double *__restrict__ 
       for (int a = 0; a < D; a++) {
         const int na = neumann_normal(g, a, p);
         if (na) acc += face_val(g, F, 2 * a + (na > 0), p, i);
-      }
-    } else if (cls == ROW_INT) {
-      if (b) acc -= b[i * g.N + n];
-      if (eps) {
-        for (int j = 0; j < D; j++) {
-          const long long sp = shift(g, j, p[j], 1), sm = shift(g, j, p[j], -1);
-          double cp[NC], cm[NC], ep[NE], em[NE];
-          for (int c = 0; c < NC; c++) {
-            cp[c] = C[c * g.SC + n + sp];
-            cm[c] = C[c * g.SC + n + sm];
-          }
-          for (int c = 0; c < NE; c++) {
-            ep[c] = eps[c * g.N + n + sp];
-            em[c] = eps[c * g.N + n + sm];
-          }
-          const double inv2h = 0.5 / g.h[j];
-          acc += (c_dot_e<D, K>(cp, ec, i, j) - c_dot_e<D, K>(cm, ec, i, j)) * inv2h;
-          acc += (c_dot_e<D, K>(cc, ep, i, j) - c_dot_e<D, K>(cc, em, i, j)) * inv2h;
-        }
       }
     } else {
       for (int fc = 0; fc < 2 * D; fc++) {
