@@ -419,9 +419,11 @@ __device__ __forceinline__ void rows_at(const Geom &g, const R *__restrict__ C, 
   }
 }
 
-// Diagonal coefficients only (no displacement needed).
-template <int D, int K, typename R>
-__device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, long long n, const int p[3], int cls,
+// Diagonal coefficients only (no displacement needed), in precision R from
+// moduli stored as RC (each value rounded to R first, so R = float from
+// FP64 moduli gives what the FP32 copy of the moduli gives).
+template <int D, int K, typename R, typename RC = R>
+__device__ __forceinline__ void diag_at(const Geom &g, const RC *__restrict__ C, long long n, const int p[3], int cls,
                                         R dg[D]) {
   if (cls == ROW_DIR) {
 #pragma unroll
@@ -440,7 +442,7 @@ __device__ __forceinline__ void diag_at(const Geom &g, const R *__restrict__ C, 
   constexpr int NC = nmod<D, K>();
   R cc[NC];
 #pragma unroll
-  for (int c = 0; c < NC; c++) cc[c] = C[c * g.SC + n];
+  for (int c = 0; c < NC; c++) cc[c] = R(C[c * g.SC + n]);
   if (cls == ROW_INT) {
 #pragma unroll
     for (int i = 0; i < D; i++) {

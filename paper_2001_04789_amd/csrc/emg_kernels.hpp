@@ -3,6 +3,7 @@
 // every load of a field component is a coalesced row of 64 nodes.
 #pragma once
 #include <algorithm>
+#include <type_traits>
 #include "emg_device.hpp"
 
 namespace emg {
@@ -266,11 +267,15 @@ __host__ inline int zm_chunks(const Geom &g, int target_wg) {
   return nzc >= 1 ? nzc : 0;
 }
 
+// xz (FP64 residual to FP32 only): also write the FP32 correction cycle's
+// first sweep from zero, xz = omegaf r32 / diag32 (diag32 from the moduli
+// rounded to FP32), the values k_jacobi_zero<float> would give.
 template <typename R, int MODE, typename TO>
 __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const R *__restrict__ C, const R *__restrict__ u,
                                           const R *__restrict__ f, TO *__restrict__ out, R omega,
                                           double *__restrict__ partial, int nzc, unsigned w, R *__restrict__ sC,
-                                          R *__restrict__ sU) {
+                                          R *__restrict__ sU, float *__restrict__ xz = nullptr, float omegaf = 0.0f) {
+  constexpr bool JZ = MODE == MODE_RESID && std::is_same<R, double>::value && std::is_same<TO, float>::value;
   constexpr int TX = BX, TY = BY, HX = ZM_HX, HY = ZM_HY, HP = ZM_HP, NH = ZM_NH, NC = 21, NV = 6;
   constexpr int HW = (NH + 63) / 64;   // wavefronts holding a halo position
   const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TX + tx;
@@ -394,6 +399,7 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
   // carried to the next step: rows through the y terms, the -z term, centre
   // displacement, diagonal, strain, right-hand side
   R cA[3], cM[3], cu[3], cd[3], ce[NV], cf[3];
+  float cdf[3];   // FP32 diagonal (JZ)
   auto finish = [&](int zp, const R *cz) {   // cz: moduli of plane zp + 1 at the node
     const unsigned o = plane(zp) + r0;
     double nrm = 0.0;
@@ -414,6 +420,12 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
           const R r = cf[i] - a;
           *oi = MODE == MODE_RESID ? TO(r) : TO(cu[i] + omega * r / cd[i]);
           nrm += double(r) * double(r);
+          if constexpr (JZ) {
+            if (xz) {
+              const float r32 = TO(r);
+              *(float *)((char *)(xz + i * N) + o * 4u) = omegaf * r32 / cdf[i];
+            }
+          }
         }
       }
     }
@@ -527,6 +539,13 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
       cA[i] = acc[i];
       cu[i] = uc[i];
       cd[i] = dg[i];
+      if constexpr (JZ) {   // interior-row diagonal of diag_at in FP32 from the rounded moduli
+        float s2 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+          s2 += float(cc[utri(NV, vslot<3>(i, j), vslot<3>(i, j))]) * float(1.0 / (g.h[j] * g.h[j]));
+        cdf[i] = -2.0f * s2;
+      }
     }
 #pragma unroll
     for (int a = 0; a < NV; a++) ce[a] = e[a];
@@ -564,17 +583,38 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom
                                                                            const R *__restrict__ f,
                                                                            TO *__restrict__ out, R omega,
                                                                            double *__restrict__ partial,
-                                                                           const Ctl *__restrict__ ctl, int nzc) {
+                                                                           const Ctl *__restrict__ ctl, int nzc,
+                                                                           float *__restrict__ xz = nullptr,
+                                                                           float omegaf = 0.0f) {
   if (skip(ctl)) return;
   __shared__ R sC[21 * ZM_HP];
   __shared__ R sU[9 * ZM_HP];
   const Split sp = split_of(g);
   const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
   if (blockIdx.x < nwg) {
-    zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU);
+    zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU, xz, omegaf);
   } else {
     const long long t = blockIdx.x - nwg;
     body_stencil<3, MOD_ANISO, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
+    if constexpr (MODE == MODE_RESID && std::is_same<R, double>::value && std::is_same<TO, float>::value) {
+      if (xz) {   // first FP32 sweep from zero on the shell nodes of this block (as k_jacobi_zero<float>)
+        const long long s = t * 256 + threadIdx.x + BX * threadIdx.y;
+        if (s < sp.shell) {
+          int p[3];
+          shell_node(g, sp, s, p);
+          const long long n = ((long long)p[2] * g.m[1] + p[1]) * g.m[0] + p[0];
+          const int cls = row_class(g, p);
+          float dg[3];
+          diag_at<3, MOD_ANISO, float, double>(g, C, n, p, cls, dg);
+#pragma unroll
+          for (int i = 0; i < 3; i++) {
+            const long long q = i * g.N + n;
+            const float f32 = out[q];   // this thread's own store
+            xz[q] = (cls == ROW_DIR) ? f32 : omegaf * f32 / dg[i];
+          }
+        }
+      }
+    }
   }
 }
 
