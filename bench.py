@@ -254,6 +254,7 @@ def main():
     ms_sweep = prob.kernel_time(0, level=0, precision="fp64", reps=args.kernel_reps)
     nodes = spec.nodes
     bytes_per_launch = 240 * nodes
+    nzc = prob.level_zmarch(0, "fp64")
     achieved = bytes_per_launch / (ms_sweep * 1e-3) / 1e9
     ms_sweep32 = prob.kernel_time(0, level=0, precision="mixed", reps=args.kernel_reps) if not args.no_mixed else None
 
@@ -281,7 +282,8 @@ def main():
                  "setup_ms": 1e3 * float(np.mean([s["setup_seconds"] for s in st64]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(),
-                     "kernel": "k_stencil<3,ANISO,double,JACOBI> finest level",
+                     "kernel": (f"k_stencil_zm<double,JACOBI> finest level (z-marching pass, {nzc} plane runs "
+                                f"per column)" if nzc else "k_stencil<3,ANISO,double,JACOBI> finest level"),
                      "avg_ms": ms_sweep, "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_mixed:
