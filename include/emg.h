@@ -287,9 +287,11 @@ emg_status emg_amr_set_displacement(emg_problem *p, int level, const double *u, 
 emg_status emg_amr_residual(emg_problem *p, int level, double *r_dev, double *norm);
 
 /* Average duration in milliseconds of one launch of a cycle kernel on the
- * problem's stream, measured with HIP events around `reps` back-to-back
- * launches in the launch configuration the solve uses.  kernel: 0 = Jacobi
- * sweep, 1 = residual with full-weighting restriction, 2 = interpolation. */
+ * problem's stream: `reps` back-to-back launches in the launch configuration
+ * the solve uses are captured into one HIP graph (as the solve's cycles are),
+ * replayed once untimed and once between two HIP events.  kernel: 0 = Jacobi
+ * sweep, 1 = residual with full-weighting restriction, 2 = interpolation.
+ * EMG_EINVAL for reps < 1, an unknown kernel or a missing coarser level. */
 emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms);
 
 #ifdef __cplusplus

@@ -2041,18 +2041,31 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
         launch_prolong<float, float>(p, p->lv[level + 1], L, p->lv[level + 1].u32[0], L.u32[1], nullptr);
     }
   };
+  // The launches are captured into one graph, as the solve's cycles are, and
+  // the graph is replayed once untimed and once between the two events.
   one();  // warm
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
-  HIPCK(hipEventRecord(e0, p->stream));
+  hipGraph_t graph;
+  HIPCK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
   for (int r = 0; r < reps; r++) one();
-  HIPCK(hipEventRecord(e1, p->stream));
-  HIPCK(hipEventSynchronize(e1));
+  HIPCK(hipStreamEndCapture(p->stream, &graph));
+  hipGraphExec_t exec;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(EMG_EDEVICE, "graph instantiate");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   float ms = 0.f;
-  HIPCK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(e0, p->stream);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, p->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return fail(EMG_EDEVICE, hipGetErrorString(e));
   *avg_ms = ms / reps;
   return finish(p);
 }

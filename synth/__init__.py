@@ -612,6 +612,105 @@ def eshelby_uniform_2d(n0: int = 129, levels: int = 3, **kw) -> Problem:
     return p
 
 
+def ellipsoid_eta(x, y, z, axes, width):
+    """Diffuse indicator of the ellipsoid x^T A x <= 1, A = diag(a_i^-2), for
+    the Eshelby example of Sec. 4.1 (its error-function mollification):
+    eta = (1 - erf((x^T A x - 1) / (2 width |A x|))) / 2, 1 inside and 0
+    outside.  Readings: A holds the inverse squared semi-axes and the
+    argument carries the "- 1" that puts the transition on the surface;
+    eta = 1 marks the eigenstrained interior."""
+    from scipy.special import erf
+    a = [float(v) for v in axes]
+    q = (x / a[0]) ** 2 + (y / a[1]) ** 2 + (z / a[2]) ** 2
+    g = np.sqrt((x / a[0] ** 2) ** 2 + (y / a[1] ** 2) ** 2 + (z / a[2] ** 2) ** 2)
+    g = np.maximum(g, 1e-300)
+    return 0.5 * (1.0 - erf((q - 1.0) / (2.0 * width * g)))
+
+
+def eshelby_ellipsoid_amr(n0: int = 33, levels: int = 5, L: float = 4.0, axes=(1.0, 0.75, 0.5), E: float = 210.0,
+                          nu: float = 0.3, eigen: float = 1e-3, width: float = 0.1, tag: float = 0.01,
+                          far_field: bool = True, phys_boxes=None) -> AmrProblem:
+    """The Eshelby inclusion of Sec. 4.1: an ellipsoid with semi-axes `axes`
+    centred in [-L, L]^3, one isotropic material (E, nu) everywhere and the
+    dilatational eigenstrain eigen * eta * I with eta from ellipsoid_eta
+    (diffuse width `width`).  Base grid n0 nodes per axis, levels - 1 boxes
+    (ratio 2): box k is the bounding box of the level-(k-1) nodes tagged by
+    |grad eta| |dx| > tag (|dx| the length of the vector of grid spacings,
+    sqrt(3) h), grown by two coarse cells and kept two coarse cells inside
+    box k-1 (with phys_boxes, a list of ((xlo, ylo, zlo), (xhi, yhi, zhi)),
+    box k is instead the given region, whose bounds must fall on even nodes
+    of level k).  Every face is Dirichlet: with far_field the displacement of
+    the equivalent centre of dilatation, u = (1+nu)/(1-nu) eigen V x /
+    (4 pi r^3) with V the ellipsoid's volume (the exterior field's leading
+    term at large r), else zero."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    base = Problem(dim=3, n=(n0, n0, n0), lo=(-L, -L, -L), hi=(L, L, L), bc=(DIRICHLET,) * 6, kind="iso",
+                   C=np.zeros(0), name=f"eshelby_ellipsoid_{n0}_{levels}L_w{width:g}")
+
+    def fields(X, Y, Z):
+        eta = ellipsoid_eta(X, Y, Z, axes, width)
+        shp = eta.shape
+        C = np.stack([np.full(shp, lam), np.full(shp, mu)])
+        e = eigen * eta
+        return C, np.stack([e, e, e, np.zeros(shp), np.zeros(shp), np.zeros(shp)])
+
+    x, y, z = base.coords()
+    X, Y, Z = np.broadcast_arrays(x, y, z)
+    base.C, base.eps0 = (np.ascontiguousarray(v) for v in fields(X, Y, Z))
+    vol = 4.0 / 3.0 * np.pi * float(np.prod(axes))
+    amp = (1.0 + nu) / (1.0 - nu) * eigen * vol / (4.0 * np.pi) if far_field else 0.0
+    for f in range(6):
+        sl = [slice(None)] * 3
+        sl[2 - f // 2] = slice(0, 1) if f % 2 == 0 else slice(base.m[2 - f // 2] - 1, base.m[2 - f // 2])
+        Xf, Yf, Zf = X[tuple(sl)], Y[tuple(sl)], Z[tuple(sl)]
+        r3 = np.sqrt(Xf ** 2 + Yf ** 2 + Zf ** 2) ** 3
+        base.face[f] = np.ascontiguousarray(np.stack([amp * Xf / r3, amp * Yf / r3, amp * Zf / r3]))
+
+    def grad_eta(X, Y, Z, h):
+        g = 0.0
+        for dx, dy, dz in ((h, 0, 0), (0, h, 0), (0, 0, h)):
+            g = g + ((ellipsoid_eta(X + dx, Y + dy, Z + dz, axes, width)
+                      - ellipsoid_eta(X - dx, Y - dy, Z - dz, axes, width)) / (2 * h)) ** 2
+        return np.sqrt(g)
+
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    prev = ((0, 0, 0), tuple(m - 1 for m in base.m))
+    nlev = levels if phys_boxes is None else len(phys_boxes) + 1
+    for k in range(1, nlev):
+        if phys_boxes is not None:
+            hk = amr.level_h(k)[0]
+            lo = [int(round((phys_boxes[k - 1][0][a] - base.lo[a]) / hk)) for a in range(3)]
+            hi = [int(round((phys_boxes[k - 1][1][a] - base.lo[a]) / hk)) for a in range(3)]
+            if any(v % 2 for v in lo + hi):
+                raise ValueError("box bounds must fall on even nodes of their level")
+        else:
+            h_prev = amr.level_h(k - 1)[0]
+            lo_p, hi_p = prev
+            idx = [np.arange(lo_p[a], hi_p[a] + 1) for a in range(3)]
+            Xc = base.lo[0] + h_prev * idx[0][None, None, :]
+            Yc = base.lo[1] + h_prev * idx[1][None, :, None]
+            Zc = base.lo[2] + h_prev * idx[2][:, None, None]
+            tagged = grad_eta(Xc, Yc, Zc, h_prev) * np.sqrt(3.0) * h_prev > tag
+            if not tagged.any():
+                break
+            zz, yy, xx = np.nonzero(tagged)
+            t_lo = [idx[0][xx.min()], idx[1][yy.min()], idx[2][zz.min()]]
+            t_hi = [idx[0][xx.max()], idx[1][yy.max()], idx[2][zz.max()]]
+            lo, hi = [], []
+            for a in range(3):
+                lo.append(max(_even_floor(2 * (t_lo[a] - 2)), 2 * (lo_p[a] + 2)))
+                hi.append(min(_even_ceil(2 * (t_hi[a] + 2)), 2 * (hi_p[a] - 2)))
+        amr.boxes.append((tuple(lo), tuple(hi)))
+        Xk, Yk, Zk = np.broadcast_arrays(*amr.box_coords(k))
+        Ck, ek = fields(Xk, Yk, Zk)
+        amr.C.append(np.ascontiguousarray(Ck))
+        amr.eps0.append(np.ascontiguousarray(ek))
+        amr.b.append(None)
+        prev = (tuple(lo), tuple(hi))
+    return amr
+
+
 def inclusion_3d(n: int = 33, seed: int = 0, radius: float = 0.25, eigen: float = 1e-3) -> Problem:
     """3D spherical inclusion in an isotropic matrix (matrix mu=1, lambda=1.5;
     inclusion mu=2, lambda=3), centre jittered by up to 0.05 per axis, tanh

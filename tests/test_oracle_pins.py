@@ -570,3 +570,70 @@ def test_von_mises_closed_forms():
     w = np.linalg.eigvalsh(T)
     ref = np.sqrt(0.5 * ((w[0] - w[1]) ** 2 + (w[1] - w[2]) ** 2 + (w[2] - w[0]) ** 2))
     assert np.isclose(oracle.von_mises(v(T))[0], ref, rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Eshelby tensor of an ellipsoid (Sec. 4.1 verification problem)
+# --------------------------------------------------------------------------
+
+def test_eshelby_tensor_sphere_values():
+    """A sphere gives the textbook values S_1111 = (7-5nu)/(15(1-nu)),
+    S_1122 = (5nu-1)/(15(1-nu)), S_1212 = (4-5nu)/(15(1-nu)), the same on
+    every axis, and S_1123 = 0."""
+    from oracle import eshelby
+    for nu in (0.0, 0.25, 0.3, 0.45):
+        S = eshelby.eshelby_tensor([0.7, 0.7, 0.7], nu)
+        d = 15.0 * (1.0 - nu)
+        for i in range(3):
+            assert np.isclose(S[i, i, i, i], (7 - 5 * nu) / d, rtol=1e-12, atol=0)
+            for j in range(3):
+                if j != i:
+                    assert np.isclose(S[i, i, j, j], (5 * nu - 1) / d, rtol=1e-11, atol=1e-14)
+                    assert np.isclose(S[i, j, i, j], (4 - 5 * nu) / d, rtol=1e-12, atol=0)
+                    assert S[i, j, i, j] == S[j, i, i, j]
+        assert S[0, 0, 1, 2] == 0.0 and S[0, 1, 2, 2] == 0.0
+
+
+def test_eshelby_tensor_elliptic_cylinder_limit():
+    """a3 -> infinity gives the elliptic cylinder's closed form (semi-axes
+    a1, a2 in the cross-section): S_1111 = [(a2^2 + 2 a1 a2)/(a1+a2)^2 +
+    (1-2nu) a2/(a1+a2)] / (2(1-nu)), S_1122 = [a2^2/(a1+a2)^2 - (1-2nu)
+    a2/(a1+a2)] / (2(1-nu)), S_1212 = [(a1^2+a2^2)/(2(a1+a2)^2) +
+    (1-2nu)/2] / (2(1-nu)), S_1133 = nu a2 / ((1-nu)(a1+a2)), S_33kk = 0."""
+    from oracle import eshelby
+    nu, a1, a2 = 0.3, 1.0, 0.6
+    S = eshelby.eshelby_tensor([a1, a2, 1e6], nu)
+    k, s = 1.0 / (2.0 * (1.0 - nu)), a1 + a2
+    assert np.isclose(S[0, 0, 0, 0], k * ((a2 ** 2 + 2 * a1 * a2) / s ** 2 + (1 - 2 * nu) * a2 / s), rtol=1e-8)
+    assert np.isclose(S[1, 1, 1, 1], k * ((a1 ** 2 + 2 * a1 * a2) / s ** 2 + (1 - 2 * nu) * a1 / s), rtol=1e-8)
+    assert np.isclose(S[0, 0, 1, 1], k * (a2 ** 2 / s ** 2 - (1 - 2 * nu) * a2 / s), rtol=1e-7)
+    assert np.isclose(S[1, 1, 0, 0], k * (a1 ** 2 / s ** 2 - (1 - 2 * nu) * a1 / s), rtol=1e-7)
+    assert np.isclose(S[0, 1, 0, 1], k * ((a1 ** 2 + a2 ** 2) / (2 * s ** 2) + (1 - 2 * nu) / 2), rtol=1e-8)
+    assert np.isclose(S[0, 0, 2, 2], nu * a2 / ((1 - nu) * s), rtol=1e-8)
+    assert np.isclose(S[1, 1, 2, 2], nu * a1 / ((1 - nu) * s), rtol=1e-8)
+    assert abs(S[2, 2, 2, 2]) < 1e-8 and abs(S[2, 2, 0, 0]) < 1e-8
+
+
+def test_eshelby_potential_integrals_prolate_and_identities():
+    """Prolate spheroid a1 > a2 = a3: I_2 = I_3 = 2 pi a1 a3^2 /
+    (a1^2 - a3^2)^(3/2) [(a1/a3)(a1^2/a3^2 - 1)^(1/2) - arccosh(a1/a3)],
+    I_1 = 4 pi - 2 I_2.  Any ellipsoid: I_1 + I_2 + I_3 = 4 pi,
+    3 I_11 + I_12 + I_13 = 4 pi / a1^2, and the dilatation inside for a
+    dilatational eigenstrain does not depend on the shape:
+    S_iikk = (1+nu)/(1-nu)."""
+    from oracle import eshelby
+    a1, a3 = 2.0, 0.8
+    I, II = eshelby.potential_integrals([a1, a3, a3])
+    I2 = 2 * np.pi * a1 * a3 ** 2 / (a1 ** 2 - a3 ** 2) ** 1.5 * (
+        (a1 / a3) * np.sqrt(a1 ** 2 / a3 ** 2 - 1) - np.arccosh(a1 / a3))
+    assert np.isclose(I[1], I2, rtol=1e-12) and np.isclose(I[2], I2, rtol=1e-12)
+    assert np.isclose(I[0], 4 * np.pi - 2 * I2, rtol=1e-12)
+    for a in ([1.0, 0.75, 0.5], [0.3, 1.7, 0.9]):
+        I, II = eshelby.potential_integrals(a)
+        assert np.isclose(I.sum(), 4 * np.pi, rtol=1e-12)
+        for i in range(3):
+            assert np.isclose(3 * II[i, i] + sum(II[i, j] for j in range(3) if j != i), 4 * np.pi / a[i] ** 2,
+                              rtol=1e-11)
+        for nu in (0.2, 0.3):
+            S = eshelby.eshelby_tensor(a, nu)
+            assert np.isclose(np.einsum("iikk", S), (1 + nu) / (1 - nu), rtol=1e-12)
