@@ -432,8 +432,12 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
     if (partial)
       block_sum_256(nrm, partial + sp.sblocks + ((long long)(zp - sp.lo[2]) * sp.nty + cy) * sp.ntx + cx);
   };
+  // FP64 issues the next plane's displacement and right-hand side first (its
+  // moduli follow in three groups); FP32 issues them last
+  constexpr bool UF_FIRST = sizeof(R) == 8;
   for (int z = zs; z < ze; z++) {
     const int zc = z + 1, zu = z + 2 <= ze ? z + 2 : ze;
+    if constexpr (UF_FIRST) issue(zc, zu, z, 3);
     issue(zc, zu, z, 0);
     __builtin_amdgcn_sched_barrier(0);
     R uc[3], up[3][3], um[3][3], upp[3][3], upm[3][3], ump[3][3], umm[3][3];
@@ -511,7 +515,7 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < 2; j++) {   // x and y modulus rows of the LDS neighbours
-      if (j == 1) {
+      if (j == 1 && !UF_FIRST) {
         __builtin_amdgcn_sched_barrier(0);
         issue(zc, zu, z, 3);
         __builtin_amdgcn_sched_barrier(0);
