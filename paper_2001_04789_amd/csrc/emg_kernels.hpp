@@ -432,8 +432,10 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
     if (partial)
       block_sum_256(nrm, partial + sp.sblocks + ((long long)(zp - sp.lo[2]) * sp.nty + cy) * sp.ntx + cx);
   };
-  // FP64 issues the next plane's displacement and right-hand side first (its
-  // moduli follow in three groups); FP32 issues them last
+  // Order of the next plane's load groups (measured): FP64 issues the
+  // displacement and right-hand side with the first moduli and the halo
+  // moduli last, after the y rows; FP32 issues the halo moduli after the
+  // centre rows and the displacement and right-hand side last.
   constexpr bool UF_FIRST = sizeof(R) == 8;
   for (int z = zs; z < ze; z++) {
     const int zc = z + 1, zu = z + 2 <= ze ? z + 2 : ze;
@@ -510,9 +512,11 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
       acc[i] = a2;
       dg[i] = R(-2) * d2;
     }
-    __builtin_amdgcn_sched_barrier(0);
-    issue(zc, zu, z, 2);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!UF_FIRST) {
+      __builtin_amdgcn_sched_barrier(0);
+      issue(zc, zu, z, 2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int j = 0; j < 2; j++) {   // x and y modulus rows of the LDS neighbours
       if (j == 1 && !UF_FIRST) {
@@ -532,6 +536,11 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
           acc[i] += (s == 0 ? sg : -sg) * i2h[j];
         }
       }
+    }
+    if constexpr (UF_FIRST) {
+      __builtin_amdgcn_sched_barrier(0);
+      issue(zc, zu, z, 2);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
