@@ -282,8 +282,8 @@ def main():
                  "setup_ms": 1e3 * float(np.mean([s["setup_seconds"] for s in st64]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": sweep_traffic(),
-                     "kernel": (f"k_stencil_zm<double,JACOBI> finest level (z-marching pass, {nzc} plane runs "
-                                f"per column)" if nzc else "k_stencil<3,ANISO,double,JACOBI> finest level"),
+                     "kernel": ("k_stencil_zm<double,JACOBI> finest level (z-marching pass)" if nzc
+                                else "k_stencil<3,ANISO,double,JACOBI> finest level"),
                      "avg_ms": ms_sweep, "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_mixed:

@@ -255,16 +255,30 @@ __global__ __launch_bounds__(256, 2) void k_stencil(Geom g, const R *__restrict_
 // of the interior tiles of body_stencil, bit for bit.
 constexpr int ZM_HX = BX + 2, ZM_HY = BY + 2, ZM_HP = ZM_HX * ZM_HY, ZM_NH = ZM_HP - BX * BY;
 
-// Workgroups of a z-marching pass: columns x chunks, or 0 if the level is
-// better served by body_stencil (fewer than 8 planes per chunk).
+// Chunks per column of a z-marching pass (workgroups = columns x chunks), or
+// 0 if the level is better served by body_stencil (fewer than 8 planes per
+// chunk).  target_wg workgroups are resident at once; the count minimises
+// rounds x (planes per chunk + 7), the 7 standing for a chunk's priming and a
+// round's ramp and tail (measured on 97^3, 129^3, 193^3 and 257^3 levels: a
+// part-filled last round costs as much as a full one, and every chunk start
+// re-reads two planes).  All columns share the chunk boundaries, so the
+// workgroups of a round march level with one another.
 __host__ inline int zm_chunks(const Geom &g, int target_wg) {
   if (g.dim != 3) return 0;
   const Split sp = split_of(g);
   if (sp.inner == 0) return 0;
   const long long cols = (long long)sp.ntx * sp.nty;
-  int nzc = (int)std::max<long long>(1, (target_wg + cols / 2) / cols);
-  nzc = std::min(nzc, sp.ntz / 8);
-  return nzc >= 1 ? nzc : 0;
+  int best = 0;
+  long long best_cost = 0;
+  for (int nzc = 1; nzc <= sp.ntz / 8; nzc++) {
+    const long long rounds = (cols * nzc + target_wg - 1) / target_wg;
+    const long long cost = rounds * ((sp.ntz + nzc - 1) / nzc + 7);
+    if (best == 0 || cost < best_cost) {
+      best = nzc;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 // xz (FP64 residual to FP32 only): also write the FP32 correction cycle's
