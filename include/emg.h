@@ -259,7 +259,9 @@ emg_status emg_server_destroy(emg_server *s);
  * off periodic axes.  Level-k fields are laid out over the box grown by one
  * ghost node per side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x]
  * (EMG_EINVAL for bounds that break these rules or a box of 2^29 or more
- * stored nodes).  Composite system solved by emg_solve (FP64 only):
+ * stored nodes).  Composite system solved by emg_solve (EMG_FP64: composite
+ * cycles in FP64; EMG_MIXED: FP64 state, composite residual, convergence test
+ * and update around an FP32 composite correction cycle):
  *   - unknowns: valid nodes of every box plus the coarser nodes not covered by
  *     the next finer box; a covered coarse node takes the coincident fine
  *     value (App. A, phi_c2 = phi_f4);

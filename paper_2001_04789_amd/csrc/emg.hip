@@ -79,6 +79,9 @@ struct Fine {
   double *C = nullptr, *eps = nullptr, *body = nullptr;
   double *f = nullptr, *u = nullptr, *rr = nullptr, *t = nullptr;
   double *e[2] = {nullptr, nullptr};
+  // FP32 correction cycle of mixed precision: moduli copy, residual, scratch, corrections
+  float *C32 = nullptr, *rr32 = nullptr, *t32 = nullptr;
+  float *e32[2] = {nullptr, nullptr};
   bool moduli_set = false;
 };
 
@@ -336,14 +339,18 @@ emg_status setup(emg_problem *p) {
   HIPCK(hipStreamSynchronize(p->stream));
   if (st) return fail(EMG_EINVAL, "coarsest-level operator is singular");
   p->setup_done = true;
+  p->mixed_ready = false;   // the FP32 copies follow the moduli setup just wrote
   return EMG_OK;
 }
 
 emg_status ensure_mixed(emg_problem *p) {
   if (p->mixed_ready) return EMG_OK;
-  if (!p->lv[0].C32 && p->ctx) {   // first use: charge the FP32 copies to the context's budget
-    size_t extra = 0;
+  size_t extra = 0;   // first use: charge the FP32 copies to the context's budget
+  if (!p->lv[0].C32)
     for (auto &L : p->lv) extra += ((size_t)L.g.SC * p->nc + (size_t)L.g.N * 4 * p->D) * sizeof(float);
+  for (auto &F : p->fine)
+    if (!F.C32) extra += ((size_t)F.g.SC * p->nc + (size_t)F.g.N * 4 * p->D) * sizeof(float);
+  if (extra && p->ctx) {
     std::lock_guard<std::mutex> lk(p->ctx->mu);
     if (p->ctx->budget && p->ctx->in_use + extra > p->ctx->budget)
       return fail(EMG_ENOMEM, "HBM budget exceeded by the FP32 copies of mixed precision");
@@ -360,6 +367,17 @@ emg_status ensure_mixed(emg_problem *p) {
       TRY(dalloc(p, &L.r32, nd));
     }
     launch_cast<double, float>(p, (long long)p->nc * L.g.SC, L.C64, L.C32, nullptr);
+  }
+  for (auto &F : p->fine) {   // refined boxes: their moduli after setup's averaging
+    const long long nd = (long long)p->D * F.g.N;
+    if (!F.C32) {
+      TRY(dalloc(p, &F.C32, (size_t)p->nc * F.g.SC));
+      TRY(dalloc(p, &F.rr32, nd));
+      TRY(dalloc(p, &F.t32, nd));
+      TRY(dalloc(p, &F.e32[0], nd));
+      TRY(dalloc(p, &F.e32[1], nd));
+    }
+    launch_cast<double, float>(p, (long long)p->nc * F.g.SC, F.C, F.C32, nullptr);
   }
   HIPCK(hipGetLastError());
   p->mixed_ready = true;
@@ -548,6 +566,7 @@ Level box_level(const Fine &F) {
   Level L;
   L.g = F.g;
   L.C64 = F.C;
+  L.C32 = F.C32;
   return L;
 }
 
@@ -668,11 +687,81 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
   }
 }
 
+// Mixed-precision composite cycle: the state, its sync, the composite
+// residual and convergence check and the final update stay FP64; the
+// correction (fine relaxations, coarse/fine residual transfer, base V-cycle
+// with its FP64 bottom solve, interpolation) runs in FP32 from the residuals
+// rounded to FP32 -- the iterative-refinement split of the single-level
+// mixed iteration applied to the composite system.
+template <int D>
+void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool fcyc) {
+  Level &L0 = p->lv[0];
+  const int Lf = (int)p->fine.size();
+  amr_sync<D>(p, p->amr_u0, p->ctl);
+  amr_residual<D>(p, p->ctl);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(1024), 0, p->stream, p->amr_partial, p->amr_nparts, p->ctl, 0);
+  launch_cast<double, float>(p, (long long)p->D * L0.g.N, L0.f64, L0.f32, p->ctl);
+  for (auto &F : p->fine) launch_cast<double, float>(p, (long long)p->D * F.g.N, F.rr, F.rr32, p->ctl);
+  std::vector<int> cur(Lf + 1, 0);
+  for (int k = Lf; k >= 1; k--) {
+    Fine &F = p->fine[k - 1];
+    Level B = box_level(F);
+    hipLaunchKernelGGL((k_ghost_fill<D, float>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr32, 0.0f, p->ctl);
+    launch_jacobi_zero<float>(p, B, F.rr32, F.e32[0], omega, p->ctl);
+    int c = 0;
+    for (int s = 1; s < nu1; s++) {
+      launch_stencil<float, MODE_JACOBI, float>(p, B, F.e32[c], F.rr32, F.e32[c ^ 1], omega, nullptr, p->ctl);
+      c ^= 1;
+    }
+    cur[k] = c;
+    launch_stencil<float, MODE_RESID, float>(p, B, F.e32[c], F.rr32, F.t32, 0.0f, nullptr, p->ctl);
+    const Geom &gc = parent_geom(p, k);
+    const int3 co = parent_origin(p, k);
+    float *rrc = k == 1 ? L0.f32 : p->fine[k - 2].rr32;
+    const float *Cc = k == 1 ? L0.C32 : p->fine[k - 2].C32;
+    dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+      constexpr int DD = decltype(Dc)::value, K = decltype(Kc)::value;
+      hipLaunchKernelGGL((k_cf_update<DD, K, float>), covered_grid(p, F.b, 1), kBlock, 0, p->stream, gc, co, F.g, F.b,
+                         Cc, (const float *)F.e32[c], rrc, p->ctl);
+    });
+    hipLaunchKernelGGL((k_restrict_cf<D, float>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b,
+                       (const float *)F.t32, gc, co, rrc, p->ctl);
+  }
+  const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc);
+  for (int k = 1; k <= Lf; k++) {
+    Fine &F = p->fine[k - 1];
+    Level B = box_level(F);
+    const float *ec = k == 1 ? L0.u32[cb] : p->fine[k - 2].e32[cur[k - 1]];
+    int c = cur[k];
+    hipLaunchKernelGGL((k_interp<D, float>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, ec, F.e32[c], F.rr32, 2, p->ctl);
+    for (int s = 0; s < nu2; s++) {
+      launch_stencil<float, MODE_JACOBI, float>(p, B, F.e32[c], F.rr32, F.e32[c ^ 1], omega, nullptr, p->ctl);
+      c ^= 1;
+    }
+    cur[k] = c;
+  }
+  const long long nd0 = (long long)p->D * L0.g.N;
+  hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
+                     p->stream, nd0, p->amr_u0, (const float *)L0.u32[cb], p->ctl);
+  for (int k = 1; k <= Lf; k++) {
+    Fine &F = p->fine[k - 1];
+    const long long nd = (long long)p->D * F.g.N;
+    hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd + 255) / 256, 8192)), dim3(256), 0,
+                       p->stream, nd, F.u, (const float *)F.e32[cur[k]], p->ctl);
+  }
+}
+
 void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, bool fcyc) {
   if (!p->fine.empty()) {
     for (int c = 0; c < k; c++) {
-      if (p->D == 2) record_amr_cycle<2>(p, nu1, nu2, omega, fcyc);
-      else record_amr_cycle<3>(p, nu1, nu2, omega, fcyc);
+      if (prec == EMG_MIXED) {
+        if (p->D == 2) record_amr_cycle_mixed<2>(p, nu1, nu2, (float)omega, fcyc);
+        else record_amr_cycle_mixed<3>(p, nu1, nu2, (float)omega, fcyc);
+      } else {
+        if (p->D == 2) record_amr_cycle<2>(p, nu1, nu2, omega, fcyc);
+        else record_amr_cycle<3>(p, nu1, nu2, omega, fcyc);
+      }
     }
     return;
   }
@@ -1743,8 +1832,6 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   emg_default_opts(&opt);
   if (o) opt = *o;
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
-  if (!p->fine.empty() && opt.precision != EMG_FP64)
-    return fail(EMG_EINVAL, "refined levels are solved in FP64 only");
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
   if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
   if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
@@ -2348,7 +2435,7 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
   TRY(dalloc(p, &p->amr_partial, (size_t)parts));
   p->amr_nparts = parts;
   destroy_graphs(p);
-  p->setup_done = p->rhs_ready = false;
+  p->setup_done = p->rhs_ready = p->mixed_ready = false;
   HIPCK(hipStreamSynchronize(p->stream));
   return EMG_OK;
 }

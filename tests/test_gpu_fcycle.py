@@ -101,6 +101,12 @@ def test_amr_with_fcycle_base(emg, ctx):
     rel = comp.norm(comp.residual(u)) / comp.norm(comp.residual(comp.initial()))
     print(f"[gpu] AMR F base: cycles={st['cycles']} composite rel residual={rel:.2e}", flush=True)
     assert rel <= 1.2e-10
+    # the same with the composite correction in FP32 (mixed precision)
+    st = prob.solve(rtol=1e-10, max_cycles=400, cycle="F", precision="mixed")
+    u = [prob.displacement()] + [prob.amr_displacement(k) for k in range(1, len(ap.boxes) + 1)]
+    rel = comp.norm(comp.residual(u)) / comp.norm(comp.residual(comp.initial()))
+    print(f"[gpu] AMR F base, mixed: cycles={st['cycles']} composite rel residual={rel:.2e}", flush=True)
+    assert st["converged"] and abs(st["cycles"] - (len(hist) - 1)) <= 2 and rel <= 1.2e-10
     prob.close()
 
 
