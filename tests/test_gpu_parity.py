@@ -106,11 +106,15 @@ def test_level_steps_match_oracle(emg, ctx, name):
         ref_jac = oracle.jacobi(g, Cs[l], u, f, 2.0 / 3.0)
         for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("mixed", torch.float32, 2e-5)):
             ud, fd = dev(u, dt), dev(f, dt)
-            out = torch.empty_like(ud)
+            # outputs start as NaN: a node the kernel skips, or fills from an
+            # unwritten value, fails the element-wise comparison
+            out = torch.full_like(ud, float("nan"))
             prob.level_apply(l, ud, out, precision=prec)
             assert rel_err(host(out), ref_apply) <= tol, (l, prec, "apply")
+            out.fill_(float("nan"))
             prob.level_residual(l, ud, fd, out, precision=prec)
             assert rel_err(host(out), ref_res) <= tol, (l, prec, "residual")
+            out.fill_(float("nan"))
             prob.level_jacobi(l, ud, fd, out, precision=prec)
             assert rel_err(host(out), ref_jac) <= tol, (l, prec, "jacobi")
         # transfers between l and l+1
@@ -119,7 +123,7 @@ def test_level_steps_match_oracle(emg, ctx, name):
         ec = rng.standard_normal(gc.shape(d))
         up_ref = oracle.prolong_add(gc, g, ec, u)
         for prec, dt, tol in (("fp64", torch.float64, 1e-14), ("mixed", torch.float32, 1e-6)):
-            fc = torch.empty(gc.shape(d), dtype=dt, device=DEV)
+            fc = torch.full(gc.shape(d), float("nan"), dtype=dt, device=DEV)
             prob.level_restrict(l, dev(f, dt), fc, precision=prec)
             assert rel_err(host(fc), fc_ref) <= tol, (l, prec, "restrict")
             ud = dev(u, dt)
@@ -130,7 +134,7 @@ def test_level_steps_match_oracle(emg, ctx, name):
     fb = rng.standard_normal(gb.shape(d))
     A = oracle.dense_matrix(gb, Cs[-1])
     eb_ref = np.linalg.solve(A, fb.ravel()).reshape(fb.shape)
-    eb = torch.empty(gb.shape(d), dtype=torch.float64, device=DEV)
+    eb = torch.full(gb.shape(d), float("nan"), dtype=torch.float64, device=DEV)
     prob.level_bottom_solve(dev(fb), eb)
     assert rel_err(host(eb), eb_ref) <= 1e-10
     # right-hand side and stress
@@ -173,6 +177,7 @@ def test_zmarch_level_steps_match_oracle(emg, ctx, name):
         ud, fd = dev(u, dt), dev(f, dt)
         out = torch.empty_like(ud)
         for step in ("apply", "residual", "jacobi"):
+            out.fill_(float("nan"))   # every node must be written
             if step == "apply":
                 prob.level_apply(0, ud, out, precision=prec)
             elif step == "residual":
