@@ -95,6 +95,12 @@ typedef struct {
   int use_graph;     /* 1 (default): replay captured HIP graphs; 0: launch kernels eagerly */
   int cycle;         /* emg_cycle (default EMG_VCYCLE); emg_solve_batch and the server take
                         EMG_VCYCLE only (EMG_EINVAL otherwise) */
+  int stall_iters;   /* EMG_MIXED in emg_solve: if the FP64 residual norm has not fallen below
+                        stall_factor times its value at the start of a window of stall_iters
+                        refinement iterations, the solve continues with FP64 cycles from the
+                        current iterate (emg_solve_stats.fp64_fallback = 1).  Default 24; 0 turns
+                        the test off; read at host convergence reads (every check_every) */
+  double stall_factor; /* in (0, 1); default 0.5 */
 } emg_solve_opts;
 
 typedef struct {
@@ -105,6 +111,7 @@ typedef struct {
   double solve_seconds;/* wall time of the cycle loop (lift to tolerance) */
   double setup_seconds;/* wall time of hierarchy setup and right-hand-side assembly in this call */
   int64_t dofs;        /* d x stored nodes not on a Dirichlet face */
+  int fp64_fallback;   /* 1 if a mixed-precision solve stalled and finished with FP64 cycles */
 } emg_solve_stats;
 
 const char *emg_last_error(void);

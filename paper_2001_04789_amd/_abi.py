@@ -42,12 +42,13 @@ class emg_domain(ctypes.Structure):
 class emg_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("max_cycles", c_int), ("precision", c_int), ("nu1", c_int), ("nu2", c_int),
                 ("omega", c_double), ("warm_start", c_int), ("check_every", c_int), ("use_graph", c_int),
-                ("cycle", c_int)]
+                ("cycle", c_int), ("stall_iters", c_int), ("stall_factor", c_double)]
 
 
 class emg_solve_stats(ctypes.Structure):
     _fields_ = [("cycles", c_int), ("converged", c_int), ("rel_res", c_double), ("conv_factor", c_double),
-                ("solve_seconds", c_double), ("setup_seconds", c_double), ("dofs", c_int64)]
+                ("solve_seconds", c_double), ("setup_seconds", c_double), ("dofs", c_int64),
+                ("fp64_fallback", c_int)]
 
 
 class emg_request(ctypes.Structure):

@@ -1658,6 +1658,8 @@ void emg_default_opts(emg_solve_opts *o) {
   o->check_every = 4;
   o->use_graph = 1;
   o->cycle = EMG_VCYCLE;
+  o->stall_iters = 24;
+  o->stall_factor = 0.5;
 }
 
 emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out) {
@@ -1836,6 +1838,8 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   if (!(opt.omega > 0.0 && opt.omega < 2.0)) return fail(EMG_EINVAL, "omega must lie in (0, 2)");
   if (!(opt.rtol >= 0.0) || opt.max_cycles < 0) return fail(EMG_EINVAL, "bad tolerance or cycle cap");
   if (opt.cycle != EMG_VCYCLE && opt.cycle != EMG_FCYCLE) return fail(EMG_EINVAL, "bad cycle type");
+  if (opt.stall_iters < 0 || (opt.stall_iters > 0 && !(opt.stall_factor > 0.0 && opt.stall_factor < 1.0)))
+    return fail(EMG_EINVAL, "bad stall test");
   const int k = std::max(1, opt.check_every);
   const auto t0 = std::chrono::steady_clock::now();
   TRY(setup(p));
@@ -1891,15 +1895,35 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   const bool fcyc = opt.cycle == EMG_FCYCLE;
   if (opt.use_graph) TRY(get_graph(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, fcyc, &exec));
   const auto t2 = std::chrono::steady_clock::now();
+  int prec = opt.precision;
+  bool fell_back = false;
+  double win_rsq = -1.0;   // stall test: residual at the start of the current window
+  int win_start = 0;
   for (;;) {
     if (exec)
       HIPCK(hipGraphLaunch(exec, p->stream));
     else
-      record_cycles(p, opt.precision, k, opt.nu1, opt.nu2, opt.omega, fcyc);
+      record_cycles(p, prec, k, opt.nu1, opt.nu2, opt.omega, fcyc);
     HIPCK(hipGetLastError());
     HIPCK(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, p->stream));
     HIPCK(hipStreamSynchronize(p->stream));
-    if (p->ctl_host->done) break;
+    const Ctl &h = *p->ctl_host;
+    if (h.done) break;
+    if (prec == EMG_MIXED && opt.stall_iters > 0) {
+      if (win_rsq < 0.0 || h.rsq <= win_rsq * opt.stall_factor * opt.stall_factor) {
+        win_rsq = h.rsq;
+        win_start = h.cycles;
+      } else if (h.cycles - win_start >= opt.stall_iters) {
+        // the FP32 corrections no longer reduce the FP64 residual: FP64
+        // cycles take over from the current iterate (the FP64 state; a
+        // pending FP32 correction is dropped), with the same reference norm,
+        // cycle count and cap
+        prec = EMG_FP64;
+        fell_back = true;
+        exec = nullptr;
+        if (opt.use_graph) TRY(get_graph(p, EMG_FP64, k, opt.nu1, opt.nu2, opt.omega, fcyc, &exec));
+      }
+    }
   }
   const auto t3 = std::chrono::steady_clock::now();
   const Ctl c = *p->ctl_host;
@@ -1937,6 +1961,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     unknown_nodes += valid - cov;
   }
   s.dofs = (long long)p->D * unknown_nodes;
+  s.fp64_fallback = fell_back ? 1 : 0;
   if (st) *st = s;
   if (c.done == 2) return fail(EMG_EDIVERGED, "residual norm is not finite");
   if (c.done == 3) return fail(EMG_ENOTCONV, "cycle cap reached before the tolerance");

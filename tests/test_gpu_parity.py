@@ -227,7 +227,7 @@ def test_solve_matches_oracle(emg, ctx, name, precision):
     lift = np.where(oracle.dirichlet_mask(g), ref.rhs, 0.0)
     r0 = oracle.residual(g, C, lift, ref.rhs)
     st = prob.solve(rtol=1e-10, max_cycles=400, precision=precision)
-    assert st["converged"] and st["rel_res"] <= 1e-10
+    assert st["converged"] and st["rel_res"] <= 1e-10 and st["fp64_fallback"] == 0
     u = prob.displacement()
     # the oracle's own residual of the GPU iterate confirms the tolerance
     assert oracle.norm(g, oracle.residual(g, C, u, ref.rhs)) / oracle.norm(g, r0) <= 1.2e-10
@@ -248,6 +248,38 @@ def test_solve_matches_oracle(emg, ctx, name, precision):
     s = prob.stress()
     s_ref = oracle.stress(g, C, spec.eps0, ref.u)
     assert np.linalg.norm(s - s_ref) / np.linalg.norm(s_ref) <= 1e-7
+    prob.close()
+
+
+@pytest.mark.parametrize("amr_case", [False, True])
+def test_mixed_stall_falls_back_to_fp64(emg, ctx, amr_case):
+    """The stall test forced from the host (a window of 4 refinement
+    iterations that would have to cut the residual by 1e-30): the mixed solve
+    switches to FP64 cycles at the second convergence read, flags it, and
+    still reaches 1e-10 with the FP64 solution (single level and AMR)."""
+    if amr_case:
+        ap = synth.smooth_amr(dim=3, levels=2, n=17, seed=2)
+        make = lambda: emg.Problem.from_amr(ctx, ap)
+    else:
+        spec = SOLVES["polycrystal_17"]()
+        make = lambda: emg.Problem.from_spec(ctx, spec)
+    prob = make()
+    ref = prob.solve(rtol=1e-10, max_cycles=400, precision="fp64")
+    uref = prob.displacement()
+    normal = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed")
+    assert normal["converged"] and normal["fp64_fallback"] == 0
+    for use_graph in (1, 0):
+        st = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed", check_every=4, stall_iters=4,
+                        stall_factor=1e-30, use_graph=use_graph)
+        u = prob.displacement()
+        err = np.linalg.norm(u - uref) / np.linalg.norm(uref)
+        print(f"[gpu] stall fallback (amr={amr_case}, graph={use_graph}): cycles {st['cycles']} "
+              f"(FP64 {ref['cycles']}, mixed {normal['cycles']}) fallback={st['fp64_fallback']} err={err:.2e}",
+              flush=True)
+        assert st["converged"] and st["rel_res"] <= 1e-10 and st["fp64_fallback"] == 1
+        assert st["cycles"] <= ref["cycles"] + 2 and err <= 1e-8
+    with pytest.raises(emg.EmgError):
+        prob.solve(precision="mixed", stall_iters=4, stall_factor=1.5)
     prob.close()
 
 
