@@ -195,6 +195,30 @@ def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4)):
     return {"workload": f"2D disc r=0.1 (config 1 moduli), base {n0}^2, boxes around the disc", "rows": rows}
 
 
+def amr_config4(emg, ctx, synth):
+    """Config 4: the diffuse penny crack on a 65^3 base with two refined
+    boxes (reflux-free composite system), FP64 and mixed precision to 1e-10
+    (second solve of each, after setup); composite DoF/s and the mixed
+    solution's difference from the FP64 one."""
+    import numpy as np
+    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.05)
+    prob = emg.Problem.from_amr(ctx, ap)
+    out = {"workload": "penny crack R=0.2 (moduli floor 1e-2, width 0.05), base 65^3 nodes, 3 levels",
+           "boxes": [[list(lo), list(hi)] for lo, hi in ap.boxes], "composite_nodes": ap.composite_nodes()}
+    sols = {}
+    for prec in ("fp64", "mixed"):
+        st = [prob.solve(rtol=1e-10, max_cycles=400, precision=prec) for _ in range(2)][-1]
+        sols[prec] = [prob.displacement()] + [prob.amr_displacement(k) for k in range(1, len(ap.boxes) + 1)]
+        out[prec] = {"cycles": st["cycles"], "rel_res": st["rel_res"], "solve_ms": 1e3 * st["solve_seconds"],
+                     "dofs": st["dofs"], "dofs_per_s": st["dofs"] / st["solve_seconds"]}
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(sols["mixed"], sols["fp64"]))
+    den = sum(float(np.sum(b ** 2)) for b in sols["fp64"])
+    out["mixed_rel_diff_vs_fp64"] = float(np.sqrt(num / den))
+    out["mixed_speedup"] = out["fp64"]["solve_ms"] / out["mixed"]["solve_ms"]
+    prob.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -352,6 +376,7 @@ def main():
     out["coupling_loop"] = loop
     prob.close()
     out["amr_efficiency"] = amr_efficiency(emg, ctx, synth)
+    out["amr_config4"] = amr_config4(emg, ctx, synth)
     del C_d, faces_d, sigma_d
     if args.serve_requests > 0:
         out["serving"] = serve(emg, torch, ctx, args)
