@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512, help="served stream length (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=16, help="concurrent requests on the GPU")
+    ap.add_argument("--serve-light-rate", type=float, default=40.0,
+                    help="arrival rate of a second, shorter served stream below the GPU's capacity (0 = skip)")
+    ap.add_argument("--serve-light-requests", type=int, default=160)
     ap.add_argument("--serve-nu", type=int, default=4, help="pre/post Jacobi sweeps per level of the served solves "
                     "(the served stream fixes no sweep count; V(4,4) serves more solves/s than V(2,2))")
     ap.add_argument("--kernel-only", action="store_true",
@@ -113,12 +116,12 @@ def cpu_baseline(spec, gpu_cycles, ncycles):
             "seconds_per_cycle": per_cycle, "setup_seconds": t1 - t0}
 
 
-def serve(emg, torch, ctx, args):
+def serve(emg, torch, ctx, args, count, rate):
     """Served stream (continuous batching); latencies from the server's clock."""
     import types
     import numpy as np
     import synth
-    trace = synth.serving_trace(count=args.serve_requests, seed=2005, rate=args.serve_rate)
+    trace = synth.serving_trace(count=count, seed=2005, rate=rate)
     dev = "cuda:0"
     pool = {}
     t0 = time.perf_counter()
@@ -157,7 +160,7 @@ def serve(emg, torch, ctx, args):
     prep = np.array([i["t_ready"] - i["t_admit"] for i in infos])
     span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
     dofs = sum(pool[(r.kind, r.n, r.variant)][1] for r in trace)
-    return {"requests": len(trace), "rate_req_per_s": args.serve_rate, "slots": args.serve_slots,
+    return {"requests": len(trace), "rate_req_per_s": rate, "slots": args.serve_slots,
             "precision": "mixed", "smoothing": f"V({args.serve_nu},{args.serve_nu})", "failed": len(bad),
             "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
             "mean_ms": 1e3 * float(lat.mean()), "queue_p50_ms": 1e3 * float(np.percentile(qwait, 50)),
@@ -379,7 +382,10 @@ def main():
     out["amr_config4"] = amr_config4(emg, ctx, synth)
     del C_d, faces_d, sigma_d
     if args.serve_requests > 0:
-        out["serving"] = serve(emg, torch, ctx, args)
+        out["serving"] = serve(emg, torch, ctx, args, args.serve_requests, args.serve_rate)
+    if args.serve_light_rate > 0 and args.serve_light_requests > 0:
+        # the same request mix offered below the GPU's capacity: latency without the queue
+        out["serving_light"] = serve(emg, torch, ctx, args, args.serve_light_requests, args.serve_light_rate)
     ctx.close()
     if args.cpu_cycles > 0:
         out["cpu_baseline"] = cpu_baseline(spec, out["fp64"]["cycles"], args.cpu_cycles)
