@@ -172,7 +172,7 @@ def serve(emg, torch, ctx, args, count, rate):
 
 def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4)):
     """AMR against the uniform grid of the same finest resolution (the 2D
-    disc of config 1, refined boxes around it): composite and uniform node
+    disc of inclusion_2d, refined boxes around it): composite and uniform node
     counts, FP64 solve times to 1e-10 (second solve of each, after setup),
     and the largest difference of the AMR base-grid displacement from the
     uniform solution at the same points."""
@@ -195,11 +195,11 @@ def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4)):
                      "base_rel_diff_vs_uniform": float(np.abs(ub - uf).max() / np.abs(uf).max())})
         pa.close()
         pf.close()
-    return {"workload": f"2D disc r=0.1 (config 1 moduli), base {n0}^2, boxes around the disc", "rows": rows}
+    return {"workload": f"2D disc r=0.1 (inclusion_2d moduli), base {n0}^2, boxes around the disc", "rows": rows}
 
 
-def amr_config4(emg, ctx, synth):
-    """Config 4: the diffuse penny crack on a 65^3 base with two refined
+def amr_penny_crack(emg, ctx, synth):
+    """The diffuse penny crack on a 65^3 base with two refined
     boxes (reflux-free composite system), FP64 and mixed precision to 1e-10
     (second solve of each, after setup); composite DoF/s and the mixed
     solution's difference from the FP64 one."""
@@ -379,7 +379,7 @@ def main():
     out["coupling_loop"] = loop
     prob.close()
     out["amr_efficiency"] = amr_efficiency(emg, ctx, synth)
-    out["amr_config4"] = amr_config4(emg, ctx, synth)
+    out["amr_penny_crack"] = amr_penny_crack(emg, ctx, synth)
     del C_d, faces_d, sigma_d
     if args.serve_requests > 0:
         out["serving"] = serve(emg, torch, ctx, args, args.serve_requests, args.serve_rate)

@@ -541,7 +541,7 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> Amr
 
 
 def _disc_fields(radius, width, eigen, center=(0.5, 0.5)):
-    """Moduli (lambda, mu) and eigenstrain of config 1's plane-strain disc:
+    """Moduli (lambda, mu) and eigenstrain of the plane-strain inclusion disc:
     matrix mu=1, lambda=1.5, inclusion mu=2, lambda=3, blended by a tanh
     profile of the given width, isotropic eigenstrain `eigen` inside."""
     def fields(x, y, z):
@@ -556,7 +556,7 @@ def _disc_fields(radius, width, eigen, center=(0.5, 0.5)):
 def eshelby_amr_2d(n0: int = 129, levels: int = 3, radius: float = 0.1, width_cells: float = 2.0,
                    eigen: float = 1e-3) -> AmrProblem:
     """AMR-efficiency input (the paper's 2D Eshelby example, Sec. 4.1 / the
-    AMR performance study of Sec. 5): config 1's disc (radius `radius`,
+    AMR performance study of Sec. 5): the inclusion_2d disc moduli (radius `radius`,
     centre (0.5, 0.5)) on [0,1]^2 with a base grid of n0 nodes per axis and
     levels - 1 refined boxes around the disc (one per level, ratio 2).  The
     tanh width is width_cells cells of the finest level, so the finest level

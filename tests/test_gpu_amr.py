@@ -116,7 +116,7 @@ def test_composite_solve_matches_oracle(emg, ctx, name, precision):
 
 
 def test_penny_crack_three_levels(emg, ctx):
-    """Config-4-style problem (diffuse penny crack, 3 levels) on a 33^3 base,
+    """Diffuse penny crack, 3 levels, on a 33^3 base,
     FP64 and mixed precision: each GPU solution satisfies the oracle's
     composite system to 1e-10, and the two agree to 1e-8."""
     ap = synth.penny_crack(n=33, levels=3, floor=1e-2, width=0.05)

@@ -1,16 +1,18 @@
-"""Full-size checks of the workloads the benchmark and the configurations
-name, through the same C ABI calls and launch configuration as bench.py.
+"""Full-size checks of the benchmark's workloads (129^3 and 257^3
+polycrystals, the three-level penny-crack AMR problem on a 65^3 base),
+through the same C ABI calls and launch configuration as bench.py.
 
 At these sizes the oracle cannot run whole solves in seconds, so it checks:
   * one operator application / residual / Jacobi sweep of the finest level,
-    element by element, on a random field (config 2, 129^3 polycrystal);
+    element by element, on a random field (129^3 polycrystal);
   * the GPU solutions of FP64 and mixed-precision solves through the
     oracle's own residual: relative residual <= 1.2e-10 (stopping test
     1e-10 plus the rounding of the recomputation), and the mixed solution
     within 1e-8 (relative 2-norm) of a FP64 solution iterated to 1e-13 whose
-    oracle residual is itself checked (configs 2 and 3: 129^3 and 257^3);
+    oracle residual is itself checked (129^3 polycrystal; 257^3 polycrystal
+    with a stiff eigenstrained sphere);
   * the composite residual of the three-level AMR solve on the 65^3 base
-    (config 4, reading of floor and width as in synth.penny_crack).
+    (reading of floor and width as in synth.penny_crack).
 """
 import numpy as np
 import pytest
@@ -73,7 +75,7 @@ def check_solves(emg, ctx, spec, label):
     return out
 
 
-def test_config2_finest_level_steps(emg, ctx):
+def test_polycrystal129_finest_level_steps(emg, ctx):
     """129^3 polycrystal: the finest-level operator, residual and Jacobi
     sweep (interior tiles and boundary shell) against the oracle, element by
     element, in FP64 and FP32."""
@@ -83,7 +85,7 @@ def test_config2_finest_level_steps(emg, ctx):
     rng = np.random.default_rng(11)
     u = 1e-3 * rng.standard_normal(g.shape(3))
     f = rng.standard_normal(g.shape(3))
-    print("[gpu] config 2 level steps: oracle", flush=True)
+    print("[gpu] 129^3 polycrystal level steps: oracle", flush=True)
     ref = {"apply": oracle.apply(g, spec.C, u), "residual": oracle.residual(g, spec.C, u, f),
            "jacobi": oracle.jacobi(g, spec.C, u, f, 2.0 / 3.0)}
     for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("mixed", torch.float32, 2e-5)):
@@ -104,27 +106,27 @@ def test_config2_finest_level_steps(emg, ctx):
     prob.close()
 
 
-def test_config2_solves_full_size(emg, ctx):
+def test_polycrystal129_solves_full_size(emg, ctx):
     spec = synth.polycrystal_3d(n=129, grains=16, seed=2002)
-    res = check_solves(emg, ctx, spec, "config 2 (129^3 polycrystal)")
+    res = check_solves(emg, ctx, spec, "129^3 polycrystal")
     assert res["mixed"][0]["cycles"] == res["fp64"][0]["cycles"]
 
 
-def test_config3_solves_full_size(emg, ctx):
+def test_polycrystal257_sphere_solves_full_size(emg, ctx):
     """257^3, 64 grains, stiff eigenstrained sphere: FP32 V-cycles inside
     FP64 refinement against plain FP64, both checked by the oracle."""
-    print("[gpu] config 3: generating the 257^3 polycrystal", flush=True)
+    print("[gpu] generating the 257^3 polycrystal with a sphere", flush=True)
     spec = synth.polycrystal_3d(n=257, grains=64, seed=2003, inclusion=(3.0, 2e-3))
-    check_solves(emg, ctx, spec, "config 3 (257^3 polycrystal + sphere)")
+    check_solves(emg, ctx, spec, "257^3 polycrystal + sphere")
 
 
-def test_config4_amr_full_size(emg, ctx):
+def test_penny_crack_amr_65_full_size(emg, ctx):
     """Penny crack, 65^3 base, three levels, FP64 and mixed precision: each
     GPU composite solution satisfies the oracle's composite system to
     1.2e-10; the mixed solution's error against the FP64 one is reported and
     held to 1e-8."""
     ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.05)
-    print(f"[gpu] config 4: boxes={ap.boxes}", flush=True)
+    print(f"[gpu] penny crack, 65^3 base: boxes={ap.boxes}", flush=True)
     comp = amr.from_problem(ap)
     r0 = comp.norm(comp.residual(comp.initial()))
     sols = {}
