@@ -494,17 +494,31 @@ def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float 
     return amr
 
 
-def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> AmrProblem:
-    """Small composite test problem: smooth isotropic moduli (analytic,
-    sampled on every level), body force, mixed Dirichlet/traction faces, and
-    centred nested boxes (each half the previous box's width)."""
+def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2, kind: str = "iso") -> AmrProblem:
+    """Small composite test problem: smooth moduli (analytic, sampled on
+    every level), body force, mixed Dirichlet/traction faces, and centred
+    nested boxes (each half the previous box's width).  kind "iso": (lambda,
+    mu) fields; kind "aniso": the Voigt matrix of those fields plus a smoothly
+    varying multiple of a fixed rotated cubic crystal (SPD everywhere),
+    stored as the 21 (3D) or 6 (2D, plane strain) upper-triangle constants."""
     rng = np.random.default_rng(seed)
     k = rng.uniform(1.0, 3.0, size=4)
+    R = shoemake_rotation(rng.random(3))
+    cub = rotate_voigt(cubic_voigt(1.68, 1.21, 0.75), R)
+    liso = np.zeros((6, 6))
+    liso[:3, :3] = 1.0
+    miso = np.diag([2.0, 2.0, 2.0, 1.0, 1.0, 1.0])
+    if dim == 2:
+        liso, miso, cub = plane_strain_voigt(liso), plane_strain_voigt(miso), plane_strain_voigt(cub)
+    lu, mu_, cu = upper_tri(liso), upper_tri(miso), upper_tri(cub)
 
     def fields(x, y, z):
         lam = 1.5 + 0.8 * np.sin(k[0] * x + 0.3) * np.cos(k[1] * y) * np.cos(k[2] * z)
         mu = 1.0 + 0.5 * np.cos(k[3] * x + y - 0.5 * z)
-        return np.stack([lam + 0 * x * y * z, mu + 0 * x * y * z])
+        if kind == "iso":
+            return np.stack([lam + 0 * x * y * z, mu + 0 * x * y * z])
+        s = 0.3 * (1.0 + 0.4 * np.sin(k[1] * x - k[2] * y + 0.7 * z))
+        return np.stack([lu[c] * lam + mu_[c] * mu + cu[c] * s + 0 * x * y * z for c in range(len(lu))])
 
     def body(x, y, z):
         g = np.exp(-((x - 0.45) ** 2 + (y - 0.55) ** 2 + (z - 0.5) ** 2) / 0.05)
@@ -514,11 +528,12 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> Amr
     hi = (1.0,) * dim + (0.0,) * (3 - dim)
     bc = ("dirichlet", "traction", "traction", "traction", "dirichlet", "traction") if dim == 3 else \
         ("dirichlet", "traction", "dirichlet", "traction", PERIODIC, PERIODIC)
-    base = Problem(dim=dim, n=n3, lo=(0.0, 0.0, 0.0), hi=hi, bc=bc, kind="iso", C=np.zeros(0),
-                   name=f"smooth_amr_{dim}d_{levels}L")
+    base = Problem(dim=dim, n=n3, lo=(0.0, 0.0, 0.0), hi=hi, bc=bc, kind=kind, C=np.zeros(0),
+                   name=f"smooth_amr_{dim}d_{levels}L_{kind}")
     x, y, z = base.coords()
     shp = (base.m[2], base.m[1], base.m[0])
-    base.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, z), (2,) + shp))
+    nc = 2 if kind == "iso" else len(lu)
+    base.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, z), (nc,) + shp))
     base.b = np.ascontiguousarray(np.broadcast_to(body(x, y, z), (dim,) + shp))
     amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
     lo_p, hi_p = [0] * 3, [m - 1 for m in base.m]
@@ -533,7 +548,7 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2) -> Amr
         amr.boxes.append((tuple(lo), tuple(hi)))
         X, Y, Z = amr.box_coords(lev)
         mshape = tuple(len(v.ravel()) for v in (Z, Y, X))
-        amr.C.append(np.ascontiguousarray(np.broadcast_to(fields(X, Y, Z), (2,) + mshape)))
+        amr.C.append(np.ascontiguousarray(np.broadcast_to(fields(X, Y, Z), (nc,) + mshape)))
         amr.eps0.append(None)
         amr.b.append(np.ascontiguousarray(np.broadcast_to(body(X, Y, Z), (dim,) + mshape)))
         lo_p, hi_p = lo, hi

@@ -27,7 +27,9 @@ def ctx(emg):
     c.close()
 
 
-CASES = {"2d_2L": (2, 2, 17), "2d_3L": (2, 3, 17), "3d_2L": (3, 2, 9), "3d_2L_17": (3, 2, 17)}
+CASES = {"2d_2L": (2, 2, 17), "2d_3L": (2, 3, 17), "3d_2L": (3, 2, 9), "3d_2L_17": (3, 2, 17),
+         # anisotropic moduli (21 / 6 stored constants) on every level
+         "2d_3L_aniso": (2, 3, 33, 5, "aniso"), "3d_2L_aniso": (3, 2, 17, 5, "aniso")}
 
 
 def _state(prob, comp, u):
@@ -155,14 +157,14 @@ def test_amr_rejects_bad_boxes(emg, ctx):
 
 
 @pytest.mark.parametrize("base", ["V", "F"])
-@pytest.mark.parametrize("case", [(2, 3, 65, 4), (3, 2, 17, 2)])
+@pytest.mark.parametrize("case", [(2, 3, 65, 4), (3, 2, 17, 2), (3, 2, 17, 5, "aniso")])
 def test_composite_cycle_iterates_match_oracle(emg, ctx, case, base):
     """Element by element: after 1, 2 and 5 composite cycles from the
     initial state, the GPU's composite unknowns (valid fine nodes, uncovered
     coarse nodes) equal the oracle's composite cycle iterates (base grid
     corrected by a V- or an F-cycle)."""
-    dim, levels, n, seed = case
-    ap = synth.smooth_amr(dim=dim, levels=levels, n=n, seed=seed)
+    dim, levels, n, seed = case[:4]
+    ap = synth.smooth_amr(dim=dim, levels=levels, n=n, seed=seed, kind=case[4] if len(case) > 4 else "iso")
     comp = amr.from_problem(ap)
     masks = comp.unknown_masks()
     u = comp.initial()
