@@ -360,3 +360,23 @@ def test_warm_start_from_solution_needs_no_cycle(emg, ctx):
     st = prob.solve(rtol=1e-6, warm_start=1)
     assert st["cycles"] <= 1
     prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start_from_perturbed_solution(emg, ctx, precision):
+    """A warm start from the solution plus a smooth perturbation: the
+    reference norm is the warm iterate's residual, the solve reaches 1e-10
+    relative to it, and the result is the cold solve's to 1e-8."""
+    spec = synth.polycrystal_3d(n=17, grains=8, seed=2002)
+    prob = emg.Problem.from_spec(ctx, spec)
+    cold = prob.solve(rtol=1e-12, max_cycles=400, precision=precision)
+    u = prob.displacement()
+    z = np.linspace(0.0, 1.0, u.shape[1])[:, None, None]
+    pert = u + 1e-4 * np.sin(np.pi * z) * np.ones_like(u)   # zero on the clamped z faces
+    prob.set_displacement(pert)
+    st = prob.solve(rtol=1e-10, max_cycles=400, precision=precision, warm_start=1)
+    w = prob.displacement()
+    err = np.linalg.norm(w - u) / np.linalg.norm(u)
+    print(f"[gpu] warm start {precision}: cycles {st['cycles']} (cold {cold['cycles']}) err {err:.2e}", flush=True)
+    assert st["converged"] and st["rel_res"] <= 1e-10 and err <= 1e-8
+    prob.close()
