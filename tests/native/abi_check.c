@@ -10,7 +10,10 @@
  *   clang++ abi_check.o -L paper_2001_04789_amd -l:libemg.so -L/opt/rocm/lib -lamdhip64 \
  *     -Wl,-rpath,<repo>/paper_2001_04789_amd -o abi_check
  *
- * Exit status 0 when every call behaves. */
+ * Exit status 0 when every call behaves.  For a sanitizer run, compile
+ * paper_2001_04789_amd/csrc/emg.hip with hipcc -c and -Xarch_host
+ * -fsanitize=address instead of linking libemg.so, build this file and link
+ * with clang++ -fsanitize=address, and run with ASAN_OPTIONS=detect_leaks=0. */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -209,5 +212,6 @@ int main(void) {
   CHECK(emg_problem_destroy(p), EMG_OK);
   CHECK(emg_ctx_destroy(ctx), EMG_OK);
   printf("abi_check: %d failure(s)\n", failures);
+  fflush(stdout);
   return failures ? 1 : 0;
 }
