@@ -362,6 +362,24 @@ def main():
         fcy[prec] = {"cycles": sts[-1]["cycles"], "solve_ms": 1e3 * sts[-1]["solve_seconds"],
                      "solve_only_dofs_per_s": dofs / sts[-1]["solve_seconds"]}
     out["fcycle"] = fcy
+    # stencil-pass plans picked by measurement (emg_autotune), then the cost
+    # model's plans again for the rest of the run
+    precs = ("fp64",) + (() if args.no_mixed else ("mixed",))
+    nlev = prob.num_levels()
+    tun = {"plans_cost_model": {p: [prob.level_zmarch(l, p) for l in range(nlev)] for p in precs}}
+    t0 = time.perf_counter()
+    tun["levels_tuned"] = {p: prob.autotune(p, reps=10, retune=True) for p in precs}
+    tun["tune_seconds"] = time.perf_counter() - t0
+    tun["plans_tuned"] = {p: [prob.level_zmarch(l, p) for l in range(nlev)] for p in precs}
+    for prec in precs:
+        sts = []
+        for _ in range(2):
+            prob.set_moduli(C_d)
+            sts.append(prob.solve(rtol=1e-10, max_cycles=400, precision=prec))
+        tun[prec] = {"cycles": sts[-1]["cycles"], "solve_ms": 1e3 * sts[-1]["solve_seconds"],
+                     "solve_only_dofs_per_s": dofs / sts[-1]["solve_seconds"]}
+    emg.autotune_reset()
+    out["autotuned"] = tun
     # phase-field style coupling loop: a precipitate grows over 6 steps; each
     # step re-sets moduli and eigenstrain and solves warm-started from the
     # previous displacement, beside a cold solve of the same step

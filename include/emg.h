@@ -303,6 +303,36 @@ emg_status emg_amr_residual(emg_problem *p, int level, double *r_dev, double *no
  * EMG_EINVAL for reps < 1, an unknown kernel or a missing coarser level. */
 emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms);
 
+/* ---- autotuner ----
+ * Picks, by measurement instead of the cost model, how the Jacobi sweep and
+ * residual of Sec. 3.1 are launched on each level; the operation itself is
+ * unchanged (a launch configuration, not a step of the method).  For every
+ * multigrid level of a 3D anisotropic problem wide enough for the
+ * z-marching pass (at least 64 x 4 interior nodes per plane and 8 planes),
+ * times the Jacobi sweep in `precision` (EMG_FP64: FP64 passes, EMG_MIXED:
+ * the FP32 ones) with the tile kernel and with the z-marching pass at every
+ * chunk count leaving at least 8 planes per chunk, each as `reps` launches
+ * captured into a graph (best of two replays), and records the fastest in a
+ * process-wide table keyed by device architecture, precision, level extents
+ * and periodic axes.  Every later plan of any problem with such a level
+ * (solves, batches, servers) takes the recorded choice; emg_level_zmarch
+ * reports it.  All variants compute bit-identical results, so tuning changes
+ * timing only.  Levels already in the table are skipped unless `retune` is
+ * nonzero.  The problem's recorded solve graphs are dropped (re-recorded at
+ * the next solve); graphs of servers already running keep their plans.
+ * If the environment variable EMG_TUNE_CACHE names a file, the table is
+ * read from it at first use and rewritten after each call that measured a
+ * level: a JSON object of "arch/fp64|fp32/m0xm1xm2/p<mask>" -> chunks per
+ * column (0 = tile kernel; mask bit a set for a periodic axis a); entries
+ * out of range for their level are ignored.  *tuned (optional) receives the
+ * number of levels measured (0 for 2D or isotropic problems, which have one
+ * variant).  EMG_EINVAL for reps outside 1..1000 or when the cache file
+ * cannot be written (the table itself is updated). */
+emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int *tuned);
+/* Empties the process-wide table; the EMG_TUNE_CACHE file, if any, is read
+ * again at the next lookup. */
+emg_status emg_autotune_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,8 @@ _SIGS = {
     "emg_level_prolong_add": ([c_void_p, c_int, c_int, c_void_p, c_void_p], c_int),
     "emg_level_bottom_solve": ([c_void_p, c_int, c_void_p, c_void_p], c_int),
     "emg_kernel_time": ([c_void_p, c_int, c_int, c_int, c_int, P(c_double)], c_int),
+    "emg_autotune": ([c_void_p, c_int, c_int, c_int, P(c_int)], c_int),
+    "emg_autotune_reset": ([], c_int),
     "emg_solve_batch": ([P(c_void_p), c_int, P(emg_solve_opts), P(emg_solve_stats)], c_int),
     "emg_server_create": ([c_void_p, c_int, P(emg_solve_opts), P(c_void_p)], c_int),
     "emg_server_submit": ([c_void_p, P(emg_request), P(ctypes.c_uint64)], c_int),
@@ -513,8 +515,23 @@ class Problem:
               "emg_kernel_time")
         return ms.value
 
+    def autotune(self, precision="fp64", reps: int = 10, retune: bool = False) -> int:
+        """Measure the stencil-pass variants of this problem's levels and
+        record the fastest process-wide (emg_autotune); returns the number of
+        levels measured."""
+        n = c_int()
+        check(lib.emg_autotune(self.handle, _PREC[precision], reps, int(bool(retune)), ctypes.byref(n)),
+              "emg_autotune")
+        return n.value
+
+
+def autotune_reset():
+    """Empty the process-wide autotuner table (emg_autotune_reset)."""
+    check(lib.emg_autotune_reset(), "emg_autotune_reset")
+
 
 __all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch",
+           "autotune_reset",
            "emg_domain", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
            "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE",
            "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_BC_NEUMANN", "EMG_VCYCLE", "EMG_FCYCLE",

@@ -124,6 +124,7 @@ struct emg_problem {
   double *sig = nullptr, *svm = nullptr;   // stress (Voigt) and von Mises output buffers
   hipStream_t own = nullptr, stream = nullptr;
   bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
+  int force_nzc = -1;   // >= 0: stencil-pass variant under measurement by emg_autotune
   std::vector<void *> allocs;
   size_t bytes = 0;
   size_t accounted = 0;   // bytes charged to the context's HBM budget
@@ -199,13 +200,120 @@ const R *moduli(const Level &L) {
   else return L.C32;
 }
 
-// Chunks per column of the z-marching pass for a level (0: tile kernel).  It
-// takes 3D anisotropic levels with enough columns x chunks of >= 8 planes to
-// give every CU a workgroup (FP64: one per CU, FP32: two); smaller levels
-// keep the tile kernel, which spreads them over more workgroups.
+// ---- autotuner table ----
+// Measured stencil-pass choice per device architecture, precision, level
+// extents and periodic axes: chunks per column of the z-marching pass, 0 for
+// the tile kernel.  emg_autotune fills it; zm_plan reads it before the cost
+// model.  With EMG_TUNE_CACHE naming a file, the table is read from it at
+// first use and written back after each tuning call (a flat JSON object).
+struct TuneTable {
+  std::mutex mu;
+  std::map<std::string, int> table;
+  std::map<int, std::string> arch;   // device -> architecture name
+  bool loaded = false;               // EMG_TUNE_CACHE read (or absent)
+};
+TuneTable &tune_table() {
+  static TuneTable t;
+  return t;
+}
+
+// Key of a 3D anisotropic level; caller holds the table's lock.
+std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g) {
+  auto it = t.arch.find(device);
+  if (it == t.arch.end()) {
+    hipDeviceProp_t prop;
+    std::string name = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      name = prop.gcnArchName;
+      const size_t colon = name.find(':');   // "gfx950:sramecc+:xnack-" -> "gfx950"
+      if (colon != std::string::npos) name.resize(colon);
+    }
+    it = t.arch.emplace(device, name).first;
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/%s/%dx%dx%d/p%d", it->second.c_str(), rbytes == 8 ? "fp64" : "fp32", g.m[0], g.m[1],
+           g.m[2], g.per[0] | (g.per[1] << 1) | (g.per[2] << 2));
+  return buf;
+}
+
+// Reads EMG_TUNE_CACHE once: every "key": integer pair of the file (keys
+// hold no quotes); anything else is skipped.  Caller holds the lock.
+void tune_load_locked(TuneTable &t) {
+  if (t.loaded) return;
+  t.loaded = true;
+  const char *path = getenv("EMG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *fp = fopen(path, "r");
+  if (!fp) return;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, fp)) > 0) s.append(buf, n);
+  fclose(fp);
+  size_t i = 0;
+  while ((i = s.find('"', i)) != std::string::npos) {
+    const size_t j = s.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = s.substr(i + 1, j - i - 1);
+    size_t k = j + 1;
+    while (k < s.size() && (s[k] == ' ' || s[k] == '\t' || s[k] == '\n' || s[k] == '\r')) k++;
+    i = j + 1;
+    if (k < s.size() && s[k] == ':') {
+      const char *a = s.c_str() + k + 1;
+      char *end = nullptr;
+      const long v = strtol(a, &end, 10);
+      if (end != a && v >= 0 && v <= 4096) t.table[key] = (int)v;
+    }
+  }
+}
+
+// Writes the table to EMG_TUNE_CACHE (through a temporary file renamed over
+// it); false if the file cannot be written.  Caller holds the lock.
+bool tune_save_locked(const TuneTable &t) {
+  const char *path = getenv("EMG_TUNE_CACHE");
+  if (!path || !*path) return true;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *fp = fopen(tmp.c_str(), "w");
+  if (!fp) return false;
+  fputs("{\n", fp);
+  size_t i = 0;
+  for (const auto &e : t.table)
+    fprintf(fp, "  \"%s\": %d%s\n", e.first.c_str(), e.second, ++i < t.table.size() ? "," : "");
+  fputs("}\n", fp);
+  const bool ok = fclose(fp) == 0;
+  return ok && rename(tmp.c_str(), path) == 0;
+}
+
+// The z-marching pass needs a workgroup row of interior nodes (64 x 4 tiles
+// fully inside the level in x and y) and at least 8 planes per chunk; a table
+// value outside that range is ignored.
+bool zm_valid(const Geom &g, int nzc) {
+  const Split sp = split_of(g);
+  if (nzc == 0) return true;
+  return g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 && nzc <= sp.ntz / 8;
+}
+
+bool tune_find(int device, int rbytes, const Geom &g, int *nzc) {
+  TuneTable &t = tune_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  tune_load_locked(t);
+  auto it = t.table.find(tune_key_locked(t, device, rbytes, g));
+  if (it == t.table.end() || !zm_valid(g, it->second)) return false;
+  *nzc = it->second;
+  return true;
+}
+
+// Chunks per column of the z-marching pass for a level (0: tile kernel): the
+// variant under measurement, else the tuned choice, else the cost model,
+// which takes 3D anisotropic levels with enough columns x chunks of >= 8
+// planes to give every CU a workgroup (FP64: one per CU, FP32: two); smaller
+// levels keep the tile kernel, which spreads them over more workgroups.
 template <typename R>
 int zm_plan(const emg_problem *p, const Geom &g) {
   if (p->D != 3 || p->K != MOD_ANISO) return 0;
+  if (p->force_nzc >= 0) return p->force_nzc;
+  int tuned;
+  if (tune_find(p->ctx->device, (int)sizeof(R), g, &tuned)) return tuned;
   const int target = sizeof(R) == 8 ? 256 : 512;
   const int nzc = zm_chunks(g, target);
   if (nzc == 0) return 0;
@@ -2130,11 +2238,10 @@ emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, 
   return finish(p);
 }
 
-emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms) {
-  TRY(level_prep(p, level, precision));
-  if (reps < 1 || !avg_ms) return fail(EMG_EINVAL, "bad reps or output");
-  if ((kernel == 1 || kernel == 2) && level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
-  if (kernel < 0 || kernel > 2) return fail(EMG_EINVAL, "unknown kernel id");
+// Average duration of one level kernel (0 Jacobi sweep, 1 residual, 2
+// interpolation) over reps launches captured into a graph; arguments checked
+// by the caller, which also synchronises.
+static emg_status time_level_kernel(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms) {
   Level &L = p->lv[level];
   auto one = [&]() {
     if (precision == EMG_FP64) {
@@ -2179,7 +2286,71 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
   (void)hipGraphExecDestroy(exec);
   if (e != hipSuccess) return fail(EMG_EDEVICE, hipGetErrorString(e));
   *avg_ms = ms / reps;
+  return EMG_OK;
+}
+
+emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms) {
+  TRY(level_prep(p, level, precision));
+  if (reps < 1 || !avg_ms) return fail(EMG_EINVAL, "bad reps or output");
+  if ((kernel == 1 || kernel == 2) && level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
+  if (kernel < 0 || kernel > 2) return fail(EMG_EINVAL, "unknown kernel id");
+  TRY(time_level_kernel(p, kernel, level, precision, reps, avg_ms));
   return finish(p);
+}
+
+// ---- autotuner ----
+
+emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int *tuned) {
+  if (tuned) *tuned = 0;
+  TRY(level_prep(p, 0, precision));
+  if (reps < 1 || reps > 1000) return fail(EMG_EINVAL, "bad reps");
+  if (p->D != 3 || p->K != MOD_ANISO) return EMG_OK;
+  const int rb = precision == EMG_FP64 ? 8 : 4;
+  TuneTable &t = tune_table();
+  int count = 0;
+  for (int l = 0; l < (int)p->lv.size(); l++) {
+    const Geom &g = p->lv[l].g;
+    const Split sp = split_of(g);
+    if (!zm_valid(g, 1)) continue;   // no z-marching variant on this level
+    int have;
+    if (!retune && tune_find(p->ctx->device, rb, g, &have)) continue;
+    double best_ms = 0.0;
+    int best = -1;
+    for (int c = 0; c <= sp.ntz / 8; c++) {
+      double ms = 0.0, ms2 = 0.0;
+      p->force_nzc = c;
+      emg_status st = time_level_kernel(p, 0, l, precision, reps, &ms);
+      if (st == EMG_OK) st = time_level_kernel(p, 0, l, precision, reps, &ms2);
+      p->force_nzc = -1;
+      if (st != EMG_OK) return st;
+      ms = ms2 < ms ? ms2 : ms;
+      if (best < 0 || ms < best_ms) {
+        best = c;
+        best_ms = ms;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(t.mu);
+      tune_load_locked(t);
+      t.table[tune_key_locked(t, p->ctx->device, rb, g)] = best;
+    }
+    count++;
+  }
+  destroy_graphs(p);   // recorded with the earlier plans
+  if (tuned) *tuned = count;
+  if (count > 0) {
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!tune_save_locked(t)) return fail(EMG_EINVAL, "cannot write the EMG_TUNE_CACHE file");
+  }
+  return finish(p);
+}
+
+emg_status emg_autotune_reset(void) {
+  TuneTable &t = tune_table();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.table.clear();
+  t.loaded = false;
+  return EMG_OK;
 }
 
 // ---- ragged batches ----
