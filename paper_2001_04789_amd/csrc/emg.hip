@@ -217,8 +217,10 @@ TuneTable &tune_table() {
   return t;
 }
 
-// Key of a 3D anisotropic level; caller holds the table's lock.
-std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g) {
+// Architecture name of a device ("gfx950"), queried once; caller holds the
+// table's lock.  Contexts query it at creation, so lookups made while a
+// stream is being captured find it cached.
+const std::string &tune_arch_locked(TuneTable &t, int device) {
   auto it = t.arch.find(device);
   if (it == t.arch.end()) {
     hipDeviceProp_t prop;
@@ -230,8 +232,14 @@ std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g)
     }
     it = t.arch.emplace(device, name).first;
   }
+  return it->second;
+}
+
+// Key of a 3D anisotropic level; caller holds the table's lock.
+std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g) {
+  const std::string &arch = tune_arch_locked(t, device);
   char buf[160];
-  snprintf(buf, sizeof buf, "%s/%s/%dx%dx%d/p%d", it->second.c_str(), rbytes == 8 ? "fp64" : "fp32", g.m[0], g.m[1],
+  snprintf(buf, sizeof buf, "%s/%s/%dx%dx%d/p%d", arch.c_str(), rbytes == 8 ? "fp64" : "fp32", g.m[0], g.m[1],
            g.m[2], g.per[0] | (g.per[1] << 1) | (g.per[2] << 2));
   return buf;
 }
@@ -1776,6 +1784,11 @@ emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out
   HIPCK(hipGetDeviceCount(&count));
   if (hip_device < 0 || hip_device >= count) return fail(EMG_EINVAL, "no such HIP device");
   HIPCK(hipSetDevice(hip_device));
+  {
+    TuneTable &t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    (void)tune_arch_locked(t, hip_device);
+  }
   emg_ctx *c = new emg_ctx;
   c->device = hip_device;
   c->budget = hbm_budget_bytes;

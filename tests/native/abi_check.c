@@ -1,5 +1,6 @@
 /* The C ABI (include/emg.h) driven from plain C, with no Python in between:
  * a context; single-level FP64 / mixed / F-cycle solves with a warm start;
+ * the autotuner on a level too narrow for its variants;
  * displacement, stress and von Mises read-back; a ragged batch of three
  * problems; a three-level AMR problem in both precisions; a server taking
  * twelve requests of two sizes through three slots; an invalid domain.
@@ -126,6 +127,14 @@ int main(void) {
   o.cycle = EMG_FCYCLE;
   o.warm_start = 1;
   CHECK(emg_solve(p, &o, &st), EMG_OK);
+  int ntuned = -1;   /* 32 x 32 x 33 stored nodes: too narrow for the z-marching variants */
+  CHECK(emg_autotune(p, EMG_FP64, 5, 0, &ntuned), EMG_OK);
+  if (ntuned != 0) {
+    fprintf(stderr, "FAIL autotune measured %d levels\n", ntuned);
+    failures++;
+  }
+  CHECK(emg_autotune(p, EMG_FP64, 0, 0, &ntuned), EMG_EINVAL);
+  CHECK(emg_autotune_reset(), EMG_OK);
   int64_t m[3];
   stored(&d3, m);
   double *u = (double *)malloc(sizeof(double) * 3 * m[0] * m[1] * m[2]);
