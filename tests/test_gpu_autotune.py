@@ -103,3 +103,40 @@ def test_autotune_argument_errors(emg, ctx):
     with pytest.raises(emg.EmgError):
         prob.autotune("fp64", reps=0)
     prob.close()
+
+
+def test_tuned_plan_reaches_batches(emg, ctx, tmp_path, monkeypatch):
+    """A table entry also steers the batched plans (one launch per cycle
+    step over several problems): with the 64x64x65 level forced to the
+    z-marching pass (3 chunks per column, which the cost model never picks
+    there), a batch of two 65^3 polycrystals gives each problem the
+    displacement and cycle count of its own solve under the cost model."""
+    cache = tmp_path / "tune.json"
+    emg.autotune_reset()
+    try:
+        specs = [synth.polycrystal_3d(n=65, grains=g, seed=s) for g, s in ((8, 7), (12, 9))]
+        probs = [emg.Problem.from_spec(ctx, sp) for sp in specs]
+        ref = {}
+        for p in PRECS:
+            for i, pr in enumerate(probs):
+                st = pr.solve(rtol=1e-10, max_cycles=300, precision=p)
+                ref[p, i] = (st["cycles"], pr.displacement().copy())
+        assert probs[0].level_zmarch(0, "fp64") == 0 and probs[0].level_zmarch(0, "mixed") == 0
+        cache.write_text(json.dumps({"gfx950/fp64/64x64x65/p3": 3, "gfx950/fp32/64x64x65/p3": 3}))
+        monkeypatch.setenv("EMG_TUNE_CACHE", str(cache))
+        emg.autotune_reset()
+        arch_ok = probs[0].level_zmarch(0, "fp64") == 3
+        if not arch_ok:
+            pytest.skip("device architecture is not gfx950")
+        assert probs[0].level_zmarch(0, "mixed") == 3
+        for p in PRECS:
+            print(f"[gpu] tuned batch {p}", flush=True)
+            sts = emg.solve_batch(probs, rtol=1e-10, max_cycles=300, precision=p)
+            for i, pr in enumerate(probs):
+                assert sts[i]["cycles"] == ref[p, i][0]
+                np.testing.assert_array_equal(pr.displacement(), ref[p, i][1])
+        for pr in probs:
+            pr.close()
+    finally:
+        monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
+        emg.autotune_reset()
