@@ -42,7 +42,8 @@ class emg_domain(ctypes.Structure):
 class emg_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("max_cycles", c_int), ("precision", c_int), ("nu1", c_int), ("nu2", c_int),
                 ("omega", c_double), ("warm_start", c_int), ("check_every", c_int), ("use_graph", c_int),
-                ("cycle", c_int), ("stall_iters", c_int), ("stall_factor", c_double)]
+                ("cycle", c_int), ("stall_iters", c_int), ("stall_factor", c_double),
+                ("inner_cycles", c_int)]
 
 
 class emg_solve_stats(ctypes.Structure):

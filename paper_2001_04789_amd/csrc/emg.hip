@@ -125,13 +125,14 @@ struct emg_problem {
   hipStream_t own = nullptr, stream = nullptr;
   bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
   int force_nzc = -1;   // >= 0: stencil-pass variant under measurement by emg_autotune
+  int inner = 1;        // FP32 cycles per mixed refinement step (set by emg_solve for its duration)
   std::vector<void *> allocs;
   size_t bytes = 0;
   size_t accounted = 0;   // bytes charged to the context's HBM budget
   bool counted = false;   // counted in the context's live objects
   // graph cache: key = (precision, cycles per replay, nu1, nu2, cycle type, omega)
   struct GraphEntry {
-    int prec, k, nu1, nu2, fcyc;
+    int prec, k, nu1, nu2, fcyc, inner;
     double omega;
     hipGraphExec_t exec;
   };
@@ -641,7 +642,9 @@ int mixed_result_buf(const emg_problem *p, int nu1, int nu2) {
 // correction, zero at the start), FP64 residual written as FP32 to the
 // level-0 FP32 right-hand side with its norm, convergence check, then one
 // FP32 V-cycle (F-cycle with fcyc) for the new correction e, left in
-// u32[mixed_result_buf()] of level 0 where the next step reads it.
+// u32[mixed_result_buf()] of level 0 where the next step reads it.  With
+// p->inner > 1 the further cycles continue from that correction (same FP32
+// right-hand side) before the step ends.
 void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc) {
   Level &L0 = p->lv[0];
   const long long nd0 = (long long)p->D * L0.g.N;
@@ -661,7 +664,8 @@ void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc)
     launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
   }
   launch_check(p, stencil_blocks(L0.g), 0);
-  const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, -1, nzc > 0);
+  int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, -1, nzc > 0);
+  for (int i = 1; i < p->inner; i++) cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, cb);
   if (cb != eb) launch_cast<float, float>(p, nd0, L0.u32[cb], L0.u32[eb], p->ctl);   // equal by construction
 }
 
@@ -891,7 +895,8 @@ void record_cycles(emg_problem *p, int prec, int k, int nu1, int nu2, double ome
 emg_status get_graph(emg_problem *p, int prec, int k, int nu1, int nu2, double omega, bool fcyc,
                      hipGraphExec_t *out) {
   for (auto &g : p->graphs)
-    if (g.prec == prec && g.k == k && g.nu1 == nu1 && g.nu2 == nu2 && g.omega == omega && g.fcyc == (int)fcyc) {
+    if (g.prec == prec && g.k == k && g.nu1 == nu1 && g.nu2 == nu2 && g.omega == omega && g.fcyc == (int)fcyc &&
+        g.inner == p->inner) {
       *out = g.exec;
       return EMG_OK;
     }
@@ -902,7 +907,7 @@ emg_status get_graph(emg_problem *p, int prec, int k, int nu1, int nu2, double o
   hipGraphExec_t exec;
   HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   HIPCK(hipGraphDestroy(graph));
-  p->graphs.push_back({prec, k, nu1, nu2, (int)fcyc, omega, exec});
+  p->graphs.push_back({prec, k, nu1, nu2, (int)fcyc, p->inner, omega, exec});
   *out = exec;
   return EMG_OK;
 }
@@ -1776,6 +1781,7 @@ void emg_default_opts(emg_solve_opts *o) {
   o->cycle = EMG_VCYCLE;
   o->stall_iters = 24;
   o->stall_factor = 0.5;
+  o->inner_cycles = 1;
 }
 
 emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out) {
@@ -1961,6 +1967,15 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   if (opt.cycle != EMG_VCYCLE && opt.cycle != EMG_FCYCLE) return fail(EMG_EINVAL, "bad cycle type");
   if (opt.stall_iters < 0 || (opt.stall_iters > 0 && !(opt.stall_factor > 0.0 && opt.stall_factor < 1.0)))
     return fail(EMG_EINVAL, "bad stall test");
+  if (opt.inner_cycles < 1 || opt.inner_cycles > 4) return fail(EMG_EINVAL, "inner_cycles must lie in 1..4");
+  if (opt.inner_cycles > 1 && (opt.precision != EMG_MIXED || !p->fine.empty()))
+    return fail(EMG_EINVAL, "inner_cycles > 1 needs a single-level mixed-precision solve");
+  const int inner = opt.inner_cycles;
+  p->inner = inner;
+  struct InnerReset {
+    emg_problem *p;
+    ~InnerReset() { p->inner = 1; }
+  } inner_reset{p};
   const int k = std::max(1, opt.check_every);
   const auto t0 = std::chrono::steady_clock::now();
   TRY(setup(p));
@@ -1971,7 +1986,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   Ctl c0{};
   c0.r0sq = -1.0;
   c0.tol2 = opt.rtol * opt.rtol;
-  c0.max_cycles = opt.max_cycles;
+  c0.max_cycles = (opt.max_cycles + inner - 1) / inner;   // refinement steps
   *p->ctl_host = c0;
   HIPCK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, p->stream));
   if (!p->fine.empty()) {
@@ -2020,6 +2035,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   bool fell_back = false;
   double win_rsq = -1.0;   // stall test: residual at the start of the current window
   int win_start = 0;
+  int fb_steps = -1;   // refinement steps done when FP64 cycles took over
   for (;;) {
     if (exec)
       HIPCK(hipGraphLaunch(exec, p->stream));
@@ -2041,6 +2057,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
         // cycle count and cap
         prec = EMG_FP64;
         fell_back = true;
+        fb_steps = h.cycles;
         exec = nullptr;
         if (opt.use_graph) TRY(get_graph(p, EMG_FP64, k, opt.nu1, opt.nu2, opt.omega, fcyc, &exec));
       }
@@ -2054,10 +2071,11 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     HIPCK(hipStreamSynchronize(p->stream));
   }
   emg_solve_stats s{};
-  s.cycles = c.cycles;
+  // V-cycles: inner per refinement step, one per FP64 cycle after a fallback
+  s.cycles = fb_steps >= 0 ? fb_steps * inner + (c.cycles - fb_steps) : c.cycles * inner;
   s.rel_res = c.r0sq > 0 ? std::sqrt(c.rsq / c.r0sq) : 0.0;
   s.converged = c.done == 1;
-  s.conv_factor = (c.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / c.cycles) : 0.0;
+  s.conv_factor = (s.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / s.cycles) : 0.0;
   s.solve_seconds = std::chrono::duration<double>(t3 - t2).count();
   s.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
   long long dir_nodes = 0;
@@ -2375,6 +2393,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   if (o) opt = *o;
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
+  if (opt.inner_cycles != 1) return fail(EMG_EINVAL, "inner_cycles applies to emg_solve only");
   if (!(opt.omega > 0.0 && opt.omega < 2.0) || opt.warm_start) return fail(EMG_EINVAL, "bad omega or warm start");
   if (opt.cycle != EMG_VCYCLE) return fail(EMG_EINVAL, "batched solves run V-cycles only");
   std::vector<emg_problem *> ps(probs, probs + n);
@@ -2454,7 +2473,7 @@ emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *
   if (o) S->opt = *o;
   if ((S->opt.precision != EMG_FP64 && S->opt.precision != EMG_MIXED) || S->opt.nu1 < 1 || S->opt.nu2 < 0 ||
       S->opt.nu1 > 16 || S->opt.nu2 > 16 || !(S->opt.omega > 0.0 && S->opt.omega < 2.0) || S->opt.warm_start ||
-      S->opt.cycle != EMG_VCYCLE) {
+      S->opt.cycle != EMG_VCYCLE || S->opt.inner_cycles != 1) {
     delete S;
     return fail(EMG_EINVAL, "bad solve options");
   }

@@ -1,0 +1,90 @@
+"""Mixed-precision refinement with several FP32 cycles per FP64 step
+(emg_solve_opts.inner_cycles): each step computes one FP64 residual, runs
+inner_cycles FP32 cycles on it (the later ones continuing from the
+correction) and applies the correction once.  The solution must meet the
+same bar as with one cycle per step: relative residual 1e-10 and within
+1e-8 of the oracle's (small cases) or of the FP64 GPU solution (a 97^3
+polycrystal on the z-marching pass); the cycle count is a multiple of
+inner_cycles and close to the one-cycle count, since the FP32 cycles
+contract the error as FP64 ones do until FP32 rounding (~1e-7 of the
+correction) is reached."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def emg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_04789_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(emg):
+    c = emg.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def check_inner(prob, inner, one):
+    st = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed", inner_cycles=inner)
+    assert st["converged"] and st["rel_res"] <= 1e-10 and st["fp64_fallback"] == 0
+    assert st["cycles"] % inner == 0
+    assert one - inner <= st["cycles"] <= one + 2 * inner, (st["cycles"], one)
+    return st
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+@pytest.mark.parametrize("case", ["poly17", "incl2d"])
+def test_inner_cycles_match_oracle(emg, ctx, case, inner):
+    spec = synth.polycrystal_3d(n=17, grains=8, seed=11) if case == "poly17" else synth.inclusion_2d(n=65)
+    print(f"[gpu] inner {case} {inner}", flush=True)
+    ref = oracle.solve(spec, tol=1e-13, max_cycles=400)
+    prob = emg.Problem.from_spec(ctx, spec)
+    one = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed")["cycles"]
+    check_inner(prob, inner, one)
+    u = prob.displacement()
+    assert rel(u, ref.u) <= 1e-8
+    # eager launches give the graph's result bit for bit
+    prob.solve(rtol=1e-10, max_cycles=400, precision="mixed", inner_cycles=inner, use_graph=0)
+    assert np.array_equal(prob.displacement(), u)
+    prob.close()
+
+
+def test_inner_cycles_zmarch_polycrystal(emg, ctx):
+    spec = synth.polycrystal_3d(n=97, grains=16, seed=5)
+    prob = emg.Problem.from_spec(ctx, spec)
+    assert prob.level_zmarch(0, "fp64") > 0 and prob.level_zmarch(0, "mixed") > 0
+    print("[gpu] inner 97^3", flush=True)
+    prob.solve(rtol=1e-13, max_cycles=400, precision="fp64")
+    u64 = prob.displacement()
+    one = prob.solve(rtol=1e-10, max_cycles=400, precision="mixed")["cycles"]
+    st = check_inner(prob, 2, one)
+    assert rel(prob.displacement(), u64) <= 1e-8
+    # a cap below the converged count stops at a whole step
+    st = prob.solve(rtol=1e-10, max_cycles=9, precision="mixed", inner_cycles=2, raise_on_error=False)
+    assert st["status"] == emg.EMG_ENOTCONV and st["cycles"] == 10
+    prob.close()
+
+
+def test_inner_cycles_rejected(emg, ctx):
+    spec = synth.polycrystal_3d(n=17, grains=8, seed=11)
+    prob = emg.Problem.from_spec(ctx, spec)
+    for kw in (dict(precision="fp64", inner_cycles=2), dict(precision="mixed", inner_cycles=0),
+               dict(precision="mixed", inner_cycles=5)):
+        with pytest.raises(emg.EmgError):
+            prob.solve(rtol=1e-10, **kw)
+    with pytest.raises(emg.EmgError):
+        emg.solve_batch([prob], rtol=1e-10, precision="mixed", inner_cycles=2)
+    prob.close()
