@@ -1,5 +1,6 @@
 /* The C ABI (include/emg.h) driven from plain C, with no Python in between:
- * a context; single-level FP64 / mixed / F-cycle solves with a warm start;
+ * a context; single-level FP64 / mixed (one and two FP32 cycles per
+ * refinement step) / F-cycle solves with a warm start;
  * the autotuner on a level too narrow for its variants;
  * displacement, stress and von Mises read-back; a ragged batch of three
  * problems; a three-level AMR problem in both precisions; a server taking
@@ -124,6 +125,13 @@ int main(void) {
   CHECK(emg_solve(p, &o, &st), EMG_OK);
   o.precision = EMG_MIXED;
   CHECK(emg_solve(p, &o, &st), EMG_OK);
+  o.inner_cycles = 2;   /* two FP32 cycles per refinement step */
+  CHECK(emg_solve(p, &o, &st), EMG_OK);
+  if (st.cycles % 2 != 0 || !st.converged) {
+    fprintf(stderr, "FAIL inner_cycles=2: %d cycles, converged %d\n", st.cycles, st.converged);
+    failures++;
+  }
+  o.inner_cycles = 1;
   o.cycle = EMG_FCYCLE;
   o.warm_start = 1;
   CHECK(emg_solve(p, &o, &st), EMG_OK);
