@@ -101,7 +101,8 @@ typedef struct {
                         current iterate (emg_solve_stats.fp64_fallback = 1).  Default 24; 0 turns
                         the test off; read at host convergence reads (every check_every) */
   double stall_factor; /* in (0, 1); default 0.5 */
-  int inner_cycles;  /* EMG_MIXED single-level emg_solve only (EMG_EINVAL elsewhere if not 1):
+  int inner_cycles;  /* EMG_MIXED only (EMG_EINVAL for FP64 or refined levels if not 1; also
+                        taken by emg_solve_batch and the server):
                         FP32 cycles per FP64 refinement step, 1..4 (default 1).  Each step
                         computes one FP64 residual and applies one correction; the cycles
                         after the first continue the FP32 correction from its iterate.  The

@@ -1135,7 +1135,10 @@ struct Planner {
   // level 0 of the correction cycle for the mixed path (from zero) / the
   // FP64 path (on the iterate); ends with the result in buffer 0
   template <typename R>
-  void level0(int nu1, int nu2, bool from_zero) {
+  // Level-0 cycle: from zero (FP32 correction), or from the iterate in
+  // buffer 0 with the residual norm and convergence check of its first sweep
+  // (norm; FP64), or without them (a continuing FP32 correction cycle).
+  void level0(int nu1, int nu2, bool from_zero, bool norm = true) {
     constexpr bool F = std::is_same<R, float>::value;
     int cur;
     if (from_zero) {
@@ -1149,6 +1152,18 @@ struct Planner {
         return true;
       });
       cur = 0;
+    } else if (!norm) {
+      step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
+        Level &L = p->lv[0];
+        e = ent_level(L.g);
+        e.C = moduli<R>(L);
+        e.a = U<R>(L, 0);
+        e.b = fbuf<R>(L);
+        e.out = U<R>(L, 1);
+        e.ctl = p->ctl;
+        return true;
+      });
+      cur = 1;
     } else {
       step(BK_JACOBI_NORM, F, [&](emg_problem *p, BEnt &e) {
         Level &L = p->lv[0];
@@ -1273,13 +1288,14 @@ struct Planner {
     check(0);
   }
 
-  void cycles(int prec, int k, int nu1, int nu2) {
+  void cycles(int prec, int k, int nu1, int nu2, int inner) {
     for (int c = 0; c < k; c++) {
       if (prec == EMG_FP64) {
         level0<double>(nu1, nu2, false);
       } else {
         mixed_outer();
         level0<float>(nu1, nu2, true);
+        for (int i = 1; i < inner; i++) level0<float>(nu1, nu2, false, false);
       }
     }
   }
@@ -1414,7 +1430,7 @@ emg_status prepare(emg_problem *p, const emg_solve_opts &opt, hipStream_t st) {
     Ctl c0{};
     c0.r0sq = -1.0;
     c0.tol2 = opt.rtol * opt.rtol;
-    c0.max_cycles = opt.max_cycles;
+    c0.max_cycles = (opt.max_cycles + opt.inner_cycles - 1) / opt.inner_cycles;   // refinement steps
     *p->ctl_host = c0;
     if (hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, st) != hipSuccess)
       s = fail(EMG_EDEVICE, "control block upload failed");
@@ -1423,12 +1439,12 @@ emg_status prepare(emg_problem *p, const emg_solve_opts &opt, hipStream_t st) {
   return s;
 }
 
-void fill_stats(emg_problem *p, const Ctl &c, emg_solve_stats *st) {
+void fill_stats(emg_problem *p, const Ctl &c, int steps_per, emg_solve_stats *st) {
   emg_solve_stats s{};
-  s.cycles = c.cycles;
+  s.cycles = c.cycles * steps_per;   // V-cycles: inner_cycles per refinement step
   s.rel_res = c.r0sq > 0 ? std::sqrt(c.rsq / c.r0sq) : 0.0;
   s.converged = c.done == 1;
-  s.conv_factor = (c.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / c.cycles) : 0.0;
+  s.conv_factor = (s.cycles > 0 && s.rel_res > 0) ? std::pow(s.rel_res, 1.0 / s.cycles) : 0.0;
   const Geom &g = p->lv[0].g;
   long long inner = 1;
   for (int a = 0; a < g.dim; a++) {
@@ -1612,7 +1628,7 @@ void finish(emg_server *S, Served *r, emg_status st) {
   if (r->p && (st == EMG_OK || st == EMG_ENOTCONV)) {
     if (r->u_out)
       (void)copy_out(r->p, r->u_out, r->p->lv[0].u64[0], (size_t)r->p->D * r->p->lv[0].g.N, r->on_device);
-    fill_stats(r->p, *r->p->ctl_host, &r->stats);
+    fill_stats(r->p, *r->p->ctl_host, S->opt.inner_cycles, &r->stats);
     r->stats.solve_seconds = r->t_done - r->t_ready;
     r->stats.setup_seconds = r->t_ready - r->t_admit;
   }
@@ -1705,7 +1721,7 @@ void serve_loop(emg_server *S) {
       std::vector<emg_problem *> ps;
       for (auto *r : S->active) ps.push_back(r->p);
       Planner pl(ps);
-      pl.cycles(S->opt.precision, k, S->opt.nu1, S->opt.nu2);
+      pl.cycles(S->opt.precision, k, S->opt.nu1, S->opt.nu2, S->opt.inner_cycles);
       plan = std::move(pl.plan);
       bool grew = false;
       if (upload_plan(plan, S->dev, S->stream, S->slots, 256, &grew) != EMG_OK) {
@@ -2393,7 +2409,8 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   if (o) opt = *o;
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
   if (opt.nu1 < 1 || opt.nu2 < 0 || opt.nu1 > 16 || opt.nu2 > 16) return fail(EMG_EINVAL, "bad sweep counts");
-  if (opt.inner_cycles != 1) return fail(EMG_EINVAL, "inner_cycles applies to emg_solve only");
+  if (opt.inner_cycles < 1 || opt.inner_cycles > 4 || (opt.inner_cycles > 1 && opt.precision != EMG_MIXED))
+    return fail(EMG_EINVAL, "inner_cycles must lie in 1..4 (above 1 in mixed precision only)");
   if (!(opt.omega > 0.0 && opt.omega < 2.0) || opt.warm_start) return fail(EMG_EINVAL, "bad omega or warm start");
   if (opt.cycle != EMG_VCYCLE) return fail(EMG_EINVAL, "batched solves run V-cycles only");
   std::vector<emg_problem *> ps(probs, probs + n);
@@ -2411,7 +2428,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   HIPCK(hipStreamSynchronize(st));
   const auto t1 = std::chrono::steady_clock::now();
   Planner pl(ps);
-  pl.cycles(opt.precision, std::max(1, opt.check_every), opt.nu1, opt.nu2);
+  pl.cycles(opt.precision, std::max(1, opt.check_every), opt.nu1, opt.nu2, opt.inner_cycles);
   BatchDev dev;
   emg_status s = upload_plan(pl.plan, dev, st);
   hipGraphExec_t exec = nullptr;
@@ -2450,7 +2467,7 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   for (int i = 0; i < n; i++) {
     const Ctl c = *ps[i]->ctl_host;
     emg_solve_stats one;
-    fill_stats(ps[i], c, &one);
+    fill_stats(ps[i], c, opt.inner_cycles, &one);
     one.solve_seconds = std::chrono::duration<double>(t3 - t2).count();
     one.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
     if (stats) stats[i] = one;
@@ -2473,7 +2490,8 @@ emg_status emg_server_create(emg_ctx *ctx, int max_slots, const emg_solve_opts *
   if (o) S->opt = *o;
   if ((S->opt.precision != EMG_FP64 && S->opt.precision != EMG_MIXED) || S->opt.nu1 < 1 || S->opt.nu2 < 0 ||
       S->opt.nu1 > 16 || S->opt.nu2 > 16 || !(S->opt.omega > 0.0 && S->opt.omega < 2.0) || S->opt.warm_start ||
-      S->opt.cycle != EMG_VCYCLE || S->opt.inner_cycles != 1) {
+      S->opt.cycle != EMG_VCYCLE || S->opt.inner_cycles < 1 || S->opt.inner_cycles > 4 ||
+      (S->opt.inner_cycles > 1 && S->opt.precision != EMG_MIXED)) {
     delete S;
     return fail(EMG_EINVAL, "bad solve options");
   }

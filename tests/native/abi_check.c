@@ -188,6 +188,7 @@ int main(void) {
   emg_server *srv = NULL;
   emg_default_opts(&o);
   o.precision = EMG_MIXED;
+  o.inner_cycles = 2;
   CHECK(emg_server_create(ctx, 3, &o, &srv), EMG_OK);
   uint64_t tickets[12];
   double *outs[12];

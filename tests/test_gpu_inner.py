@@ -86,5 +86,27 @@ def test_inner_cycles_rejected(emg, ctx):
         with pytest.raises(emg.EmgError):
             prob.solve(rtol=1e-10, **kw)
     with pytest.raises(emg.EmgError):
-        emg.solve_batch([prob], rtol=1e-10, precision="mixed", inner_cycles=2)
+        emg.solve_batch([prob], rtol=1e-10, precision="fp64", inner_cycles=2)
     prob.close()
+
+
+def test_inner_cycles_batch_bitwise_equals_solo(emg, ctx):
+    """A ragged batch with two FP32 cycles per step gives every member the
+    displacement and cycle count of its own emg_solve, bit for bit."""
+    specs = [synth.polycrystal_3d(n=17, grains=8, seed=11), synth.inclusion_3d(n=33, seed=3),
+             synth.inclusion_2d(n=65)]
+    solo = []
+    for sp in specs:
+        p = emg.Problem.from_spec(ctx, sp)
+        st = p.solve(rtol=1e-10, max_cycles=400, precision="mixed", inner_cycles=2)
+        solo.append((st["cycles"], p.displacement()))
+        p.close()
+    print("[gpu] inner batch", flush=True)
+    probs = [emg.Problem.from_spec(ctx, sp) for sp in specs]
+    stats = emg.solve_batch(probs, rtol=1e-10, max_cycles=400, precision="mixed", inner_cycles=2)
+    for sp, p, st, (c, u) in zip(specs, probs, stats, solo):
+        assert st["converged"] and st["rel_res"] <= 1e-10 and st["cycles"] % 2 == 0, sp.name
+        assert st["cycles"] == c, (sp.name, st["cycles"], c)
+        assert np.array_equal(p.displacement(), u), sp.name
+    for p in probs:
+        p.close()
