@@ -84,20 +84,23 @@ typedef struct {
 typedef struct {
   double rtol;       /* stop when ||r||_2 / ||r_0||_2 <= rtol (default 1e-10); the norm runs over
                         non-Dirichlet rows, r_0 is the residual of the Dirichlet lift */
-  int max_cycles;    /* cap on V-cycles (FP64) or refinement iterations (mixed); default 200 */
+  int max_cycles;    /* cap on V-cycles, default 200.  EMG_MIXED: each refinement step runs
+                        inner_cycles FP32 V-cycles, so the cap is rounded up to whole steps; after
+                        an FP64 fallback every FP64 V-cycle counts one against what is left */
   int precision;     /* EMG_FP64: V-cycles in FP64.  EMG_MIXED: FP64 residual and update around
                         one FP32 V-cycle per iteration, FP64 coarsest solve */
   int nu1, nu2;      /* damped-Jacobi sweeps before / after the coarse correction (default 2, 2) */
   double omega;      /* Jacobi damping (default 2/3) */
   int warm_start;    /* 1: start from the current displacement instead of the Dirichlet lift */
-  int check_every;   /* cycles per device-side launch between host convergence reads (default 4);
-                        cycles after convergence inside a launch are skipped on the device */
+  int check_every;   /* V-cycles (EMG_FP64) or refinement steps (EMG_MIXED) per device-side launch
+                        between host convergence reads (default 4); those after convergence inside
+                        a launch are skipped on the device */
   int use_graph;     /* 1 (default): replay captured HIP graphs; 0: launch kernels eagerly */
   int cycle;         /* emg_cycle (default EMG_VCYCLE); emg_solve_batch and the server take
                         EMG_VCYCLE only (EMG_EINVAL otherwise) */
   int stall_iters;   /* EMG_MIXED in emg_solve: if the FP64 residual norm has not fallen below
                         stall_factor times its value at the start of a window of stall_iters
-                        refinement iterations, the solve continues with FP64 cycles from the
+                        refinement steps (not V-cycles), the solve continues with FP64 cycles from the
                         current iterate (emg_solve_stats.fp64_fallback = 1).  Default 24; 0 turns
                         the test off; read at host convergence reads (every check_every) */
   double stall_factor; /* in (0, 1); default 0.5 */

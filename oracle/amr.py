@@ -304,8 +304,6 @@ class Composite:
             fl = self.fines[k - 1]
             g, C = fl.grid, fl.C
             ec = e[k - 1].copy()
-            if k - 1 >= 1:
-                pass
             pe = interp_to_box(ec, self.origin(k - 1), fl)
             ghost = np.ones(fl.shape, dtype=bool)
             ghost[(slice(None),) + fl.valid()] = False

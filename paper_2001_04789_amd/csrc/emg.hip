@@ -666,7 +666,9 @@ void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc)
   launch_check(p, stencil_blocks(L0.g), 0);
   int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, -1, nzc > 0);
   for (int i = 1; i < p->inner; i++) cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, cb);
-  if (cb != eb) launch_cast<float, float>(p, nd0, L0.u32[cb], L0.u32[eb], p->ctl);   // equal by construction
+  // a continuing cycle flips the buffer nu1 + nu2 times: with an odd count
+  // the correction ends in the other buffer and is moved back to u32[eb]
+  if (cb != eb) launch_cast<float, float>(p, nd0, L0.u32[cb], L0.u32[eb], p->ctl);
 }
 
 // ---- AMR helpers ----
@@ -2074,6 +2076,11 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
         prec = EMG_FP64;
         fell_back = true;
         fb_steps = h.cycles;
+        // the cap counts V-cycles: fb_steps steps used inner V-cycles each,
+        // every FP64 cycle from here on counts one
+        p->ctl_host->max_cycles = fb_steps + std::max(0, opt.max_cycles - fb_steps * inner);
+        HIPCK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, p->stream));
+        HIPCK(hipStreamSynchronize(p->stream));
         exec = nullptr;
         if (opt.use_graph) TRY(get_graph(p, EMG_FP64, k, opt.nu1, opt.nu2, opt.omega, fcyc, &exec));
       }

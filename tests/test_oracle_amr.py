@@ -193,3 +193,201 @@ def test_amr_approaches_uniform_fine():
     err_amr = np.abs(ua[1] - ref)[:, :, 1:-1, 1:-1].max()
     err_coarse = np.abs(coarse_on_fine - ref)[:, :, 1:-1, 1:-1].max()
     assert err_amr < 0.5 * err_coarse
+
+
+# ---- coarse-under-fine averaging (Sec. 1: coarse levels are updated from
+# the finer levels by averaging) ----
+#
+# Full weighting is the tensor product of [1/4, 1/2, 1/4] over the fine
+# neighbours of the coincident fine node.  On a quadratic
+#   q(x) = sum_a A_aa x_a^2 + sum_{a<b} A_ab x_a x_b + b.x + c
+# it returns q(x0) + (h_f^2 / 2) sum_a A_aa exactly: each factor x_a^2
+# averages to x0_a^2 + h_f^2/2, each x_a to x0_a, and the cross terms are
+# products of averaged linear factors.  Injection would return q(x0).
+
+def _quadratic(rng, dim):
+    A = rng.uniform(-2.0, 2.0, size=(3, 3))
+    b = rng.uniform(-1.0, 1.0, size=3)
+    c = rng.uniform(3.0, 4.0)
+
+    def q(x, y, z):
+        X = (x, y, z)
+        v = c + 0.0 * x * y * z
+        for a in range(dim):
+            v = v + b[a] * X[a] + A[a, a] * X[a] ** 2
+            for e in range(a + 1, dim):
+                v = v + A[a, e] * X[a] * X[e]
+        return v
+    return q, sum(A[a, a] for a in range(dim))
+
+
+def _averaging_case(dim, seed=7):
+    """Base grid with constant (lambda, mu), one fine box whose moduli and
+    eigenstrain are quadratics; returns the composite and the quadratics."""
+    rng = np.random.default_rng(seed)
+    ql, tl = _quadratic(rng, dim)
+    qm, tm = _quadratic(rng, dim)
+    qe, te = _quadratic(rng, dim)
+    if dim == 2:
+        p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, 1.5, 1.0, n=17)
+        lo, hi = (8, 8, 0), (24, 24, 0)
+    else:
+        p = synth.random_problem(3, (9, 9, 9), ("dirichlet",) * 6, "iso", seed=3, with_eps0=False,
+                                 with_face_data=False)
+        p.C = np.stack([np.full(p.C.shape[1:], 1.5), np.full(p.C.shape[1:], 1.0)])
+        lo, hi = (4, 4, 4), (12, 12, 12)
+    ne = 6 if dim == 3 else 3
+    p.eps0 = np.zeros((ne,) + p.C.shape[1:])
+    fl = _fine(p, lo, hi, lambda x, y, z: np.stack([ql(x, y, z), qm(x, y, z)]))
+    X, Y, Z = np.broadcast_arrays(*_box_axes(p, lo, hi))
+    fl.eps0 = np.stack([qe(X, Y, Z) * (0.1 * (i + 1)) for i in range(ne)])
+    comp = amr.Composite(p, [fl])
+    return p, comp, (ql, tl), (qm, tm), (qe, te), lo, hi
+
+
+def _box_axes(p, lo, hi):
+    h = [p.h[a] / 2 for a in range(3)]
+    ax = [p.lo[a] + h[a] * np.arange(lo[a] - 1, hi[a] + 2) if a < p.dim else np.zeros(1) for a in range(3)]
+    return ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None]
+
+
+def _covered_coords(p, lo, hi):
+    """Coordinates and base-array slices of the coarse nodes under the box."""
+    sl, ax = [], []
+    for a in (2, 1, 0):
+        if a >= p.dim:
+            sl.append(slice(None)); ax.append(np.zeros(1)); continue
+        idx = np.arange(lo[a] // 2, hi[a] // 2 + 1)
+        sl.append(slice(idx[0], idx[-1] + 1))
+        ax.append(p.lo[a] + p.h[a] * idx)
+    Z, Y, X = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    return (X, Y, Z), tuple(sl)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_average_to_coarse_full_weighting_of_quadratics(dim):
+    """Covered coarse moduli and eigenstrain equal the full-weighting value
+    of the quadratic the fine level samples: q(x0) + h_f^2/2 * trace(A)."""
+    p, comp, (ql, tl), (qm, tm), (qe, te), lo, hi = _averaging_case(dim)
+    (X, Y, Z), sl = _covered_coords(p, lo, hi)
+    hf2 = (p.h[0] / 2) ** 2
+    exp_l = ql(X, Y, Z) + 0.5 * hf2 * tl
+    exp_m = qm(X, Y, Z) + 0.5 * hf2 * tm
+    np.testing.assert_allclose(comp.C0[(0,) + sl], exp_l, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(comp.C0[(1,) + sl], exp_m, rtol=1e-13, atol=1e-13)
+    ne = comp.E0.shape[0]
+    for i in range(ne):
+        exp_e = (qe(X, Y, Z) + 0.5 * hf2 * te) * (0.1 * (i + 1))
+        np.testing.assert_allclose(comp.E0[(i,) + sl], exp_e, rtol=1e-13, atol=1e-13)
+    # the correction term is far above rounding, so injection cannot pass
+    assert 0.5 * hf2 * abs(tl) > 1e-5 and 0.5 * hf2 * abs(tm) > 1e-5
+    # nodes outside the box keep the base grid's own values
+    mask = np.ones(comp.C0.shape[1:], dtype=bool)
+    mask[sl] = False
+    assert np.all(comp.C0[0][mask] == 1.5) and np.all(comp.C0[1][mask] == 1.0)
+
+
+def _shell_row_expected(p, comp, lam_at, mu_at, G, node):
+    """Hand-built interior row of the coarse operator for a linear
+    displacement u = G x (no eigenstrain, no body force) in 2D: with the
+    second and mixed differences of a linear field zero and its central
+    differences equal to G, row i is sum_j (s_ij(x + h e_j) - s_ij(x - h e_j))
+    / (2 h) with s = lam tr(G) I + mu (G + G^T) at the axis neighbours."""
+    x, y = node
+    h = p.h[0]
+
+    def s(ix, iy):
+        lam, mu = lam_at(ix, iy), mu_at(ix, iy)
+        tr = G[0, 0] + G[1, 1]
+        return np.array([[lam * tr + 2 * mu * G[0, 0], mu * (G[0, 1] + G[1, 0])],
+                         [mu * (G[0, 1] + G[1, 0]), lam * tr + 2 * mu * G[1, 1]]])
+    row = np.zeros(2)
+    for i in range(2):
+        row[i] = (s(x + 1, y)[i, 0] - s(x - 1, y)[i, 0]) / (2 * h) + (s(x, y + 1)[i, 1] - s(x, y - 1)[i, 1]) / (2 * h)
+    return row
+
+
+def test_average_to_coarse_enters_the_uncovered_shell_rows():
+    """The composite residual at uncovered coarse nodes next to the box, for
+    a linear displacement on every level: minus the hand-built coarse row in
+    which the covered neighbours carry the full-weighting value of the fine
+    quadratic moduli and the uncovered ones the base grid's constants."""
+    p, comp, (ql, tl), (qm, tm), _, lo, hi = _averaging_case(2)
+    comp.E0 = None
+    comp.fines[0].eps0 = None
+    comp.f = [oracle.rhs(comp.g0, comp.C0, None, p.b, p.face)] + [oracle.rhs(comp.fines[0].grid, comp.fines[0].C,
+                                                                             None, None, None)]
+    G = np.array([[1.0e-3, -4.0e-4], [7.0e-4, 2.0e-3]])
+    hf2 = (p.h[0] / 2) ** 2
+    c0, c1 = lo[0] // 2, hi[0] // 2
+
+    def covered(ix, iy):
+        return c0 <= ix <= c1 and c0 <= iy <= c1
+
+    def lam_at(ix, iy):
+        x, y = ix * p.h[0], iy * p.h[1]
+        return ql(x, y, 0.0) + 0.5 * hf2 * tl if covered(ix, iy) else 1.5
+
+    def mu_at(ix, iy):
+        x, y = ix * p.h[0], iy * p.h[1]
+        return qm(x, y, 0.0) + 0.5 * hf2 * tm if covered(ix, iy) else 1.0
+
+    u = []
+    for k in range(2):
+        gk = comp.grid(k)
+        hk = p.h[0] / 2 ** k
+        off = 0 if k == 0 else lo[0] - 1
+        xs = (np.arange(gk.m[0]) + off) * hk
+        ys = (np.arange(gk.m[1]) + off) * hk
+        X, Y = np.meshgrid(xs, ys, indexing="xy")
+        u.append(np.stack([G[0, 0] * X + G[0, 1] * Y, G[1, 0] * X + G[1, 1] * Y])[:, None])
+    r = comp.residual(comp.sync(u))
+    checked = 0
+    for node in [(c0 - 1, 6), (c1 + 1, 7), (5, c0 - 1), (8, c1 + 1), (c0 - 1, c0 + 2)]:
+        exp = -_shell_row_expected(p, comp, lam_at, mu_at, G, node)
+        got = r[0][:, 0, node[1], node[0]]
+        np.testing.assert_allclose(got, exp, rtol=1e-10, atol=1e-14)
+        checked += 1
+    # the averaged moduli move these rows by far more than the tolerance
+    inj = -_shell_row_expected(p, comp, lambda i, j: ql(i * p.h[0], j * p.h[1], 0.0) if covered(i, j) else 1.5,
+                               lambda i, j: qm(i * p.h[0], j * p.h[1], 0.0) if covered(i, j) else 1.0, G,
+                               (c0 - 1, 6))
+    assert np.abs(inj - r[0][:, 0, 6, c0 - 1]).max() > 1e3 * 1e-10 * np.abs(inj).max()
+    assert checked == 5
+
+
+def test_averaging_pins_catch_planted_mistakes(monkeypatch):
+    """The pins above fail for injection and for wrong weights: each variant
+    is planted in the oracle (on the CPU) and the quadratic check rejects it."""
+
+    def check():
+        p, comp, (ql, tl), (qm, tm), _, lo, hi = _averaging_case(2)
+        (X, Y, Z), sl = _covered_coords(p, lo, hi)
+        hf2 = (p.h[0] / 2) ** 2
+        return np.allclose(comp.C0[(0,) + sl], ql(X, Y, Z) + 0.5 * hf2 * tl, rtol=1e-13, atol=1e-13)
+
+    assert check()
+    good = amr.average_to_coarse
+
+    def injection(fl, field):
+        _, fs = amr.covered_slices(fl, (0, 0, 0))
+        return np.asarray(field)[fs]
+
+    def thirds(fl, field):
+        res = np.asarray(field, dtype=np.float64)
+        for a in range(fl.dim):
+            ax = 3 - a
+            n = res.shape[ax]
+            full = (np.take(res, np.arange(1, n - 1), axis=ax) + np.take(res, np.arange(0, n - 2), axis=ax)
+                    + np.take(res, np.arange(2, n), axis=ax)) / 3.0
+            pad = [(0, 0)] * res.ndim
+            pad[ax] = (1, 1)
+            res = np.pad(full, pad)
+        _, fs = amr.covered_slices(fl, (0, 0, 0))
+        return res[fs]
+
+    for bad in (injection, thirds):
+        monkeypatch.setattr(amr, "average_to_coarse", bad)
+        assert not check(), bad.__name__
+    monkeypatch.setattr(amr, "average_to_coarse", good)
+    assert check()
