@@ -40,13 +40,59 @@ ROW_INTERIOR, ROW_TRACTION, ROW_DIRICHLET, ROW_NEUMANN = 0, 1, 2, 3
 _BC = {"dirichlet": DIRICHLET, "traction": TRACTION, "periodic": PERIODIC, "neumann": NEUMANN}
 
 
+# -O3 for the host's instruction set.  The oracle is built where the sources
+# are and may run on another host, so -march=native of the build host could
+# fault there: two builds are made, x86-64-v4 (AVX-512) and x86-64-v3 (AVX2,
+# FMA), and the one the running CPU supports is loaded.
+_LIB_V4 = os.path.join(_HERE, "liboracle_v4.so")
+_BASE_FLAGS = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+_V4_CPU_FLAGS = ("avx512f", "avx512dq", "avx512cd", "avx512bw", "avx512vl")
+
+
+def _cpu_has_v4() -> bool:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("flags"):
+                    have = set(line.split(":", 1)[1].split())
+                    return all(f in have for f in _V4_CPU_FLAGS)
+    except OSError:
+        pass
+    return False
+
+
+def _variants():
+    return [(_LIB, "x86-64-v3"), (_LIB_V4, "x86-64-v4")]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (OpenMP only splits node loops)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (OpenMP only splits node loops), in both
+    instruction-set variants; returns the one this CPU loads."""
+    for path, march in _variants():
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + f".tmp{os.getpid()}"
+            subprocess.check_call(["gcc"] + _BASE_FLAGS + ["-march=" + march, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
+    return _LIB_V4 if _cpu_has_v4() else _LIB
+
+
+def build_flags() -> List[str]:
+    """gcc flags of the variant this CPU loads."""
+    return _BASE_FLAGS + ["-march=" + ("x86-64-v4" if _cpu_has_v4() else "x86-64-v3")]
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's node loops (omp_set_num_threads)."""
+    fn = lib().omp_set_num_threads
+    fn.argtypes = [ctypes.c_int]
+    fn.restype = None
+    fn(int(n))
+
+
+def max_threads() -> int:
+    fn = lib().omp_get_max_threads
+    fn.restype = ctypes.c_int
+    return int(fn())
 
 
 class _Grid(ctypes.Structure):

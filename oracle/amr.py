@@ -1,28 +1,34 @@
 """Oracle of the reflux-free coarse/fine coupling on block-structured AMR
 (Sec. 3.2 "Reflux-free BSAMR extension" and App. A).  TEST INFRASTRUCTURE ONLY.
 
-Levels: level 0 is the base grid (a plain ``Grid``); level k >= 1 is one
-box of nodes [lo, hi] (inclusive, even bounds) in its own index space, with
-spacing h_{k-1}/2, stored with a one-node ghost layer around it (array
-extent hi - lo + 3 per axis).  The box lies inside level k-1's box (or the
-domain) with at least two coarse cells to spare, so no fine node touches the
-domain boundary.
+Levels: level 0 is the base grid (a plain ``Grid``); level k >= 1 (spacing
+h_{k-1}/2) is a list of boxes of nodes [lo, hi] (inclusive, even bounds) in
+its own index space.  The level's valid nodes are the union of its boxes;
+its fields are stored over the bounding box of the union grown by one node
+per side (array extent hi - lo + 3 per axis of the bounding box).  Every box
+grown by two coarse cells lies inside the valid nodes of level k-1 (for
+k = 1: inside the domain, off its boundary), so no fine node touches the
+domain boundary and every ghost is interpolated from valid coarse nodes.
 
 Composite system (the reading of Sec. 3.2 and App. A):
-  * unknowns: every valid node of every fine box, plus the level-0 (and
-    intermediate-level) nodes not covered by the next finer box;
+  * unknowns: every valid node of every refined level, plus the level-0 (and
+    intermediate-level) nodes not covered by valid nodes of the next level;
   * a covered coarse node takes the value of the coincident fine node
     (App. A: phi_c2 = phi_f4);
-  * a fine ghost node takes the bi/trilinear interpolation of the next
-    coarser level (Sec. 3.2: interpolation operator; App. A:
-    phi_f3 = (phi_c1 + phi_c2)/2);
+  * a fine node that is not valid takes the bi/trilinear interpolation of
+    the next coarser level (Sec. 3.2: interpolation operator; App. A:
+    phi_f3 = (phi_c1 + phi_c2)/2); those next to valid nodes are the ghosts
+    the fine rows read;
   * rows: fine valid nodes use the fine operator with those ghosts (the
     coarse/fine boundary layer is relaxed like any fine node, Sec. 3.2);
     uncovered coarse nodes use the coarse operator with injected
-    neighbours; domain-boundary rows as on a single level.
-A fine level is handled as a box grid whose faces are all Dirichlet: its
-outer (ghost) layer are the Dirichlet rows, its valid nodes the interior
-rows, so the single-level primitives apply unchanged.
+    neighbours; domain-boundary rows as on a single level.  Where two boxes
+    of a level meet, their nodes are simply valid nodes: the union, not the
+    box list, defines the rows.
+A refined level is handled as a grid whose faces are all Dirichlet and whose
+non-valid nodes are Dirichlet rows as well (their value is the right-hand
+side: zero or the interpolated ghost value), so the single-level primitives
+apply with that one override.
 """
 from __future__ import annotations
 
@@ -35,16 +41,23 @@ from . import (DIRICHLET, Grid, Hierarchy, ROW_DIRICHLET, apply, dirichlet_mask,
 
 
 class FineLevel:
-    """One refined box: valid nodes [lo, hi] of its level's index space."""
+    """One refined level: the union of boxes of nodes [lo, hi] of its level's
+    index space, stored over their bounding box grown by one node."""
 
-    def __init__(self, parent_h, dim, kind, lo, hi, C, eps0=None, b=None):
+    def __init__(self, parent_h, dim, kind, lo, hi, C, eps0=None, b=None, boxes=None):
         self.dim = dim
-        self.lo = tuple(int(v) for v in lo)
-        self.hi = tuple(int(v) for v in hi)
+        if boxes is None:
+            boxes = [(lo, hi)]
+        self.boxes = [(tuple(int(v) for v in bl), tuple(int(v) for v in bh)) for bl, bh in boxes]
+        self.lo = tuple(min(bl[a] for bl, _ in self.boxes) if a < dim else 0 for a in range(3))
+        self.hi = tuple(max(bh[a] for _, bh in self.boxes) if a < dim else 0 for a in range(3))
+        assert tuple(int(v) for v in lo)[:dim] == self.lo[:dim] and tuple(int(v) for v in hi)[:dim] == self.hi[:dim], \
+            "lo, hi must be the bounding box of the boxes"
         m = [1, 1, 1]
         h = [1.0, 1.0, 1.0]
         for a in range(dim):
-            assert self.lo[a] % 2 == 0 and self.hi[a] % 2 == 0 and self.hi[a] > self.lo[a]
+            for bl, bh in self.boxes:
+                assert bl[a] % 2 == 0 and bh[a] % 2 == 0 and bh[a] > bl[a]
             m[a] = self.hi[a] - self.lo[a] + 3
             h[a] = parent_h[a] / 2.0
         bc = [DIRICHLET] * (2 * dim) + [2] * (6 - 2 * dim)
@@ -53,14 +66,24 @@ class FineLevel:
         self.eps0 = None if eps0 is None else np.array(eps0, dtype=np.float64, order="C", copy=True)
         self.b = None if b is None else np.array(b, dtype=np.float64, order="C", copy=True)
         assert self.C.shape[1:] == (m[2], m[1], m[0])
+        # valid nodes: the union of the boxes, in array coordinates [z][y][x]
+        self.valid_mask = np.zeros((m[2], m[1], m[0]), dtype=bool)
+        for bl, bh in self.boxes:
+            sl = tuple(slice(bl[a] - self.lo[a] + 1, bh[a] - self.lo[a] + 2) if a < dim else slice(None)
+                       for a in (2, 1, 0))
+            self.valid_mask[sl] = True
 
     @property
     def shape(self):
         return self.grid.shape(self.dim)
 
-    def valid(self):
-        """Slices of the valid nodes inside the ghosted array ([z][y][x])."""
-        return tuple(slice(1, self.grid.m[a] - 1) if a < self.dim else slice(None) for a in (2, 1, 0))
+    def valid_full(self):
+        """Valid-node mask broadcast over the vector components."""
+        return np.broadcast_to(self.valid_mask, self.shape)
+
+    def global_index(self, a, i):
+        """Level index along axis a of array index i."""
+        return self.lo[a] - 1 + i
 
 
 def _axis_interp(lo_f, n_f, coarse_index_of):
@@ -98,24 +121,39 @@ def interp_to_box(uc: np.ndarray, coarse_origin, fine: FineLevel) -> np.ndarray:
     return np.ascontiguousarray(out)
 
 
+def covered_index(fine: FineLevel, coarse_origin):
+    """Index arrays ([z][y][x], with a leading component slice) of the
+    coarse nodes coincident with valid fine nodes, in the coarse array
+    (whose index 0 is coarse index ``coarse_origin``), and of those fine
+    nodes in the fine array; in storage order of the fine array."""
+    sel = fine.valid_mask.copy()
+    for a in range(fine.dim):
+        ax = 2 - a
+        idx = np.arange(sel.shape[ax])
+        even = (fine.lo[a] - 1 + idx) % 2 == 0
+        shp = [1, 1, 1]
+        shp[ax] = -1
+        sel &= even.reshape(shp)
+    fz, fy, fx = np.nonzero(sel)
+    f = (fz, fy, fx)
+    c = []
+    for ax, a in ((0, 2), (1, 1), (2, 0)):
+        if a < fine.dim:
+            c.append((fine.lo[a] - 1 + f[ax]) // 2 - coarse_origin[a])
+        else:
+            c.append(f[ax])
+    return (slice(None),) + tuple(c), (slice(None),) + f
+
+
 def covered_slices(fine: FineLevel, coarse_origin):
-    """Array slices (in the coarse array) of the coarse nodes coincident with
-    the fine box's valid nodes, and the matching fine-array slices."""
-    cs, fs = [], []
-    for a in (2, 1, 0):
-        if a >= fine.dim:
-            cs.append(slice(None)); fs.append(slice(None)); continue
-        c0 = fine.lo[a] // 2 - coarse_origin[a]
-        c1 = fine.hi[a] // 2 - coarse_origin[a]
-        cs.append(slice(c0, c1 + 1))
-        fs.append(slice(1, fine.grid.m[a] - 1, 2))
-    return (slice(None),) + tuple(cs), (slice(None),) + tuple(fs)
+    """Same as covered_index (kept for callers of the one-box form)."""
+    return covered_index(fine, coarse_origin)
 
 
 def average_to_coarse(fl: FineLevel, field: np.ndarray) -> np.ndarray:
     """Full weighting (tensor product of [1/4, 1/2, 1/4]) of a field given on
-    the ghosted fine box, at the fine nodes coincident with the coarse nodes
-    under the box."""
+    the ghosted fine array, at the fine nodes coincident with the coarse
+    nodes the level covers (order of covered_index)."""
     res = np.asarray(field, dtype=np.float64)
     for a in range(fl.dim):
         ax = 3 - a
@@ -127,8 +165,15 @@ def average_to_coarse(fl: FineLevel, field: np.ndarray) -> np.ndarray:
         pad = [(0, 0)] * res.ndim
         pad[ax] = (1, 1)
         res = np.pad(full, pad)
-    _, fs = covered_slices(fl, (0, 0, 0))
+    _, fs = covered_index(fl, (0, 0, 0))
     return res[fs]
+
+
+def relax(fl: FineLevel, e: np.ndarray, f: np.ndarray, omega: float) -> np.ndarray:
+    """One damped Jacobi sweep on a refined level: the fine operator's sweep
+    at valid nodes, the Dirichlet row (value f) at every other node."""
+    out = jacobi(fl.grid, fl.C, e, f, omega)
+    return np.where(fl.valid_full(), out, f)
 
 
 class Composite:
@@ -139,11 +184,21 @@ class Composite:
         self.g0 = Grid.of(base_prob)
         self.fines = list(fines)
         self.dim = base_prob.dim
-        prev_lo, prev_hi = (0, 0, 0), tuple(m - 1 for m in self.g0.m)
-        for k, fl in enumerate(self.fines):
-            for a in range(self.dim):
-                assert fl.lo[a] // 2 - 2 >= prev_lo[a] and fl.hi[a] // 2 + 2 <= prev_hi[a], "improper nesting"
-            prev_lo, prev_hi = fl.lo, fl.hi
+        for k, fl in enumerate(self.fines, start=1):
+            for bl, bh in fl.boxes:
+                # the box grown by two coarse cells lies inside the valid nodes of level k-1
+                rng = [range(bl[a] // 2 - 2, bh[a] // 2 + 3) if a < self.dim else range(1) for a in range(3)]
+                if k == 1:
+                    for a in range(self.dim):
+                        assert rng[a][0] >= 0 and rng[a][-1] <= self.g0.m[a] - 1, "improper nesting"
+                else:
+                    par = self.fines[k - 2]
+                    o = self.origin(k - 1)
+                    sl = tuple(slice(rng[a][0] - o[a], rng[a][-1] - o[a] + 1) if a < self.dim else slice(None)
+                               for a in (2, 1, 0))
+                    for a in range(self.dim):
+                        assert rng[a][0] - o[a] >= 0 and rng[a][-1] - o[a] < par.grid.m[a], "improper nesting"
+                    assert par.valid_mask[sl].all(), "improper nesting"
         # coarse levels take the average of the finer level where it exists
         # (Sec. 1: coarse levels are updated from fine levels by averaging):
         # moduli and eigenstrain at covered nodes <- full weighting of the
@@ -152,7 +207,7 @@ class Composite:
         self.E0 = None if base_prob.eps0 is None else np.array(base_prob.eps0, dtype=np.float64)
         for k in range(len(self.fines), 0, -1):
             fl = self.fines[k - 1]
-            cs, _ = covered_slices(fl, self.origin(k - 1))
+            cs, _ = covered_index(fl, self.origin(k - 1))
             tgtC = self.C0 if k == 1 else self.fines[k - 2].C
             tgtC[cs] = average_to_coarse(fl, fl.C)
             if fl.eps0 is not None:
@@ -183,14 +238,12 @@ class Composite:
         then fine ghosts <- interpolation of the next coarser level."""
         u = [x.copy() for x in u]
         for k in range(len(self.fines), 0, -1):
-            cs, fs = covered_slices(self.fines[k - 1], self.origin(k - 1))
+            cs, fs = covered_index(self.fines[k - 1], self.origin(k - 1))
             u[k - 1][cs] = u[k][fs]
         for k in range(1, len(self.fines) + 1):
             fl = self.fines[k - 1]
             gi = interp_to_box(u[k - 1], self.origin(k - 1), fl)
-            ghost = np.ones(fl.shape, dtype=bool)
-            ghost[(slice(None),) + fl.valid()] = False
-            u[k] = np.where(ghost, gi, u[k])
+            u[k] = np.where(fl.valid_full(), u[k], gi)
         return u
 
     def unknown_masks(self) -> List[np.ndarray]:
@@ -201,10 +254,9 @@ class Composite:
             if k == 0:
                 mk = ~dirichlet_mask(g).copy()
             else:
-                mk = np.zeros(g.shape(self.dim), dtype=bool)
-                mk[(slice(None),) + self.fines[k - 1].valid()] = True
+                mk = self.fines[k - 1].valid_full().copy()
             if k < len(self.fines):
-                cs, _ = covered_slices(self.fines[k], self.origin(k))
+                cs, _ = covered_index(self.fines[k], self.origin(k))
                 mk = np.array(mk)
                 mk[cs] = False
             masks.append(np.array(mk))
@@ -284,13 +336,13 @@ class Composite:
             g, C = fl.grid, fl.C
             ek = np.zeros(fl.shape)
             for _ in range(nu1):
-                ek = jacobi(g, C, ek, rr[k], omega)       # ghost rows: rhs 0 -> stay 0
+                ek = relax(fl, ek, rr[k], omega)          # non-valid rows: rhs 0 -> stay 0
             e[k] = ek
             rk = residual(g, C, ek, rr[k])
-            rk[~np.broadcast_to(masks[k] | self._covered_valid(k), rk.shape)] = 0.0
+            rk[~fl.valid_full()] = 0.0
             # coarse residual at uncovered nodes: minus the coarse operator of the injected fine correction
             gc, Cc = self.grid(k - 1), self.C(k - 1)
-            cs, fs = covered_slices(fl, self.origin(k - 1))
+            cs, fs = covered_index(fl, self.origin(k - 1))
             inj = np.zeros(gc.shape(self.dim))
             inj[cs] = ek[fs]
             Ainj = apply(gc, Cc, inj)
@@ -305,30 +357,21 @@ class Composite:
             g, C = fl.grid, fl.C
             ec = e[k - 1].copy()
             pe = interp_to_box(ec, self.origin(k - 1), fl)
-            ghost = np.ones(fl.shape, dtype=bool)
-            ghost[(slice(None),) + fl.valid()] = False
-            ek = e[k] + np.where(ghost, 0.0, pe)
-            ek = np.where(ghost, pe, ek)
-            fk = np.where(ghost, pe, rr[k])
+            valid = fl.valid_full()
+            ek = np.where(valid, e[k] + pe, pe)
+            fk = np.where(valid, rr[k], pe)
             for _ in range(nu2):
-                ek = jacobi(g, C, ek, fk, omega)
+                ek = relax(fl, ek, fk, omega)
             e[k] = ek
         return self.sync([u[k] + e[k] for k in range(L + 1)])
 
-    def _covered_valid(self, k):
-        """Valid nodes of fine level k (used to keep their residual for restriction)."""
-        fl = self.fines[k - 1]
-        m = np.zeros(fl.shape, dtype=bool)
-        m[(slice(None),) + fl.valid()] = True
-        return m
-
     def _restrict_valid(self, fl: FineLevel, rk: np.ndarray) -> np.ndarray:
         """Full weighting of a fine residual onto the coarse nodes coincident
-        with the box's valid nodes, over valid fine nodes only, the weights
-        renormalised to sum to one where the stencil would reach a ghost."""
+        with the level's valid nodes, over valid fine nodes only, the weights
+        renormalised to sum to one where the stencil would reach a non-valid
+        node."""
         d = fl.dim
-        valid = np.zeros(fl.shape[1:], dtype=float)
-        valid[fl.valid()] = 1.0
+        valid = fl.valid_mask.astype(float)
         num = rk.copy()
         den = valid.copy()
         for a in range(d):
@@ -340,7 +383,7 @@ class Composite:
                 return y
             num = fw(num, ax + 1)
             den = fw(den, ax)
-        _, fs = covered_slices(fl, (0, 0, 0))
+        _, fs = covered_index(fl, (0, 0, 0))
         return num[fs] / den[fs[1:]]
 
     def solve(self, tol=1e-12, max_cycles=300, nu1=2, nu2=2, omega=2.0 / 3.0, base="V"):
@@ -365,5 +408,5 @@ def from_problem(ap) -> Composite:
     fines = []
     for k, (lo, hi) in enumerate(ap.boxes, start=1):
         fines.append(FineLevel(ap.level_h(k - 1), ap.base.dim, kind, lo, hi, ap.C[k - 1], ap.eps0[k - 1],
-                               ap.b[k - 1]))
+                               ap.b[k - 1], boxes=ap.level_boxes(k)))
     return Composite(ap.base, fines)

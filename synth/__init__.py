@@ -382,15 +382,34 @@ def upper_tri(V: np.ndarray) -> np.ndarray:
 
 @dataclasses.dataclass
 class AmrProblem:
-    """Base grid plus one box per refined level (ratio 2).  Box k (k >= 1)
-    holds nodes [lo, hi] (inclusive, even) of level k's index space; its
-    fields are sampled on the box grown by one ghost node per side."""
+    """Base grid plus refined levels (ratio 2).  Level k >= 1 is a list of
+    boxes of nodes [lo, hi] (inclusive, even) of level k's index space
+    (``boxlists[k-1]``; one box if ``boxlists`` is None); ``boxes[k-1]`` is
+    the bounding box of that list, and the level's fields are sampled on the
+    bounding box grown by one node per side."""
     base: Problem
     boxes: list
     C: list
     eps0: list
     b: list
     name: str = ""
+    boxlists: Optional[list] = None
+
+    def level_boxes(self, k):
+        """The boxes of refined level k (k >= 1)."""
+        if self.boxlists is None:
+            return [self.boxes[k - 1]]
+        return list(self.boxlists[k - 1])
+
+    def valid_mask(self, k):
+        """Valid nodes of level k over its ghosted bounding box, [z][y][x]."""
+        lo, hi = self.boxes[k - 1]
+        d = self.base.dim
+        shp = [hi[a] - lo[a] + 3 if a < d else 1 for a in range(3)]
+        m = np.zeros((shp[2], shp[1], shp[0]), dtype=bool)
+        for bl, bh in self.level_boxes(k):
+            m[tuple(slice(bl[a] - lo[a] + 1, bh[a] - lo[a] + 2) if a < d else slice(None) for a in (2, 1, 0))] = True
+        return m
 
     def level_h(self, k):
         return tuple(self.base.h[a] / 2 ** k if a < self.base.dim else 1.0 for a in range(3))
@@ -407,14 +426,20 @@ class AmrProblem:
         return out[0][None, None, :], out[1][None, :, None], out[2][:, None, None]
 
     def composite_nodes(self):
+        """Valid nodes of every level minus the coarse nodes they cover."""
         n = self.base.nodes
-        for k, (lo, hi) in enumerate(self.boxes, start=1):
-            cnt = 1
-            cov = 1
-            for a in range(self.base.dim):
-                cnt *= hi[a] - lo[a] + 1
-                cov *= hi[a] // 2 - lo[a] // 2 + 1
-            n += cnt - cov
+        d = self.base.dim
+        for k in range(1, len(self.boxes) + 1):
+            m = self.valid_mask(k)
+            lo = self.boxes[k - 1][0]
+            even = m.copy()
+            for a in range(d):
+                ax = 2 - a
+                idx = np.arange(m.shape[ax])
+                shp = [1, 1, 1]
+                shp[ax] = -1
+                even &= ((lo[a] - 1 + idx) % 2 == 0).reshape(shp)
+            n += int(m.sum()) - int(even.sum())
         return n
 
 

@@ -47,9 +47,9 @@ def _rel(u, ref, comp):
     num = float(np.sum((u[0] - ref[0]) ** 2))
     den = float(np.sum(ref[0] ** 2))
     for k in range(1, len(u)):
-        v = (slice(None),) + comp.fines[k - 1].valid()
-        num += float(np.sum((u[k][v] - ref[k][v]) ** 2))
-        den += float(np.sum(ref[k][v] ** 2))
+        v = comp.fines[k - 1].valid_full()
+        num += float(np.sum(((u[k] - ref[k]) ** 2)[v]))
+        den += float(np.sum((ref[k] ** 2)[v]))
     return np.sqrt(num / den)
 
 

@@ -370,7 +370,7 @@ def test_averaging_pins_catch_planted_mistakes(monkeypatch):
     good = amr.average_to_coarse
 
     def injection(fl, field):
-        _, fs = amr.covered_slices(fl, (0, 0, 0))
+        _, fs = amr.covered_index(fl, (0, 0, 0))
         return np.asarray(field)[fs]
 
     def thirds(fl, field):
@@ -383,7 +383,7 @@ def test_averaging_pins_catch_planted_mistakes(monkeypatch):
             pad = [(0, 0)] * res.ndim
             pad[ax] = (1, 1)
             res = np.pad(full, pad)
-        _, fs = amr.covered_slices(fl, (0, 0, 0))
+        _, fs = amr.covered_index(fl, (0, 0, 0))
         return res[fs]
 
     for bad in (injection, thirds):
@@ -391,3 +391,206 @@ def test_averaging_pins_catch_planted_mistakes(monkeypatch):
         assert not check(), bad.__name__
     monkeypatch.setattr(amr, "average_to_coarse", good)
     assert check()
+
+
+# ---- several boxes per refined level ----
+
+def _fine_boxes(p, boxes, fields, kind=None):
+    """Refined level made of `boxes` (fine index space), moduli from
+    `fields(x, y, z)` sampled on the ghosted bounding box."""
+    d = p.dim
+    lo = tuple(min(b[0][a] for b in boxes) if a < d else 0 for a in range(3))
+    hi = tuple(max(b[1][a] for b in boxes) if a < d else 0 for a in range(3))
+    h = [p.h[a] / 2 for a in range(3)]
+    ax = [p.lo[a] + h[a] * np.arange(lo[a] - 1, hi[a] + 2) if a < d else np.zeros(1) for a in range(3)]
+    x, y, z = ax[0][None, None, :], ax[1][None, :, None], ax[2][:, None, None]
+    C = fields(x, y, z)
+    shape = (len(ax[2]), len(ax[1]), len(ax[0]))
+    C = np.ascontiguousarray(np.broadcast_to(C, (C.shape[0],) + shape))
+    if kind is None:
+        kind = oracle.ISO if C.shape[0] == 2 else oracle.ANISO
+    return amr.FineLevel(p.h, d, kind, lo, hi, C, boxes=boxes)
+
+
+L_BOXES = [((8, 8, 0), (24, 16, 0)), ((8, 16, 0), (16, 24, 0))]      # an L: a reentrant corner at (16, 16)
+
+
+def test_two_boxes_with_the_union_of_one_box_give_its_system():
+    """The union, not the box list, defines the composite rows: a level made
+    of two boxes meeting along x = 16 whose union is [8, 24]^2 has the
+    composite residual of the single box, bit for bit, for any state."""
+    p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, 1.5, 1.0, n=17)
+    x, y, _ = p.coords()
+
+    def fields(x, y, z):
+        return np.stack([1.5 + 0.5 * np.sin(3 * x) * np.cos(2 * y) + 0 * z, 1.0 + 0.3 * np.cos(x + 2 * y) + 0 * z])
+    p.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, 0), p.C.shape))
+    one = amr.Composite(p, [_fine_boxes(p, [((8, 8, 0), (24, 24, 0))], fields)])
+    two = amr.Composite(p, [_fine_boxes(p, [((8, 8, 0), (16, 24, 0)), ((16, 8, 0), (24, 24, 0))], fields)])
+    rng = np.random.default_rng(3)
+    u = [rng.standard_normal(one.grid(k).shape(2)) for k in range(2)]
+    for a, b in zip(one.residual(u), two.residual(u)):
+        assert np.array_equal(a, b)
+
+
+def _laplace_L():
+    p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, -1.0, 1.0)
+    fl = _fine_boxes(p, L_BOXES, lambda x, y, z: np.stack([-1.0 + 0 * x * y, 1.0 + 0 * x * y]))
+    return p, amr.Composite(p, [fl])
+
+
+def test_appendix_a_stencil_where_two_boxes_meet():
+    """The Laplacian reduction on an L-shaped level of two boxes.  The fine
+    node (8, 16) sits on the low-x coarse/fine face where the two boxes meet:
+    its row is App. A's one-sided face stencil along x (coefficients 1,
+    -3/2 and the coarse node 1/2) and the interior 3-point stencil along y
+    across the junction.  The reentrant corner (16, 16) has valid axis
+    neighbours on both sides: plain interior row.  The convex corner
+    (24, 8) has App. A's corner stencil."""
+    g = json.load(open(GOLDEN))
+    p, comp = _laplace_L()
+    hf = p.h[0] / 2
+    fl = comp.fines[0]
+
+    def at(I, J):   # fine level index -> array index (component 0 added by caller)
+        return (0, J - fl.lo[1] + 1, I - fl.lo[0] + 1)
+
+    def coef(row, col_level, col):
+        u = [np.zeros(comp.grid(k).shape(2)) for k in range(2)]
+        u[col_level][col] = 1.0
+        r = comp.residual(u)
+        return -r[1][row] * hf * hf
+
+    one = g["one_d_normal"]
+    row = (0,) + at(8, 16)
+    assert coef(row, 1, row) == pytest.approx(one["self"] - 2.0, abs=1e-12)
+    assert coef(row, 1, (0,) + at(9, 16)) == pytest.approx(one["fine_inside"], abs=1e-12)
+    assert coef(row, 0, (0, 0, 8, 3)) == pytest.approx(one["coarse_outside"], abs=1e-12)   # coarse (3, 8)
+    assert coef(row, 1, (0,) + at(8, 15)) == pytest.approx(1.0, abs=1e-12)   # inside box 1
+    assert coef(row, 1, (0,) + at(8, 17)) == pytest.approx(1.0, abs=1e-12)   # inside box 2
+    row = (0,) + at(16, 16)
+    assert coef(row, 1, row) == pytest.approx(-4.0, abs=1e-12)
+    for nb in ((15, 16), (17, 16), (16, 15), (16, 17)):
+        assert coef(row, 1, (0,) + at(*nb)) == pytest.approx(1.0, abs=1e-12)
+    two = g["two_d_corner"]
+    row = (0,) + at(24, 8)
+    assert coef(row, 1, row) == pytest.approx(two["self"], abs=1e-12)
+    assert coef(row, 1, (0,) + at(23, 8)) == pytest.approx(two["fine_inside_x"], abs=1e-12)
+    assert coef(row, 1, (0,) + at(24, 9)) == pytest.approx(two["fine_inside_y"], abs=1e-12)
+    assert coef(row, 0, (0, 0, 4, 13)) == pytest.approx(two["coarse_outside_x"], abs=1e-12)
+    assert coef(row, 0, (0, 0, 3, 12)) == pytest.approx(two["coarse_outside_y"], abs=1e-12)
+
+
+def test_l_shaped_level_masks_and_counts():
+    """Valid, covered and ghost nodes of the L-shaped level, counted by hand:
+    valid = 17 x 9 + 9 x 9 - 9 (the shared row y = 16, x = 8..16); covered
+    coarse nodes = 9 x 5 + 5 x 5 - 5; the fine node (17, 17) off both boxes
+    is interpolated from four coarse nodes, three of them covered."""
+    p, comp = _laplace_L()
+    fl = comp.fines[0]
+    assert int(fl.valid_mask.sum()) == 17 * 9 + 9 * 9 - 9
+    cs, fs = amr.covered_index(fl, (0, 0, 0))
+    assert len(cs[1]) == 9 * 5 + 5 * 5 - 5
+    masks = comp.unknown_masks()
+    assert int(masks[1][0].sum()) == 17 * 9 + 9 * 9 - 9
+    assert int((~masks[0][0]).sum()) == 17 * 17 - 15 * 15 + (9 * 5 + 5 * 5 - 5)
+    rng = np.random.default_rng(5)
+    u = comp.sync([rng.standard_normal(comp.grid(k).shape(2)) for k in range(2)])
+    ghost = u[1][:, 0, 17 - fl.lo[1] + 1, 17 - fl.lo[0] + 1]
+    exp = 0.25 * (u[0][:, 0, 8, 8] + u[0][:, 0, 8, 9] + u[0][:, 0, 9, 8] + u[0][:, 0, 9, 9])
+    np.testing.assert_allclose(ghost, exp, rtol=1e-15, atol=1e-18)
+    assert np.array_equal(u[0][:, 0, 8, 9], u[1][:, 0, 16 - fl.lo[1] + 1, 18 - fl.lo[0] + 1])   # injected
+
+
+def _affine_multibox(dim):
+    rng = np.random.default_rng(4)
+    A = rng.uniform(-1, 1, size=(3, 3)) * 1e-3
+    c = rng.uniform(-1, 1, size=3) * 1e-3
+    if dim == 2:
+        p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, 1.5, 1.0, n=17)
+        boxes = L_BOXES
+        fields = lambda x, y, z: np.stack([1.5 + 0 * x * y, 1.0 + 0 * x * y])
+    else:
+        p = synth.random_problem(3, (9, 9, 9), ("dirichlet",) * 6, "aniso", seed=3, with_eps0=False,
+                                 with_face_data=False)
+        p.C = np.broadcast_to(p.C[:, :1, :1, :1], p.C.shape).copy()
+        c0 = p.C[:, 0, 0, 0].copy()
+        boxes = [((4, 4, 4), (12, 8, 12)), ((4, 8, 4), (8, 12, 8))]
+        fields = lambda x, y, z: c0.reshape(-1, 1, 1, 1) + 0 * x * y * z
+    x, y, z = p.coords()
+    shp = (p.m[2], p.m[1], p.m[0])
+    pos = [np.broadcast_to(v, shp) for v in (x, y, z)]
+    uex = np.stack([sum(A[k, l] * pos[l] for l in range(dim)) + c[k] for k in range(dim)])
+    for f in range(2 * dim):
+        a = f // 2
+        sl = [slice(None)] * 3
+        sl[2 - a] = slice(0, 1) if f % 2 == 0 else slice(p.m[a] - 1, p.m[a])
+        p.face[f] = uex[(slice(None),) + tuple(sl)].copy()
+    fl = _fine_boxes(p, boxes, fields)
+    return p, fl, A, c
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_affine_patch_test_several_boxes(dim):
+    """P10(i) with a level of several boxes (2D: an L; 3D: two boxes meeting
+    on a face, with reentrant edges and a reentrant corner): an affine
+    displacement is the composite solution on every level."""
+    p, fl, A, c = _affine_multibox(dim)
+    comp = amr.Composite(p, [fl])
+    u = comp.dense_solve()
+    x, y, z = p.coords()
+    shp = (p.m[2], p.m[1], p.m[0])
+    pos = [np.broadcast_to(v, shp) for v in (x, y, z)]
+    uex = np.stack([sum(A[k, l] * pos[l] for l in range(dim)) + c[k] for k in range(dim)])
+    assert np.abs(u[0] - uex).max() <= 1e-12
+    hf = [p.h[a] / 2 for a in range(3)]
+    ax = [p.lo[a] + hf[a] * np.arange(fl.lo[a] - 1, fl.hi[a] + 2) if a < dim else np.zeros(1) for a in range(3)]
+    fpos = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    ufex = np.stack([sum(A[k, l] * fpos[2 - l] for l in range(dim)) + c[k] for k in range(dim)])
+    assert np.abs(u[1] - ufex)[fl.valid_full()].max() <= 1e-12
+
+
+def _smooth_multibox_2d(levels=2):
+    def fields(x, y, z):
+        lam = 1.5 + 0.8 * np.sin(3 * x + 0.3) * np.cos(2 * y)
+        mu = 1.0 + 0.5 * np.cos(2 * x + y)
+        return np.stack([lam + 0 * x * y, mu + 0 * x * y])
+    p = synth.random_problem(2, (17, 17), ("dirichlet", "traction", "dirichlet", "traction", "periodic", "periodic"),
+                             "iso", seed=2, with_eps0=False, with_body=True)
+    x, y, _ = p.coords()
+    p.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, 0), p.C.shape))
+    fines = [_fine_boxes(p, [((6, 6, 0), (26, 14, 0)), ((6, 14, 0), (14, 26, 0))], fields)]
+    if levels == 2:
+        q = synth.Problem(**{**p.__dict__})
+        q.n = (33, 33, 1)
+        # two disjoint boxes of level 2 inside the L (each grown by two level-1 cells stays valid)
+        fines.append(_fine_boxes(q, [((18, 18, 0), (30, 24, 0)), ((18, 34, 0), (24, 46, 0))], fields))
+    return amr.Composite(p, fines)
+
+
+@pytest.mark.parametrize("levels,base", [(1, "V"), (2, "V"), (2, "F")])
+def test_composite_cycle_reaches_dense_solution_several_boxes(levels, base):
+    """Variable moduli, traction faces, body force; an L-shaped level 1 and
+    two disjoint boxes on level 2: the composite cycle's fixed point is the
+    dense solution of the composite system."""
+    comp = _smooth_multibox_2d(levels)
+    ud = comp.dense_solve()
+    assert comp.norm(comp.residual(ud)) <= 1e-10 * comp.norm(comp.residual(comp.initial()))
+    u, hist = comp.solve(tol=1e-13, max_cycles=200, base=base)
+    assert hist[-1] <= 1e-12
+    for k, (a, b) in enumerate(zip(u, ud)):
+        m = comp.unknown_masks()[k] if k else np.ones(a.shape, dtype=bool)
+        assert np.abs(a - b)[m].max() <= 1e-10 * np.abs(ud[0]).max()
+
+
+def test_improper_nesting_is_rejected():
+    """A level-2 box that reaches into the notch of the L (less than two
+    level-1 cells of valid nodes around it) is refused."""
+    p = _base2d(("dirichlet",) * 4 + ("periodic",) * 2, 1.5, 1.0, n=17)
+    fields = lambda x, y, z: np.stack([1.5 + 0 * x * y, 1.0 + 0 * x * y])
+    l1 = _fine_boxes(p, L_BOXES, fields)
+    q = synth.Problem(**{**p.__dict__})
+    q.n = (33, 33, 1)
+    with pytest.raises(AssertionError):
+        amr.Composite(p, [l1, _fine_boxes(q, [((24, 24, 0), (36, 36, 0))], fields)])
+    amr.Composite(p, [l1, _fine_boxes(q, [((20, 20, 0), (28, 28, 0))], fields)])
