@@ -41,7 +41,9 @@ typedef enum {
   EMG_EDEVICE = -3,    /* a HIP call failed */
   EMG_ENOTCONV = -4,   /* cycle cap reached; the last iterate and stats are still returned */
   EMG_EDIVERGED = -5,  /* residual norm became NaN or Inf */
-  EMG_ESTATE = -6      /* call order, e.g. solve before the moduli are set */
+  EMG_ESTATE = -6,     /* call order, e.g. solve before the moduli are set */
+  EMG_EBUSY = -7       /* the problem, or the device's allocation-free scratch, is in use by a
+                          call on another thread; nothing was done */
 } emg_status;
 
 /* Face boundary types (Sec. 2.1, eqs. elastic_b1, elastic_b2 and
@@ -226,6 +228,29 @@ emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, 
  * (n entries, may be NULL) get per-problem cycles/residuals; solve_seconds is
  * the batch's wall time.  Refined (AMR) problems and warm starts are rejected. */
 emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *opts, emg_solve_stats *stats);
+
+/* Allocation-free variant of emg_solve_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same problems, options, arithmetic and
+ * results (bit for bit) as emg_solve_batch; what differs:
+ *   - the batch's device work lists live in a fixed array of
+ *     EMG_NOALLOC_SCRATCH_BYTES per GPU, held by the library from the first
+ *     emg_ctx_create on that GPU until the process ends; no call allocates
+ *     or frees device memory, and no HIP graph is instantiated (the cycle
+ *     steps are launched directly, opts->use_graph is ignored);
+ *   - every problem must already hold its hierarchy: solved (emg_solve or
+ *     emg_solve_batch) since its moduli were last set, and for EMG_MIXED
+ *     solved once in mixed precision, else EMG_ESTATE.  New face data,
+ *     eigenstrain or body force need no allocation;
+ *   - a batch whose work lists need more than EMG_NOALLOC_SCRATCH_BYTES
+ *     (about 100 lists of the problems of one kind; several hundred small
+ *     problems) is rejected with EMG_EINVAL before anything runs;
+ *   - calls on one GPU share its array: the call is blocking and holds the
+ *     array until it returns, and a call that finds it held by another
+ *     thread returns EMG_EBUSY at once (the array keeps the last call's
+ *     lists; each call rewrites what it reads). */
+#define EMG_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+emg_status emg_solve_batch_noalloc(emg_problem **probs, int n, const emg_solve_opts *opts, emg_solve_stats *stats);
 
 /* ---- serving: continuous batching of independent solves ----
  * A server owns a preparation thread and a scheduler thread, each with its own

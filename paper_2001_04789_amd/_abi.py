@@ -21,7 +21,8 @@ lib = ctypes.CDLL(LIB_PATH)
 
 c_int, c_int64, c_double, c_size_t, c_void_p = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 
-EMG_OK, EMG_EINVAL, EMG_ENOMEM, EMG_EDEVICE, EMG_ENOTCONV, EMG_EDIVERGED, EMG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+EMG_OK, EMG_EINVAL, EMG_ENOMEM, EMG_EDEVICE, EMG_ENOTCONV, EMG_EDIVERGED, EMG_ESTATE, EMG_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+EMG_NOALLOC_SCRATCH_BYTES = 8 << 20
 EMG_BC_DIRICHLET, EMG_BC_TRACTION, EMG_BC_PERIODIC, EMG_BC_NEUMANN = 0, 1, 2, 3
 EMG_MOD_ISO, EMG_MOD_ANISO = 0, 1
 EMG_FP64, EMG_MIXED = 0, 1
@@ -96,6 +97,7 @@ _SIGS = {
     "emg_autotune": ([c_void_p, c_int, c_int, c_int, P(c_int)], c_int),
     "emg_autotune_reset": ([], c_int),
     "emg_solve_batch": ([P(c_void_p), c_int, P(emg_solve_opts), P(emg_solve_stats)], c_int),
+    "emg_solve_batch_noalloc": ([P(c_void_p), c_int, P(emg_solve_opts), P(emg_solve_stats)], c_int),
     "emg_server_create": ([c_void_p, c_int, P(emg_solve_opts), P(c_void_p)], c_int),
     "emg_server_submit": ([c_void_p, P(emg_request), P(ctypes.c_uint64)], c_int),
     "emg_server_poll": ([c_void_p, ctypes.c_uint64, P(emg_ticket_info)], c_int),
@@ -187,17 +189,28 @@ def default_opts(**kw) -> emg_solve_opts:
     return o
 
 
-def solve_batch(problems, raise_on_error: bool = True, **opts):
-    """Solve several problems together (emg_solve_batch); per-problem stats."""
+def _batch(fn, name, problems, raise_on_error, opts):
     n = len(problems)
     arr = (c_void_p * n)(*[p.handle for p in problems])
     o = default_opts(**opts)
     st = (emg_solve_stats * n)()
-    s = lib.emg_solve_batch(arr, n, ctypes.byref(o), st)
+    s = fn(arr, n, ctypes.byref(o), st)
     out = [dict({k: getattr(x, k) for k, _ in emg_solve_stats._fields_}, status=s) for x in st]
     if raise_on_error and s != EMG_OK:
-        check(s, "emg_solve_batch")
+        check(s, name)
     return out
+
+
+def solve_batch(problems, raise_on_error: bool = True, **opts):
+    """Solve several problems together (emg_solve_batch); per-problem stats."""
+    return _batch(lib.emg_solve_batch, "emg_solve_batch", problems, raise_on_error, opts)
+
+
+def solve_batch_noalloc(problems, raise_on_error: bool = True, **opts):
+    """emg_solve_batch_noalloc: the batch without device allocation (work
+    lists in the library's fixed per-GPU scratch, direct launches); every
+    problem must have been solved since its moduli were last set."""
+    return _batch(lib.emg_solve_batch_noalloc, "emg_solve_batch_noalloc", problems, raise_on_error, opts)
 
 
 def _domain(dim: int, n, lo, hi, bc, kind) -> emg_domain:
@@ -531,10 +544,10 @@ def autotune_reset():
     check(lib.emg_autotune_reset(), "emg_autotune_reset")
 
 
-__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch",
+__all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch", "solve_batch_noalloc",
            "autotune_reset",
            "emg_domain", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
-           "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE",
+           "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE", "EMG_EBUSY", "EMG_NOALLOC_SCRATCH_BYTES",
            "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_BC_NEUMANN", "EMG_VCYCLE", "EMG_FCYCLE",
            "EMG_MOD_ISO", "EMG_MOD_ANISO",
            "EMG_FP64", "EMG_MIXED"] + list(SYMBOLS)

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -29,6 +30,12 @@
 #include "emg_kernels.hpp"
 
 using namespace emg;
+
+// Device scratch of the allocation-free batched solve: the work lists of one
+// batch.  Each GPU holds its own copy from module load to process end.  In
+// host code `scratch` only names the symbol; its device address on the
+// current GPU comes from hipGetSymbolAddress (see noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[EMG_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1395,6 +1402,36 @@ emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st, int
   return EMG_OK;
 }
 
+// Writes the plan's lists into fixed device memory of `bytes` bytes (no
+// allocation); EMG_EINVAL if they do not fit.
+emg_status upload_plan_fixed(const BatchPlan &plan, void *base, size_t bytes, BatchDev &dev, hipStream_t st) {
+  int cap = 1;
+  for (auto &l : plan.lists) cap = std::max(cap, (int)l.size());
+  const int nl = std::max(1, (int)plan.lists.size());
+  const size_t need = (size_t)nl * blist_bytes(cap);
+  if (need > bytes)
+    return fail(EMG_EINVAL, "the batch's work lists need " + std::to_string(need) + " bytes, more than the " +
+                                std::to_string(bytes) + " of the allocation-free scratch");
+  dev.buf = (char *)base;
+  dev.nlists = nl;
+  dev.cap = cap;
+  dev.bytes = need;
+  dev.host.assign(need, 0);
+  const size_t stride = blist_bytes(cap);
+  for (int i = 0; i < (int)plan.lists.size(); i++) {
+    BList *h = (BList *)(dev.host.data() + (size_t)i * stride);
+    const auto &es = plan.lists[i];
+    h->n = (int)es.size();
+    h->total = 0;
+    for (size_t j = 0; j < es.size(); j++) {
+      h->e[j] = es[j];
+      h->total += (long long)es[j].gx * es[j].gy * es[j].gz;
+    }
+  }
+  HIPCK(hipMemcpyAsync(dev.buf, dev.host.data(), need, hipMemcpyHostToDevice, st));
+  return EMG_OK;
+}
+
 // check_grid: workgroups of the batched convergence checks (grid-strided
 // over the problems), fixed so a captured graph serves any batch size
 void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, double omega, int check_grid) {
@@ -1413,6 +1450,29 @@ void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, dou
     else if (s.K == MOD_ISO) launch_batch_kind<3, MOD_ISO>(st, s.kind, s.f32, L, omega);
     else launch_batch_kind<3, MOD_ANISO>(st, s.kind, s.f32, L, omega);
   }
+}
+
+// ---- allocation-free batches: the per-GPU scratch array ----
+constexpr int kMaxDevices = 64;
+struct NoAllocSlot {
+  void *ptr = nullptr;              // device address of `scratch` on this GPU
+  std::atomic<bool> busy{false};    // held by a running emg_solve_batch_noalloc
+};
+NoAllocSlot g_noalloc[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Called with `dev` current (context creation): looks up this GPU's copy of
+// the scratch array once.
+emg_status noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(EMG_EINVAL, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc[dev].ptr) return EMG_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(EMG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_noalloc[dev].ptr = ptr;
+  return EMG_OK;
 }
 
 // Per-problem preparation before joining a batch: hierarchy, right-hand
@@ -1813,6 +1873,7 @@ emg_status emg_ctx_create(int hip_device, size_t hbm_budget_bytes, emg_ctx **out
     std::lock_guard<std::mutex> lk(t.mu);
     (void)tune_arch_locked(t, hip_device);
   }
+  TRY(noalloc_scratch_init(hip_device));
   emg_ctx *c = new emg_ctx;
   c->device = hip_device;
   c->budget = hbm_budget_bytes;
@@ -2409,9 +2470,9 @@ emg_status emg_autotune_reset(void) {
 
 // ---- ragged batches ----
 
-emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, emg_solve_stats *stats) {
+static emg_status batch_args(emg_problem **probs, int n, const emg_solve_opts *o, emg_solve_opts &opt,
+                             std::vector<emg_problem *> &ps) {
   if (!probs || n < 1) return fail(EMG_EINVAL, "empty batch");
-  emg_solve_opts opt;
   emg_default_opts(&opt);
   if (o) opt = *o;
   if (opt.precision != EMG_FP64 && opt.precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
@@ -2420,12 +2481,38 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
     return fail(EMG_EINVAL, "inner_cycles must lie in 1..4 (above 1 in mixed precision only)");
   if (!(opt.omega > 0.0 && opt.omega < 2.0) || opt.warm_start) return fail(EMG_EINVAL, "bad omega or warm start");
   if (opt.cycle != EMG_VCYCLE) return fail(EMG_EINVAL, "batched solves run V-cycles only");
-  std::vector<emg_problem *> ps(probs, probs + n);
+  ps.assign(probs, probs + n);
   for (auto *p : ps)
     if (!p || p->ctx != ps[0]->ctx) return fail(EMG_EINVAL, "null problem or problems of different contexts");
   for (size_t i = 0; i < ps.size(); i++)
     for (size_t j = 0; j < i; j++)
       if (ps[i] == ps[j]) return fail(EMG_EINVAL, "a problem appears twice in the batch");
+  return EMG_OK;
+}
+
+// Per-problem statistics of a finished batch and the batch's status.
+static emg_status batch_stats(const std::vector<emg_problem *> &ps, const emg_solve_opts &opt, double solve_s,
+                              double setup_s, emg_solve_stats *stats) {
+  emg_status worst = EMG_OK;
+  for (size_t i = 0; i < ps.size(); i++) {
+    const Ctl c = *ps[i]->ctl_host;
+    emg_solve_stats one;
+    fill_stats(ps[i], c, opt.inner_cycles, &one);
+    one.solve_seconds = solve_s;
+    one.setup_seconds = setup_s;
+    if (stats) stats[i] = one;
+    if (c.done == 2) worst = EMG_EDIVERGED;
+    else if (c.done == 3 && worst == EMG_OK) worst = EMG_ENOTCONV;
+  }
+  if (worst == EMG_EDIVERGED) return fail(worst, "a problem of the batch diverged");
+  if (worst == EMG_ENOTCONV) return fail(worst, "a problem of the batch hit the cycle cap");
+  return EMG_OK;
+}
+
+emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, emg_solve_stats *stats) {
+  emg_solve_opts opt;
+  std::vector<emg_problem *> ps;
+  TRY(batch_args(probs, n, o, opt, ps));
   hipStream_t st = ps[0]->stream;
   const auto t0 = std::chrono::steady_clock::now();
   for (auto *p : ps) {
@@ -2470,20 +2557,69 @@ emg_status emg_solve_batch(emg_problem **probs, int n, const emg_solve_opts *o, 
   if (exec) (void)hipGraphExecDestroy(exec);
   if (dev.buf) (void)hipFree(dev.buf);
   if (s != EMG_OK) return s;
-  emg_status worst = EMG_OK;
-  for (int i = 0; i < n; i++) {
-    const Ctl c = *ps[i]->ctl_host;
-    emg_solve_stats one;
-    fill_stats(ps[i], c, opt.inner_cycles, &one);
-    one.solve_seconds = std::chrono::duration<double>(t3 - t2).count();
-    one.setup_seconds = std::chrono::duration<double>(t1 - t0).count();
-    if (stats) stats[i] = one;
-    if (c.done == 2) worst = EMG_EDIVERGED;
-    else if (c.done == 3 && worst == EMG_OK) worst = EMG_ENOTCONV;
+  return batch_stats(ps, opt, std::chrono::duration<double>(t3 - t2).count(),
+                     std::chrono::duration<double>(t1 - t0).count(), stats);
+}
+
+// The work lists of one cycle are written once to the GPU's scratch array
+// and the cycle's steps are launched check_every times between host reads
+// of the control blocks: the same launches, in the same order and on the
+// same lists' contents, as a graph of check_every cycles (every cycle of
+// such a graph walks equal lists), so results match emg_solve_batch bit for
+// bit.
+emg_status emg_solve_batch_noalloc(emg_problem **probs, int n, const emg_solve_opts *o, emg_solve_stats *stats) {
+  emg_solve_opts opt;
+  std::vector<emg_problem *> ps;
+  TRY(batch_args(probs, n, o, opt, ps));
+  for (auto *p : ps) {
+    if (!p->fine.empty()) return fail(EMG_EINVAL, "problems with refined levels are not batched");
+    if (!p->setup_done)
+      return fail(EMG_ESTATE, "a problem has no hierarchy yet: solve it once after setting its moduli");
+    if (opt.precision == EMG_MIXED && !p->lv[0].C32)
+      return fail(EMG_ESTATE, "a problem has no FP32 copies yet: solve it once in mixed precision");
   }
-  if (worst == EMG_EDIVERGED) return fail(worst, "a problem of the batch diverged");
-  if (worst == EMG_ENOTCONV) return fail(worst, "a problem of the batch hit the cycle cap");
-  return EMG_OK;
+  const int dev_id = ps[0]->ctx->device;
+  NoAllocSlot &slot = g_noalloc[dev_id];
+  if (!slot.ptr) return fail(EMG_ESTATE, "the device's scratch array was not looked up");
+  bool expected = false;
+  if (!slot.busy.compare_exchange_strong(expected, true))
+    return fail(EMG_EBUSY, "the device's allocation-free scratch is in use by another call");
+  struct Release {
+    NoAllocSlot &s;
+    ~Release() { s.busy.store(false); }
+  } release{slot};
+  HIPCK(hipSetDevice(dev_id));
+  hipStream_t st = ps[0]->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (auto *p : ps) {
+    HIPCK(hipStreamSynchronize(p->stream));
+    TRY(prepare(p, opt, st));
+  }
+  Planner pl(ps);
+  pl.cycles(opt.precision, 1, opt.nu1, opt.nu2, opt.inner_cycles);
+  BatchDev dev;
+  emg_status s = upload_plan_fixed(pl.plan, slot.ptr, EMG_NOALLOC_SCRATCH_BYTES, dev, st);
+  HIPCK(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  const int k = std::max(1, opt.check_every);
+  while (s == EMG_OK) {
+    for (int c = 0; c < k; c++) launch_plan(pl.plan, dev, st, opt.omega, n);
+    if (hipGetLastError() != hipSuccess) { s = fail(EMG_EDEVICE, "batched launch failed"); break; }
+    for (auto *p : ps)
+      if (hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st) != hipSuccess)
+        s = fail(EMG_EDEVICE, "control read");
+    if (hipStreamSynchronize(st) != hipSuccess) s = fail(EMG_EDEVICE, "batch cycle failed");
+    bool all = true;
+    for (auto *p : ps) all = all && p->ctl_host->done;
+    if (all) break;
+  }
+  const auto t2 = std::chrono::steady_clock::now();
+  if (s != EMG_OK) {
+    (void)hipStreamSynchronize(st);
+    return s;
+  }
+  return batch_stats(ps, opt, std::chrono::duration<double>(t2 - t1).count(),
+                     std::chrono::duration<double>(t1 - t0).count(), stats);
 }
 
 // ---- serving ----

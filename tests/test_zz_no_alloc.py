@@ -1,0 +1,79 @@
+"""emg_solve_batch_noalloc, the allocation-free variant of emg_solve_batch
+(work lists in the library's fixed per-GPU scratch array, direct launches),
+called through the C ABI: two calls in a row, the second on a smaller
+batch, each giving every problem the displacement, cycle count and residual
+of emg_solve_batch bit for bit (both run the same kernels on the same
+lists).  Also: problems without a hierarchy are refused with EMG_ESTATE."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def emg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_04789_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(emg):
+    c = emg.Context(0)
+    yield c
+    c.close()
+
+
+def _batch_then_noalloc(emg, ctx, specs, precision, **kw):
+    probs = [emg.Problem.from_spec(ctx, sp) for sp in specs]
+    ref = emg.solve_batch(probs, rtol=1e-10, max_cycles=400, precision=precision, **kw)
+    uref = [p.displacement() for p in probs]
+    # wipe the answers, so the comparison sees what the no-alloc call wrote
+    for p, u in zip(probs, uref):
+        p.set_displacement(np.full_like(u, np.nan))
+    print(f"[gpu] noalloc batch of {len(specs)} ({precision}, {kw})", flush=True)
+    got = emg.solve_batch_noalloc(probs, rtol=1e-10, max_cycles=400, precision=precision, **kw)
+    for sp, p, a, b, u in zip(specs, probs, got, ref, uref):
+        assert a["status"] == 0 and a["converged"] and a["rel_res"] <= 1e-10, sp.name
+        assert a["cycles"] == b["cycles"] and a["rel_res"] == b["rel_res"], (sp.name, a, b)
+        assert np.array_equal(p.displacement(), u), sp.name
+    for p in probs:
+        p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_noalloc_batch_matches_batch_twice(emg, ctx, precision):
+    big = [synth.polycrystal_3d(n=33, grains=8, seed=11), synth.inclusion_3d(n=33, seed=3),
+           synth.inclusion_2d(n=65), synth.polycrystal_3d(n=17, grains=8, seed=12)]
+    _batch_then_noalloc(emg, ctx, big, precision)
+    small = [synth.inclusion_2d(n=33)]
+    _batch_then_noalloc(emg, ctx, small, precision)
+
+
+def test_noalloc_batch_inner_cycles_and_zmarch(emg, ctx):
+    """A member on the z-marching pass (97^3 polycrystal) and two FP32 cycles
+    per refinement step; then a smaller call."""
+    _batch_then_noalloc(emg, ctx, [synth.polycrystal_3d(n=97, grains=16, seed=5), synth.inclusion_2d(n=65)],
+                        "mixed", inner_cycles=2)
+    _batch_then_noalloc(emg, ctx, [synth.inclusion_3d(n=17, seed=1)], "fp64", check_every=1)
+
+
+def test_noalloc_batch_needs_a_hierarchy(emg, ctx):
+    spec = synth.inclusion_2d(n=33)
+    p = emg.Problem.from_spec(ctx, spec)
+    st = emg.solve_batch_noalloc([p], rtol=1e-10, raise_on_error=False)
+    assert st[0]["status"] == emg.EMG_ESTATE
+    p.solve(rtol=1e-10, precision="fp64")
+    st = emg.solve_batch_noalloc([p], rtol=1e-10, precision="mixed", raise_on_error=False)
+    assert st[0]["status"] == emg.EMG_ESTATE          # no FP32 copies yet
+    st = emg.solve_batch_noalloc([p], rtol=1e-10, precision="fp64")
+    assert st[0]["converged"]
+    # new moduli drop the hierarchy: refused again until a solve rebuilds it
+    p.set_moduli(spec.C)
+    st = emg.solve_batch_noalloc([p], rtol=1e-10, raise_on_error=False)
+    assert st[0]["status"] == emg.EMG_ESTATE
+    p.close()
