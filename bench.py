@@ -401,15 +401,17 @@ def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4)):
 
 
 def amr_penny_crack(emg, ctx, synth):
-    """The diffuse penny crack on a 65^3 base with two refined
-    boxes (reflux-free composite system), FP64 and mixed precision to 1e-10
-    (second solve of each, after setup); composite DoF/s and the mixed
-    solution's difference from the FP64 one."""
+    """The diffuse penny crack on a 65^3 base, three levels of 16/32-cell
+    blocks where |grad eta| h > 0.1 (reflux-free composite system), FP64 and
+    mixed precision to 1e-10 (second solve of each, after setup); composite
+    DoF/s and the mixed solution's difference from the FP64 one."""
     import numpy as np
-    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.05)
+    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.01)
     prob = emg.Problem.from_amr(ctx, ap)
-    out = {"workload": "penny crack R=0.2 (moduli floor 1e-2, width 0.05), base 65^3 nodes, 3 levels",
-           "boxes": [[list(lo), list(hi)] for lo, hi in ap.boxes], "composite_nodes": ap.composite_nodes()}
+    out = {"workload": "penny crack R=0.2, width 0.01, moduli floor 1e-2 (the 1 % cap), base 65^3 nodes, "
+                       "3 levels of 16/32-cell blocks tagged where |grad eta| h > 0.1",
+           "boxes_per_level": [len(ap.level_boxes(k)) for k in range(1, len(ap.boxes) + 1)],
+           "bounding_boxes": [[list(lo), list(hi)] for lo, hi in ap.boxes], "composite_nodes": ap.composite_nodes()}
     sols = {}
     for prec in ("fp64", "mixed"):
         st = [prob.solve(rtol=1e-10, max_cycles=400, precision=prec) for _ in range(2)][-1]

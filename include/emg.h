@@ -174,13 +174,21 @@ emg_status emg_set_face(emg_problem *p, int face, const double *values, int on_d
  * EMG_ENOTCONV / EMG_EDIVERGED still leave the last iterate readable. */
 emg_status emg_solve(emg_problem *p, const emg_solve_opts *opts, emg_solve_stats *stats);
 
-/* Outputs on level 0: displacement (d components) and stress
- * sigma = C (grad u - eps0) in Voigt order (6 in 3D: 11,22,33,23,31,12;
- * 3 in 2D: 11,22,12); central differences inside, 3-point one-sided on
- * non-periodic faces.  Also the assembled right-hand side (d components). */
+/* Outputs on level 0: displacement (d components) and the assembled
+ * right-hand side (d components).  Stress sigma = C (grad u - eps0) (Sec. 4.3)
+ * in Voigt order (6 in 3D: 11,22,33,23,31,12; 3 in 2D: 11,22,12) on `level`:
+ * 0 = the base grid (6 or 3 components over its stored nodes; central
+ * differences inside, 3-point one-sided on non-periodic faces); k >= 1 = the
+ * refined level k after a solve (over its bounding array, extents of
+ * emg_amr_level_shape), from its displacement with the interpolated ghosts
+ * and the moduli of the solve (covered nodes averaged from level k+1);
+ * values are the stress of the composite solution at valid nodes (central
+ * differences: their neighbours are valid or ghosts); at other nodes they
+ * are those of the interpolated coarse field (3-point one-sided on the
+ * array's outer ring).  EMG_EINVAL for a level that does not exist. */
 emg_status emg_get_displacement(emg_problem *p, double *u, int on_device);
 emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device);
-emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device);
+emg_status emg_get_stress(emg_problem *p, int level, double *sigma, int on_device);
 /* Von Mises stress sqrt(3/2 S_ij S_ij), S the deviator of the stress that
  * emg_get_stress returns (Sec. 4.3), one value per stored node of level 0.
  * 3D problems only (EMG_EINVAL in 2D: plane strain does not store the moduli
@@ -295,21 +303,26 @@ emg_status emg_server_now(emg_server *s, double *t);
 emg_status emg_server_destroy(emg_server *s);
 
 /* ---- block-structured AMR with reflux-free coarse/fine coupling (Sec. 3.2, App. A) ----
- * Refined level k >= 1 (ratio 2) is one box of valid nodes [lo, hi] of its
- * own index space (inclusive; every bound even, so the box corners fall on
- * coarse nodes).  It must lie inside level k-1's box (the base grid for
- * k = 1) with at least two coarse cells to spare, off the domain boundary and
- * off periodic axes.  Level-k fields are laid out over the box grown by one
- * ghost node per side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x]
- * (EMG_EINVAL for bounds that break these rules or a box of 2^29 or more
- * stored nodes).  Composite system solved by emg_solve (EMG_FP64: composite
+ * Refined level k >= 1 (ratio 2, spacing h_{k-1}/2) is a list of boxes of
+ * nodes of its own index space (inclusive bounds, every bound even so box
+ * corners fall on coarse nodes; Sec. 1 block-structured hierarchy, Fig.
+ * "hierarchy").  Its valid nodes are the union of the boxes; boxes may touch
+ * or overlap (shared nodes are simply valid).  Every box grown by two coarse
+ * cells must consist of valid nodes of level k-1 (for k = 1: lie inside the
+ * base grid, off its boundary, on non-periodic axes).  Level-k fields are
+ * laid out over the bounding box [lo, hi] of the list grown by one node per
+ * side: extents m[a] = hi[a] - lo[a] + 3, [comp][z][y][x]; nodes of that
+ * array that are not valid are ghosts (next to valid nodes) or unused, and
+ * input fields must hold finite values there, moduli positive definite
+ * (EMG_EINVAL for bounds that break these rules or a bounding array of 2^29
+ * or more nodes).  Composite system solved by emg_solve (EMG_FP64: composite
  * cycles in FP64; EMG_MIXED: FP64 state, composite residual, convergence test
  * and update around an FP32 composite correction cycle):
- *   - unknowns: valid nodes of every box plus the coarser nodes not covered by
- *     the next finer box; a covered coarse node takes the coincident fine
- *     value (App. A, phi_c2 = phi_f4);
- *   - fine ghost nodes take the bi/trilinear interpolation of the next coarser
- *     level (App. A, phi_f3 = (phi_c1 + phi_c2)/2);
+ *   - unknowns: valid nodes of every refined level plus the coarser nodes not
+ *     covered by valid nodes of the next level; a covered coarse node takes
+ *     the coincident fine value (App. A, phi_c2 = phi_f4);
+ *   - fine nodes that are not valid take the bi/trilinear interpolation of
+ *     the next coarser level (App. A, phi_f3 = (phi_c1 + phi_c2)/2);
  *   - fine valid rows use the fine operator, uncovered coarse rows the coarse
  *     operator; moduli and eigenstrain of covered coarse nodes are replaced by
  *     the full-weighting average of the finer level (Sec. 1: coarse levels
@@ -317,8 +330,21 @@ emg_status emg_server_destroy(emg_server *s);
  * The relative residual is the 2-norm over all composite rows.  With a warm
  * start the reference norm is the warm iterate's own residual.  After a solve
  * emg_get_displacement returns the base grid (covered nodes injected) and
- * emg_amr_get_displacement a box with its ghosts interpolated. */
+ * emg_amr_get_displacement a level's array with its other nodes
+ * interpolated. */
+typedef struct {
+  int64_t lo[3], hi[3];   /* inclusive node box in its level's index space (2D: lo[2] = hi[2] = 0) */
+} emg_box;
+/* Adds refined level `level` as the union of boxes[0..nbox-1] (copied).
+ * Levels are added in order: `level` must be the number of refined levels
+ * so far plus one (EMG_ESTATE otherwise); nbox >= 1.  Drops the problem's
+ * hierarchy and graphs (moduli of the new level must be set before a solve). */
+emg_status emg_set_level_boxes(emg_problem *p, int level, const emg_box *boxes, int nbox);
+/* One-box form of emg_set_level_boxes for the next level. */
 emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t hi[3]);
+/* Valid-node mask of refined level `level` over its bounding array (1 byte
+ * per node, layout [z][y][x]; NULL to skip) and the number of valid nodes. */
+emg_status emg_amr_level_valid(emg_problem *p, int level, unsigned char *mask, int64_t *nvalid);
 emg_status emg_amr_num_levels(emg_problem *p, int *levels);
 emg_status emg_amr_level_shape(emg_problem *p, int level, int64_t m[3]);
 emg_status emg_amr_set_moduli(emg_problem *p, int level, const double *C, int on_device);

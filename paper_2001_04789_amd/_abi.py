@@ -40,6 +40,10 @@ class emg_domain(ctypes.Structure):
                 ("bc", c_int * 6), ("kind", c_int)]
 
 
+class emg_box(ctypes.Structure):
+    _fields_ = [("lo", c_int64 * 3), ("hi", c_int64 * 3)]
+
+
 class emg_solve_opts(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("max_cycles", c_int), ("precision", c_int), ("nu1", c_int), ("nu2", c_int),
                 ("omega", c_double), ("warm_start", c_int), ("check_every", c_int), ("use_graph", c_int),
@@ -80,7 +84,7 @@ _SIGS = {
     "emg_solve": ([c_void_p, P(emg_solve_opts), P(emg_solve_stats)], c_int),
     "emg_get_displacement": ([c_void_p, c_void_p, c_int], c_int),
     "emg_set_displacement": ([c_void_p, c_void_p, c_int], c_int),
-    "emg_get_stress": ([c_void_p, c_void_p, c_int], c_int),
+    "emg_get_stress": ([c_void_p, c_int, c_void_p, c_int], c_int),
     "emg_get_von_mises": ([c_void_p, c_void_p, c_int], c_int),
     "emg_level_zmarch": ([c_void_p, c_int, c_int, P(c_int)], c_int),
     "emg_get_rhs": ([c_void_p, c_void_p, c_int], c_int),
@@ -105,6 +109,8 @@ _SIGS = {
     "emg_server_now": ([c_void_p, P(c_double)], c_int),
     "emg_server_destroy": ([c_void_p], c_int),
     "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
+    "emg_set_level_boxes": ([c_void_p, c_int, c_void_p, c_int], c_int),
+    "emg_amr_level_valid": ([c_void_p, c_int, c_void_p, P(c_int64)], c_int),
     "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
     "emg_amr_level_shape": ([c_void_p, c_int, P(c_int64)], c_int),
     "emg_amr_set_moduli": ([c_void_p, c_int, c_void_p, c_int], c_int),
@@ -403,8 +409,17 @@ class Problem:
         ptr, dev, keep = _host_or_device(u)
         check(lib.emg_set_displacement(self.handle, ptr, dev), "emg_set_displacement")
 
-    def stress(self, out=None):
-        return self._get(lib.emg_get_stress, 6 if self.dim == 3 else 3, out)
+    def stress(self, out=None, level: int = 0):
+        """Voigt stress on the base grid (level 0) or on refined level k (its
+        bounding array, valid after a solve)."""
+        comps = 6 if self.dim == 3 else 3
+        if out is not None:
+            check(lib.emg_get_stress(self.handle, level, _dev(out), 1), "emg_get_stress")
+            return out
+        m = self.m if level == 0 else self.amr_level_shape(level)
+        a = np.empty((comps, m[2], m[1], m[0]))
+        check(lib.emg_get_stress(self.handle, level, a.ctypes.data_as(c_void_p), 0), "emg_get_stress")
+        return a
 
     def von_mises(self, out=None):
         """Von Mises stress per node (3D), shape (1, mz, my, mx) on the host."""
@@ -468,14 +483,35 @@ class Problem:
         """Create from an AMR description (base problem + nested boxes with
         fields on the ghosted boxes, e.g. ``synth.AmrProblem``)."""
         p = cls.from_spec(ctx, amr.base)
-        for k, (lo, hi) in enumerate(amr.boxes, start=1):
-            p.amr_add_level(lo, hi)
+        for k in range(1, len(amr.boxes) + 1):
+            boxes = amr.level_boxes(k) if hasattr(amr, "level_boxes") else [amr.boxes[k - 1]]
+            p.set_level_boxes(k, boxes)
             p.amr_set_moduli(k, amr.C[k - 1])
             if amr.eps0[k - 1] is not None:
                 p.amr_set_eigenstrain(k, amr.eps0[k - 1])
             if amr.b[k - 1] is not None:
                 p.amr_set_body_force(k, amr.b[k - 1])
         return p
+
+    def set_level_boxes(self, level, boxes):
+        """Refined level `level` (the next one) as the union of boxes, each
+        ((lo_x, lo_y, lo_z), (hi_x, hi_y, hi_z)) in that level's index space."""
+        arr = (emg_box * len(boxes))()
+        for i, (lo, hi) in enumerate(boxes):
+            for a in range(3):
+                arr[i].lo[a] = int(lo[a]) if a < len(lo) else 0
+                arr[i].hi[a] = int(hi[a]) if a < len(hi) else 0
+        check(lib.emg_set_level_boxes(self.handle, int(level), ctypes.cast(arr, c_void_p), len(boxes)),
+              "emg_set_level_boxes")
+
+    def amr_level_valid(self, level):
+        """Valid-node mask (bool, [z][y][x]) of a refined level's array and its count."""
+        m = self.amr_level_shape(level)
+        mask = np.zeros((m[2], m[1], m[0]), dtype=np.uint8)
+        n = c_int64()
+        check(lib.emg_amr_level_valid(self.handle, level, mask.ctypes.data_as(c_void_p), ctypes.byref(n)),
+              "emg_amr_level_valid")
+        return mask.astype(bool), int(n.value)
 
     def amr_add_level(self, lo, hi):
         l3 = (c_int64 * 3)(*[int(v) for v in lo])
@@ -546,7 +582,7 @@ def autotune_reset():
 
 __all__ = ["lib", "LIB_PATH", "SYMBOLS", "Context", "Problem", "Server", "EmgError", "check", "default_opts", "solve_batch", "solve_batch_noalloc",
            "autotune_reset",
-           "emg_domain", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
+           "emg_domain", "emg_box", "emg_solve_opts", "emg_solve_stats", "emg_request", "emg_ticket_info",
            "EMG_OK", "EMG_EINVAL", "EMG_ENOMEM", "EMG_EDEVICE", "EMG_ENOTCONV", "EMG_EDIVERGED", "EMG_ESTATE", "EMG_EBUSY", "EMG_NOALLOC_SCRATCH_BYTES",
            "EMG_BC_DIRICHLET", "EMG_BC_TRACTION", "EMG_BC_PERIODIC", "EMG_BC_NEUMANN", "EMG_VCYCLE", "EMG_FCYCLE",
            "EMG_MOD_ISO", "EMG_MOD_ANISO",

@@ -77,12 +77,19 @@ struct Level {
   double *f64 = nullptr, *r64 = nullptr;
   float *u32[2] = {nullptr, nullptr};
   float *f32 = nullptr, *r32 = nullptr;
+  const unsigned char *vm = nullptr;   // refined AMR level: valid-node mask (masked tile passes)
 };
 
-// One refined AMR level: a box of valid nodes with a one-node ghost layer.
+// One refined AMR level: valid nodes = the union of `boxes`, stored over
+// their bounding box b grown by one node, with the valid-node mask vm.
 struct Fine {
   Geom g{};
   Box b{};
+  std::vector<Box> boxes;
+  std::vector<unsigned char> hmask;   // host copy of vm (nesting checks of the next level)
+  unsigned char *vm = nullptr;
+  double *sig = nullptr;              // stress output buffer (allocated on first use)
+  long long nvalid = 0, ncov = 0;     // valid nodes; coarse nodes they cover
   double *C = nullptr, *eps = nullptr, *body = nullptr;
   double *f = nullptr, *u = nullptr, *rr = nullptr, *t = nullptr;
   double *e[2] = {nullptr, nullptr};
@@ -340,6 +347,16 @@ int zm_plan(const emg_problem *p, const Geom &g) {
 template <typename R, int MODE, typename TO>
 void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *out, R omega, double *partial,
                     const Ctl *ctl) {
+  if constexpr (MODE != MODE_APPLY) {
+    if (L.vm) {   // refined AMR level: tile kernel with the valid-node mask (no norm partials)
+      dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+        constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+        hipLaunchKernelGGL((k_stencil_mask<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0,
+                           p->stream, L.g, moduli<R>(L), u, f, out, omega, L.vm, ctl);
+      });
+      return;
+    }
+  }
   const int nzc = zm_plan<R>(p, L.g);
   if (nzc > 0) {
     const Split sp = split_of(L.g);
@@ -360,7 +377,7 @@ void launch_jacobi_zero(emg_problem *p, const Level &L, const R *f, R *out, R om
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
     hipLaunchKernelGGL((k_jacobi_zero<D, K, R>), grid_of(L.g), kBlock, 0, p->stream, L.g, moduli<R>(L), f, out, omega,
-                       ctl);
+                       ctl, L.vm);
   });
 }
 
@@ -422,13 +439,13 @@ emg_status setup(emg_problem *p) {
     const dim3 gr((F.b.hi[0] / 2 - F.b.lo[0] / 2 + BX) / BX, (F.b.hi[1] / 2 - F.b.lo[1] / 2 + BY) / BY,
                   p->D == 3 ? F.b.hi[2] / 2 - F.b.lo[2] / 2 + 1 : 1);
     if (p->D == 2) {
-      hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc, F.g.SC, gc.SC);
+      hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.vm, F.C, Cc, p->nc, F.g.SC, gc.SC);
       if (Ec && F.eps)
-        hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne, F.g.N, gc.N);
+        hipLaunchKernelGGL((k_average_cf<2>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.vm, F.eps, Ec, p->ne, F.g.N, gc.N);
     } else {
-      hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.C, Cc, p->nc, F.g.SC, gc.SC);
+      hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.vm, F.C, Cc, p->nc, F.g.SC, gc.SC);
       if (Ec && F.eps)
-        hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.eps, Ec, p->ne, F.g.N, gc.N);
+        hipLaunchKernelGGL((k_average_cf<3>), gr, kBlock, 0, p->stream, gc, co, F.g, F.b, F.vm, F.eps, Ec, p->ne, F.g.N, gc.N);
     }
   }
   const int L = (int)p->lv.size();
@@ -696,6 +713,7 @@ Level box_level(const Fine &F) {
   L.g = F.g;
   L.C64 = F.C;
   L.C32 = F.C32;
+  L.vm = F.vm;
   return L;
 }
 
@@ -706,49 +724,44 @@ void amr_sync(emg_problem *p, double *u0, const Ctl *ctl) {
     Fine &F = p->fine[k - 1];
     double *uc = k == 1 ? u0 : p->fine[k - 2].u;
     hipLaunchKernelGGL((k_inject<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, parent_geom(p, k),
-                       parent_origin(p, k), F.g, F.b, F.u, uc, D, ctl);
+                       parent_origin(p, k), F.g, F.b, F.vm, F.u, uc, D, ctl);
   }
   for (int k = 1; k <= Lf; k++) {
     Fine &F = p->fine[k - 1];
     const double *uc = k == 1 ? u0 : p->fine[k - 2].u;
     hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, uc, F.u, (double *)nullptr, 1, ctl);
+                       F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 1, ctl);
   }
 }
 
-// covered region of level k+1 inside level k's array, for the masked norm
-void covered_array_box(emg_problem *p, int k, int3 &xlo, int3 &xhi) {
-  if (k + 1 > (int)p->fine.size()) {
-    xlo = make_int3(1, 1, 1);
-    xhi = make_int3(0, 0, 0);
-    return;
-  }
-  const Box &b = p->fine[k].b;
-  const int3 co = k == 0 ? make_int3(0, 0, 0) : parent_origin(p, k + 1);
-  xlo = make_int3(b.lo[0] / 2 - co.x, b.lo[1] / 2 - co.y, p->D == 3 ? b.lo[2] / 2 - co.z : 0);
-  xhi = make_int3(b.hi[0] / 2 - co.x, b.hi[1] / 2 - co.y, p->D == 3 ? b.hi[2] / 2 - co.z : 0);
-}
-
-// Composite residual of the (synced) state: base rows into L0.f64, box rows
-// into each box's rr, squared-norm partials of the composite rows.
+// Composite residual of the (synced) state: base rows into L0.f64, refined
+// rows into each level's rr, squared-norm partials of the composite rows.
 template <int D>
 void amr_residual(emg_problem *p, const Ctl *ctl) {
   Level &L0 = p->lv[0];
+  const int Lf = (int)p->fine.size();
   launch_stencil<double, MODE_RESID, double>(p, L0, p->amr_u0, p->amr_f0, L0.f64, 0.0, nullptr, ctl);
   long long off = 0;
-  int3 xlo, xhi;
-  covered_array_box(p, 0, xlo, xhi);
-  hipLaunchKernelGGL((k_masked_norm<D>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.f64, xlo, xhi,
-                     p->amr_partial + off, ctl);
-  off += grid_blocks(L0.g);
-  for (int k = 1; k <= (int)p->fine.size(); k++) {
-    Fine &F = p->fine[k - 1];
-    Level B = box_level(F);
-    launch_stencil<double, MODE_RESID, double>(p, B, F.u, F.f, F.rr, 0.0, nullptr, ctl);
-    covered_array_box(p, k, xlo, xhi);
-    hipLaunchKernelGGL((k_masked_norm<D>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr, xlo, xhi,
+  for (int k = 0; k <= Lf; k++) {
+    const Geom &g = k == 0 ? L0.g : p->fine[k - 1].g;
+    const double *r = k == 0 ? L0.f64 : p->fine[k - 1].rr;
+    const unsigned char *own = k == 0 ? nullptr : p->fine[k - 1].vm;
+    const int3 co = k == 0 ? make_int3(0, 0, 0) : parent_origin(p, k + 1);
+    Geom cg{};
+    Box cb{};
+    const unsigned char *cvm = nullptr;
+    if (k < Lf) {
+      cg = p->fine[k].g;
+      cb = p->fine[k].b;
+      cvm = p->fine[k].vm;
+    }
+    if (k > 0) {
+      Fine &F = p->fine[k - 1];
+      launch_stencil<double, MODE_RESID, double>(p, box_level(F), F.u, F.f, F.rr, 0.0, nullptr, ctl);
+    }
+    hipLaunchKernelGGL((k_masked_norm<D>), grid_of(g), kBlock, 0, p->stream, g, r, own, co, cg, cb, cvm,
                        p->amr_partial + off, ctl);
-    off += grid_blocks(F.g);
+    off += grid_blocks(g);
   }
 }
 
@@ -770,7 +783,7 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
   for (int k = Lf; k >= 1; k--) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
-    hipLaunchKernelGGL((k_ghost_fill<D, double>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr, 0.0, p->ctl);
+    hipLaunchKernelGGL((k_ghost_fill<D, double>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.vm, F.rr, 0.0, p->ctl);
     launch_jacobi_zero<double>(p, B, F.rr, F.e[0], omega, p->ctl);
     int c = 0;
     for (int s = 1; s < nu1; s++) {
@@ -786,9 +799,9 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
     dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
       constexpr int DD = decltype(Dc)::value, K = decltype(Kc)::value;
       hipLaunchKernelGGL((k_cf_update<DD, K, double>), covered_grid(p, F.b, 1), kBlock, 0, p->stream, gc, co, F.g, F.b,
-                         Cc, (const double *)F.e[c], rrc, p->ctl);
+                         F.vm, Cc, (const double *)F.e[c], rrc, p->ctl);
     });
-    hipLaunchKernelGGL((k_restrict_cf<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b,
+    hipLaunchKernelGGL((k_restrict_cf<D, double>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b, F.vm,
                        (const double *)F.t, gc, co, rrc, p->ctl);
   }
   const int cb = coarse_cycle<double>(p, 0, nu1, nu2, omega, fcyc);
@@ -798,7 +811,7 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
     const double *ec = k == 1 ? L0.u64[cb] : p->fine[k - 2].e[cur[k - 1]];
     int c = cur[k];
     hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, ec, F.e[c], F.rr, 2, p->ctl);
+                       F.g, F.b, F.vm, ec, F.e[c], F.rr, 2, p->ctl);
     for (int s = 0; s < nu2; s++) {
       launch_stencil<double, MODE_JACOBI, double>(p, B, F.e[c], F.rr, F.e[c ^ 1], omega, nullptr, p->ctl);
       c ^= 1;
@@ -835,7 +848,7 @@ void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool 
   for (int k = Lf; k >= 1; k--) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
-    hipLaunchKernelGGL((k_ghost_fill<D, float>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.rr32, 0.0f, p->ctl);
+    hipLaunchKernelGGL((k_ghost_fill<D, float>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.vm, F.rr32, 0.0f, p->ctl);
     launch_jacobi_zero<float>(p, B, F.rr32, F.e32[0], omega, p->ctl);
     int c = 0;
     for (int s = 1; s < nu1; s++) {
@@ -851,9 +864,9 @@ void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool 
     dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
       constexpr int DD = decltype(Dc)::value, K = decltype(Kc)::value;
       hipLaunchKernelGGL((k_cf_update<DD, K, float>), covered_grid(p, F.b, 1), kBlock, 0, p->stream, gc, co, F.g, F.b,
-                         Cc, (const float *)F.e32[c], rrc, p->ctl);
+                         F.vm, Cc, (const float *)F.e32[c], rrc, p->ctl);
     });
-    hipLaunchKernelGGL((k_restrict_cf<D, float>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b,
+    hipLaunchKernelGGL((k_restrict_cf<D, float>), covered_grid(p, F.b, 0), kBlock, 0, p->stream, F.g, F.b, F.vm,
                        (const float *)F.t32, gc, co, rrc, p->ctl);
   }
   const int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc);
@@ -863,7 +876,7 @@ void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool 
     const float *ec = k == 1 ? L0.u32[cb] : p->fine[k - 2].e32[cur[k - 1]];
     int c = cur[k];
     hipLaunchKernelGGL((k_interp<D, float>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, ec, F.e32[c], F.rr32, 2, p->ctl);
+                       F.g, F.b, F.vm, ec, F.e32[c], F.rr32, 2, p->ctl);
     for (int s = 0; s < nu2; s++) {
       launch_stencil<float, MODE_JACOBI, float>(p, B, F.e32[c], F.rr32, F.e32[c ^ 1], omega, nullptr, p->ctl);
       c ^= 1;
@@ -2081,10 +2094,10 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
         const double *uc = k == 1 ? p->amr_u0 : p->fine[k - 2].u;
         if (p->D == 2)
           hipLaunchKernelGGL((k_interp<2, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
-                             parent_origin(p, k), F.g, F.b, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+                             parent_origin(p, k), F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
         else
           hipLaunchKernelGGL((k_interp<3, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
-                             parent_origin(p, k), F.g, F.b, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+                             parent_origin(p, k), F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
       }
     }
     // with a warm start the reference norm is the warm iterate's composite residual
@@ -2175,14 +2188,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
     dir_nodes = g.N - inner;
   }
   long long unknown_nodes = L0.g.N - dir_nodes;
-  for (auto &F : p->fine) {
-    long long valid = 1, cov = 1;
-    for (int a = 0; a < p->D; a++) {
-      valid *= F.b.hi[a] - F.b.lo[a] + 1;
-      cov *= F.b.hi[a] / 2 - F.b.lo[a] / 2 + 1;
-    }
-    unknown_nodes += valid - cov;
-  }
+  for (auto &F : p->fine) unknown_nodes += F.nvalid - F.ncov;
   s.dofs = (long long)p->D * unknown_nodes;
   s.fp64_fallback = fell_back ? 1 : 0;
   if (st) *st = s;
@@ -2210,17 +2216,31 @@ emg_status emg_get_rhs(emg_problem *p, double *f, int on_device) {
   return copy_out(p, f, p->fine.empty() ? p->lv[0].f64 : p->amr_f0, (size_t)p->D * p->lv[0].g.N, on_device);
 }
 
-emg_status emg_get_stress(emg_problem *p, double *sigma, int on_device) {
+emg_status emg_get_stress(emg_problem *p, int level, double *sigma, int on_device) {
   if (!p || !sigma) return fail(EMG_EINVAL, "null argument");
   if (!p->moduli_set) return fail(EMG_ESTATE, "moduli not set");
-  const Level &L0 = p->lv[0];
-  if (!p->sig) TRY(dalloc(p, &p->sig, (size_t)p->ne * L0.g.N));
+  if (level < 0 || level > (int)p->fine.size()) return fail(EMG_EINVAL, "no such level");
+  if (level == 0) {
+    const Level &L0 = p->lv[0];
+    if (!p->sig) TRY(dalloc(p, &p->sig, (size_t)p->ne * L0.g.N));
+    dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+      constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+      hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, base_u(p),
+                         p->sig);
+    });
+    HIPCK(hipGetLastError());
+    return copy_out(p, sigma, p->sig, (size_t)p->ne * L0.g.N, on_device);
+  }
+  TRY(setup(p));   // moduli of covered nodes averaged from the finer level, as in the solve
+  Fine &F = p->fine[level - 1];
+  if (!F.sig) TRY(dalloc(p, &F.sig, (size_t)p->ne * F.g.N));
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_stress<D, K>), grid_of(L0.g), kBlock, 0, p->stream, L0.g, L0.C64, p->eps, base_u(p), p->sig);
+    hipLaunchKernelGGL((k_stress<D, K>), grid_of(F.g), kBlock, 0, p->stream, F.g, (const double *)F.C,
+                       (const double *)F.eps, (const double *)F.u, F.sig);
   });
   HIPCK(hipGetLastError());
-  return copy_out(p, sigma, p->sig, (size_t)p->ne * L0.g.N, on_device);
+  return copy_out(p, sigma, F.sig, (size_t)p->ne * F.g.N, on_device);
 }
 
 emg_status emg_get_von_mises(emg_problem *p, double *svm, int on_device) {
@@ -2768,26 +2788,59 @@ emg_status emg_server_destroy(emg_server *S) {
 
 // ---- block-structured AMR ----
 
-emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t hi[3]) {
-  if (!p || !lo || !hi) return fail(EMG_EINVAL, "null argument");
+// Refined level `level` (the next one) as the union of `boxes`: checks
+// bounds and nesting, builds the bounding array and its valid-node mask.
+static emg_status add_refined_level(emg_problem *p, int level, const emg_box *boxes, int nbox) {
+  if (!p || !boxes || nbox < 1) return fail(EMG_EINVAL, "null argument or no boxes");
   const int k = (int)p->fine.size() + 1;
+  if (level != k)
+    return fail(EMG_ESTATE, "refined levels are added in order; the next one is level " + std::to_string(k));
   const Geom &pg = parent_geom(p, k);
+  const Fine *par = k == 1 ? nullptr : &p->fine[k - 2];
   Fine F;
-  int plo[3], phi[3];
-  for (int a = 0; a < 3; a++) {
-    if (k == 1) { plo[a] = 0; phi[a] = pg.m[a] - 1; }
-    else { plo[a] = p->fine[k - 2].b.lo[a]; phi[a] = p->fine[k - 2].b.hi[a]; }
-  }
   F.g.dim = p->D;
+  for (int i = 0; i < nbox; i++) {
+    Box bx{};
+    for (int a = 0; a < 3; a++) {
+      if (a >= p->D) continue;
+      const int64_t lo = boxes[i].lo[a], hi = boxes[i].hi[a];
+      if (lo % 2 || hi % 2 || hi <= lo) return fail(EMG_EINVAL, "box bounds must be even with hi > lo");
+      if (lo < 0 || hi > (int64_t)1 << 30) return fail(EMG_EINVAL, "box bounds out of range");
+      if (k == 1 && pg.per[a]) return fail(EMG_EINVAL, "refined boxes need non-periodic axes");
+      if (k == 1 && (lo / 2 - 2 < 0 || hi / 2 + 2 > pg.m[a] - 1))
+        return fail(EMG_EINVAL, "box must nest inside the base grid with two coarse cells to spare");
+      bx.lo[a] = (int)lo;
+      bx.hi[a] = (int)hi;
+    }
+    if (par) {   // every coarse node of the box grown by two coarse cells is a valid node of level k-1
+      const int o[3] = {par->b.lo[0] - 1, par->b.lo[1] - 1, p->D == 3 ? par->b.lo[2] - 1 : 0};
+      int q0[3] = {0, 0, 0}, q1[3] = {0, 0, 0};
+      for (int a = 0; a < p->D; a++) {
+        q0[a] = bx.lo[a] / 2 - 2 - o[a];
+        q1[a] = bx.hi[a] / 2 + 2 - o[a];
+        if (q0[a] < 0 || q1[a] > par->g.m[a] - 1)
+          return fail(EMG_EINVAL, "box must nest inside the valid nodes of the coarser level with two coarse cells "
+                                  "to spare");
+      }
+      for (int z = q0[2]; z <= q1[2]; z++)
+        for (int y = q0[1]; y <= q1[1]; y++)
+          for (int x = q0[0]; x <= q1[0]; x++)
+            if (!par->hmask[((size_t)z * par->g.m[1] + y) * par->g.m[0] + x])
+              return fail(EMG_EINVAL, "box must nest inside the valid nodes of the coarser level with two coarse "
+                                      "cells to spare");
+    }
+    F.boxes.push_back(bx);
+  }
   for (int a = 0; a < 3; a++) {
     if (a < p->D) {
-      if (lo[a] % 2 || hi[a] % 2 || hi[a] <= lo[a]) return fail(EMG_EINVAL, "box bounds must be even with hi > lo");
-      if (lo[a] / 2 - 2 < plo[a] || hi[a] / 2 + 2 > phi[a])
-        return fail(EMG_EINVAL, "box must nest inside the coarser level with two coarse cells to spare");
-      if (k == 1 && pg.per[a]) return fail(EMG_EINVAL, "refined boxes need non-periodic axes");
-      F.b.lo[a] = (int)lo[a];
-      F.b.hi[a] = (int)hi[a];
-      F.g.m[a] = (int)(hi[a] - lo[a] + 3);
+      int lo = F.boxes[0].lo[a], hi = F.boxes[0].hi[a];
+      for (auto &bx : F.boxes) {
+        lo = std::min(lo, bx.lo[a]);
+        hi = std::max(hi, bx.hi[a]);
+      }
+      F.b.lo[a] = lo;
+      F.b.hi[a] = hi;
+      F.g.m[a] = hi - lo + 3;
       F.g.per[a] = 0;
       F.g.h[a] = pg.h[a] / 2.0;
       F.g.bc[2 * a] = F.g.bc[2 * a + 1] = EMG_BC_DIRICHLET;
@@ -2800,9 +2853,28 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
     }
   }
   F.g.N = (long long)F.g.m[0] * F.g.m[1] * F.g.m[2];
-  if (F.g.N >= kMaxNodes) return fail(EMG_EINVAL, "box too large (2^29 stored nodes at most)");
+  if (F.g.N >= kMaxNodes) return fail(EMG_EINVAL, "level too large (2^29 stored nodes at most in its bounding box)");
   F.g.SC = moduli_stride(F.g.N);
+  // valid-node mask over the bounding array; counts of valid and covered-coarse nodes
+  F.hmask.assign((size_t)F.g.N, 0);
+  for (auto &bx : F.boxes) {
+    const int z0 = p->D == 3 ? bx.lo[2] - F.b.lo[2] + 1 : 0, z1 = p->D == 3 ? bx.hi[2] - F.b.lo[2] + 1 : 0;
+    for (int z = z0; z <= z1; z++)
+      for (int y = bx.lo[1] - F.b.lo[1] + 1; y <= bx.hi[1] - F.b.lo[1] + 1; y++)
+        for (int x = bx.lo[0] - F.b.lo[0] + 1; x <= bx.hi[0] - F.b.lo[0] + 1; x++)
+          F.hmask[((size_t)z * F.g.m[1] + y) * F.g.m[0] + x] = 1;
+  }
+  for (long long n = 0; n < F.g.N; n++) {
+    if (!F.hmask[n]) continue;
+    F.nvalid++;
+    const int x = int(n % F.g.m[0]), y = int((n / F.g.m[0]) % F.g.m[1]), z = int(n / ((long long)F.g.m[0] * F.g.m[1]));
+    const bool even = (F.b.lo[0] - 1 + x) % 2 == 0 && (F.b.lo[1] - 1 + y) % 2 == 0 &&
+                      (p->D == 2 || (F.b.lo[2] - 1 + z) % 2 == 0);
+    if (even) F.ncov++;
+  }
   const size_t nd = (size_t)p->D * F.g.N;
+  TRY(dalloc(p, &F.vm, (size_t)F.g.N));
+  HIPCK(hipMemcpyAsync(F.vm, F.hmask.data(), (size_t)F.g.N, hipMemcpyHostToDevice, p->stream));
   TRY(dalloc(p, &F.C, (size_t)p->nc * F.g.SC));
   TRY(dalloc(p, &F.f, nd));
   TRY(dalloc(p, &F.u, nd));
@@ -2817,7 +2889,7 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
     launch_fill<double>(p, (long long)nd0, p->amr_u0, 0.0);
   }
   launch_fill<double>(p, (long long)nd, F.u, 0.0);
-  p->fine.push_back(F);
+  p->fine.push_back(std::move(F));
   // norm partials of every level's composite rows
   long long parts = grid_blocks(p->lv[0].g);
   for (auto &G : p->fine) parts += grid_blocks(G.g);
@@ -2826,6 +2898,29 @@ emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t 
   destroy_graphs(p);
   p->setup_done = p->rhs_ready = p->mixed_ready = false;
   HIPCK(hipStreamSynchronize(p->stream));
+  return EMG_OK;
+}
+
+emg_status emg_set_level_boxes(emg_problem *p, int level, const emg_box *boxes, int nbox) {
+  return add_refined_level(p, level, boxes, nbox);
+}
+
+emg_status emg_amr_add_level(emg_problem *p, const int64_t lo[3], const int64_t hi[3]) {
+  if (!p || !lo || !hi) return fail(EMG_EINVAL, "null argument");
+  emg_box b;
+  for (int a = 0; a < 3; a++) {
+    b.lo[a] = lo[a];
+    b.hi[a] = hi[a];
+  }
+  return add_refined_level(p, (int)p->fine.size() + 1, &b, 1);
+}
+
+emg_status emg_amr_level_valid(emg_problem *p, int level, unsigned char *mask, int64_t *nvalid) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  if (level < 1 || level > (int)p->fine.size()) return fail(EMG_EINVAL, "no such refined level");
+  const Fine &F = p->fine[level - 1];
+  if (mask) std::memcpy(mask, F.hmask.data(), F.hmask.size());
+  if (nvalid) *nvalid = F.nvalid;
   return EMG_OK;
 }
 

@@ -167,10 +167,15 @@ __device__ __forceinline__ void finish_rows(long long N, long long n, int cls, c
   }
 }
 
-template <int D, int K, typename R, int MODE, typename TO>
+// MASK (refined AMR levels): nodes of the interior box whose byte in vm is 0
+// (not valid: ghosts and nodes outside every box of the level) take the
+// Dirichlet row instead, as the outer ring of the level's array does.
+template <int D, int K, typename R, int MODE, typename TO, bool MASK = false>
 __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict__ C, const R *__restrict__ u,
                                              const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                             double *__restrict__ pslot, long long t) {
+                                             double *__restrict__ pslot, long long t,
+                                             const unsigned char *__restrict__ vm = nullptr) {
+  static_assert(!MASK || MODE != MODE_APPLY, "masked passes are residuals and sweeps");
   const Split sp = split_of(g);
   double nrm = 0.0;
   if (t >= sp.sblocks) {
@@ -198,15 +203,20 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
       R acc[D], dg[D], uc[D], fc[D];
       interior_rows<D, K, R, PtrU<R>, unsigned>(C, g.SC, PtrU<R>{u, g.N}, n, om, op, i2h, ih2, acc, dg,
                                                 MODE == MODE_APPLY ? nullptr : f, g.N, fc, uc);
+      const bool valid = !MASK || vm[n] != 0;
 #pragma unroll
-      for (int i = 0; i < D; i++) {   // interior rows: never Dirichlet
+      for (int i = 0; i < D; i++) {   // interior rows (unless masked out): never Dirichlet
         TO *__restrict__ oi = (TO *)((char *)(out + i * g.N) + n * (unsigned)sizeof(TO));
         if constexpr (MODE == MODE_APPLY) {
           *oi = TO(acc[i]);
         } else {
           const R r = fc[i] - acc[i];
-          *oi = MODE == MODE_RESID ? TO(r) : TO(uc[i] + omega * r / dg[i]);
-          nrm += double(r) * double(r);
+          if (valid) {
+            *oi = MODE == MODE_RESID ? TO(r) : TO(uc[i] + omega * r / dg[i]);
+            nrm += double(r) * double(r);
+          } else {
+            *oi = MODE == MODE_RESID ? TO(fc[i] - uc[i]) : TO(fc[i]);
+          }
         }
       }
     }
@@ -223,6 +233,17 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
     }
   }
   if (pslot) block_sum_256(nrm, pslot);
+}
+
+// The tile kernel on a refined AMR level: rows of nodes that are not valid
+// (vm[n] == 0) are Dirichlet rows.
+template <int D, int K, typename R, int MODE, typename TO>
+__global__ __launch_bounds__(256, 2) void k_stencil_mask(Geom g, const R *__restrict__ C, const R *__restrict__ u,
+                                                      const R *__restrict__ f, TO *__restrict__ out, R omega,
+                                                      const unsigned char *__restrict__ vm,
+                                                      const Ctl *__restrict__ ctl) {
+  if (skip(ctl)) return;
+  body_stencil<D, K, R, MODE, TO, true>(g, C, u, f, out, omega, nullptr, blockIdx.x, vm);
 }
 
 // One launch of split_of(g).blocks workgroups (64 x 4 threads) in dispatch
@@ -656,12 +677,13 @@ __global__ __launch_bounds__(256) void k_add_correction(long long n, double *__r
 // First sweep from a zero initial guess: out = omega f / diag (Dirichlet: f).
 template <int D, int K, typename R>
 __device__ __forceinline__ void body_jacobi_zero(const Geom &g, const R *__restrict__ C, const R *__restrict__ f,
-                                                 R *__restrict__ out, R omega, int tx, int ty, int tz) {
+                                                 R *__restrict__ out, R omega, int tx, int ty, int tz,
+                                                 const unsigned char *__restrict__ vm = nullptr) {
   const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
   if (x >= g.m[0] || y >= g.m[1]) return;
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
-  const int cls = row_class(g, p);
+  const int cls = (vm && !vm[n]) ? ROW_DIR : row_class(g, p);
   R dg[D];
   diag_at<D, K, R>(g, C, n, p, cls, dg);
 #pragma unroll
@@ -673,11 +695,12 @@ __device__ __forceinline__ void body_jacobi_zero(const Geom &g, const R *__restr
 
 template <int D, int K, typename R>
 __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
-                                                     R *__restrict__ out, R omega, const Ctl *__restrict__ ctl) {
+                                                     R *__restrict__ out, R omega, const Ctl *__restrict__ ctl,
+                                                     const unsigned char *__restrict__ vm) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  body_jacobi_zero<D, K, R>(g, C, f, out, omega, tx_, ty_, tz_);
+  body_jacobi_zero<D, K, R>(g, C, f, out, omega, tx_, ty_, tz_, vm);
 }
 
 // Per-axis full-weighting weights and fine offsets of coarse node P (fine
@@ -1270,49 +1293,64 @@ __global__ __launch_bounds__(256) void k_bottom_solve(const double *__restrict__
 }  // namespace emg
 
 // ======================= block-structured AMR coupling =======================
-// A refined level is one box of valid nodes [lo, hi] (even bounds) in its own
-// index space, stored with a one-node ghost layer (array extents hi-lo+3) as a
-// level whose faces are all Dirichlet: the ghost layer are the Dirichlet rows,
-// the valid nodes (including the coarse/fine boundary layer) the interior
+// A refined level is a list of boxes of valid nodes [lo, hi] (even bounds)
+// in its own index space; its fields are stored over the bounding box b of
+// the boxes grown by one node per side (array extents hi-lo+3), with a byte
+// mask vm over that array (1: valid node, the union of the boxes; 0: ghost
+// or outside every box).  The array is treated as a level whose faces are
+// all Dirichlet and whose masked-out nodes are Dirichlet rows as well, so
+// valid nodes (including the coarse/fine boundary layer) are the interior
 // rows.  Coarse arrays are addressed with `co`, the global index of their
-// array index 0 (0 for the base grid, lo-1 for a refined level's box).
+// array index 0 (0 for the base grid, lo-1 for a refined level).
 namespace emg {
 
 struct Box {
-  int lo[3], hi[3];   // valid nodes, fine index space
+  int lo[3], hi[3];   // nodes, fine index space (a level's bounding box)
 };
+
+using Mask = const unsigned char *__restrict__;
 
 // coarse node J (global) -> coarse array index, and fine global I -> fine array index
 __device__ __forceinline__ long long lin(const Geom &g, int x, int y, int z) {
   return ((long long)z * g.m[1] + y) * g.m[0] + x;
 }
 
+// Fine array index of the fine node coincident with coarse node (cx, cy, cz)
+// (global indices), for a coarse node under the bounding box b.
+template <int D>
+__device__ __forceinline__ long long coincident(const Geom &gf, const Box &b, int cx, int cy, int cz) {
+  return lin(gf, 2 * cx - b.lo[0] + 1, 2 * cy - b.lo[1] + 1, D == 3 ? 2 * cz - b.lo[2] + 1 : 0);
+}
+
 // Covered coarse nodes <- coincident fine values (Sec. 3.2 / App. A:
-// phi_c2 = phi_f4).  One thread per covered coarse node.
+// phi_c2 = phi_f4).  One thread per coarse node under the bounding box;
+// those whose fine node is not valid are not covered.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_inject(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ uf,
+__global__ __launch_bounds__(256) void k_inject(Geom gc, int3 co, Geom gf, Box b, Mask vm, const R *__restrict__ uf,
                                                 R *__restrict__ uc, int ncomp, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
   const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
   const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
   if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  const long long nf = coincident<D>(gf, b, cx, cy, cz);
+  if (!vm[nf]) return;
   const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
-  const long long nf = lin(gf, 2 * cx - b.lo[0] + 1, 2 * cy - b.lo[1] + 1, D == 3 ? 2 * cz - b.lo[2] + 1 : 0);
   for (int i = 0; i < ncomp; i++) uc[i * gc.N + nc] = uf[i * gf.N + nf];
 }
 
-// Full weighting of a field given on the ghosted box (moduli, eigenstrain)
+// Full weighting of a field given on the fine array (moduli, eigenstrain)
 // at the covered coarse nodes: coarse levels carry the average of the finer
-// level where it exists (Sec. 1).
-// sf, sc: component strides of af and ac.
+// level where it exists (Sec. 1).  sf, sc: component strides of af and ac.
 template <int D>
-__global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, Box b, const double *__restrict__ af,
-                                                    double *__restrict__ ac, int ncomp, long long sf, long long sc) {
+__global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, Box b, Mask vm,
+                                                    const double *__restrict__ af, double *__restrict__ ac, int ncomp,
+                                                    long long sf, long long sc) {
   const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
   const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
   const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
   if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  if (!vm[coincident<D>(gf, b, cx, cy, cz)]) return;
   const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
   const int fx = 2 * cx - b.lo[0] + 1, fy = 2 * cy - b.lo[1] + 1, fz = D == 3 ? 2 * cz - b.lo[2] + 1 : 0;
   for (int i = 0; i < ncomp; i++) {
@@ -1327,13 +1365,13 @@ __global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, B
   }
 }
 
-// Bi/trilinear interpolation of a coarse field at the nodes of the ghosted box.
+// Bi/trilinear interpolation of a coarse field at the nodes of the fine array.
 //   mode 0: dst = interp at every node
-//   mode 1: dst = interp at ghost nodes only
-//   mode 2: dst += interp at valid nodes, dst = interp at ghost nodes
-// dst2 (optional): = interp at ghost nodes.
+//   mode 1: dst = interp at nodes that are not valid
+//   mode 2: dst += interp at valid nodes, dst = interp at the others
+// dst2 (optional): = interp at nodes that are not valid.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ uc,
+__global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b, Mask vm, const R *__restrict__ uc,
                                                 R *__restrict__ dst, R *__restrict__ dst2, int mode,
                                                 const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
@@ -1342,8 +1380,8 @@ __global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b
   const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const int p[3] = {x, y, z};
-  bool ghost = false;
-  for (int a = 0; a < D; a++) ghost = ghost || p[a] == 0 || p[a] == gf.m[a] - 1;
+  const long long nf = lin(gf, x, y, z);
+  const bool ghost = !vm[nf];
   if (mode == 1 && !ghost) return;
   const int cox[3] = {co.x, co.y, co.z};
   int c0[3], c1[3];
@@ -1359,7 +1397,6 @@ __global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b
       w1[a] = R(0);
     }
   }
-  const long long nf = lin(gf, x, y, z);
   for (int i = 0; i < D; i++) {
     R v = R(0);
     for (int sz = 0; sz < (D == 3 ? 2 : 1); sz++)
@@ -1376,32 +1413,34 @@ __global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b
   }
 }
 
-// Ghost rows of a box array <- v.
+// Rows of a refined level's array that are not valid <- v.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_ghost_fill(Geom gf, R *__restrict__ a, R v, const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_ghost_fill(Geom gf, Mask vm, R *__restrict__ a, R v,
+                                                    const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
   const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
-  const int p[3] = {x, y, z};
-  bool ghost = false;
-  for (int a = 0; a < D; a++) ghost = ghost || p[a] == 0 || p[a] == gf.m[a] - 1;
-  if (!ghost) return;
-  for (int i = 0; i < D; i++) a[i * gf.N + lin(gf, x, y, z)] = v;
+  const long long n = lin(gf, x, y, z);
+  if (vm[n]) return;
+  for (int i = 0; i < D; i++) a[i * gf.N + n] = v;
 }
 
 // Restriction of a fine residual onto the covered coarse nodes: full
 // weighting over the valid fine nodes only, weights renormalised to sum to
-// one where the stencil would reach a ghost node (coarse/fine boundary).
+// one where the stencil would reach a node that is not valid (coarse/fine
+// boundary).  A covered node's fine node is valid, hence off the array's
+// outer ring, so every stencil point lies in the array.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_restrict_cf(Geom gf, Box b, const R *__restrict__ rf, Geom gc, int3 co,
-                                                     R *__restrict__ rc, const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_restrict_cf(Geom gf, Box b, Mask vm, const R *__restrict__ rf, Geom gc,
+                                                     int3 co, R *__restrict__ rc, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   const int cx = b.lo[0] / 2 + blockIdx.x * BX + threadIdx.x;
   const int cy = b.lo[1] / 2 + blockIdx.y * BY + threadIdx.y;
   const int cz = (D == 3 ? b.lo[2] / 2 : 0) + blockIdx.z;
   if (cx > b.hi[0] / 2 || cy > b.hi[1] / 2 || (D == 3 && cz > b.hi[2] / 2)) return;
+  if (!vm[coincident<D>(gf, b, cx, cy, cz)]) return;
   const long long nc = lin(gc, cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0);
   const int f[3] = {2 * cx - b.lo[0] + 1, 2 * cy - b.lo[1] + 1, D == 3 ? 2 * cz - b.lo[2] + 1 : 0};
   R acc[D], wsum = R(0);
@@ -1409,62 +1448,73 @@ __global__ __launch_bounds__(256) void k_restrict_cf(Geom gf, Box b, const R *__
   for (int oz = (D == 3 ? -1 : 0); oz <= (D == 3 ? 1 : 0); oz++)
     for (int oy = -1; oy <= 1; oy++)
       for (int ox = -1; ox <= 1; ox++) {
-        const int q[3] = {f[0] + ox, f[1] + oy, f[2] + oz};
-        bool valid = true;
-        for (int a = 0; a < D; a++) valid = valid && q[a] >= 1 && q[a] <= gf.m[a] - 2;
-        if (!valid) continue;
+        const long long q = lin(gf, f[0] + ox, f[1] + oy, f[2] + oz);
+        if (!vm[q]) continue;
         const R w = (ox ? R(0.25) : R(0.5)) * (oy ? R(0.25) : R(0.5)) * (D == 3 ? (oz ? R(0.25) : R(0.5)) : R(1));
         wsum += w;
-        for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + lin(gf, q[0], q[1], q[2])];
+        for (int i = 0; i < D; i++) acc[i] += w * rf[i * gf.N + q];
       }
   for (int i = 0; i < D; i++) rc[i * gc.N + nc] = acc[i] / wsum;
 }
 
+// Is coarse node (x, y, z) (global) covered by the refined level (b, vm)?
+template <int D>
+__device__ __forceinline__ bool covered_by(const Geom &gf, const Box &b, Mask vm, int x, int y, int z) {
+  if (x < b.lo[0] / 2 || x > b.hi[0] / 2 || y < b.lo[1] / 2 || y > b.hi[1] / 2) return false;
+  if (D == 3 && (z < b.lo[2] / 2 || z > b.hi[2] / 2)) return false;
+  return vm[coincident<D>(gf, b, x, y, z)] != 0;
+}
+
 // Coarse-side effect of a fine correction: the uncovered coarse rows next to
-// the box see the correction through the covered (injected) nodes, so their
-// residual drops by the coarse operator applied to the injected correction.
+// the level see the correction through the covered (injected) nodes, so
+// their residual drops by the coarse operator applied to the injected
+// correction.
 template <int D, int K, typename R>
 struct InjU {
   const R *__restrict__ ef;
   Geom gc, gf;
   int3 co;
   Box b;
+  const unsigned char *__restrict__ vm;
   __device__ __forceinline__ R operator()(int k, long long i) const {
     const int x = int(i % gc.m[0]) + co.x, y = int((i / gc.m[0]) % gc.m[1]) + co.y;
     const int z = D == 3 ? int(i / ((long long)gc.m[0] * gc.m[1])) + co.z : 0;
-    if (x < b.lo[0] / 2 || x > b.hi[0] / 2 || y < b.lo[1] / 2 || y > b.hi[1] / 2) return R(0);
-    if (D == 3 && (z < b.lo[2] / 2 || z > b.hi[2] / 2)) return R(0);
-    return ef[k * gf.N + lin(gf, 2 * x - b.lo[0] + 1, 2 * y - b.lo[1] + 1, D == 3 ? 2 * z - b.lo[2] + 1 : 0)];
+    if (!covered_by<D>(gf, b, vm, x, y, z)) return R(0);
+    return ef[k * gf.N + coincident<D>(gf, b, x, y, z)];
   }
 };
 
+// One thread per coarse node of the covered bounding box grown by one; only
+// uncovered nodes with a row are updated (a node with no covered neighbour
+// gets exactly zero).
 template <int D, int K, typename R>
-__global__ __launch_bounds__(256) void k_cf_update(Geom gc, int3 co, Geom gf, Box b, const R *__restrict__ Cc,
-                                                   const R *__restrict__ ef, R *__restrict__ rc,
-                                                   const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_cf_update(Geom gc, int3 co, Geom gf, Box b, Mask vm,
+                                                   const R *__restrict__ Cc, const R *__restrict__ ef,
+                                                   R *__restrict__ rc, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  // coarse nodes of the covered box grown by one, minus the covered box
   const int cx = b.lo[0] / 2 - 1 + blockIdx.x * BX + threadIdx.x;
   const int cy = b.lo[1] / 2 - 1 + blockIdx.y * BY + threadIdx.y;
   const int cz = (D == 3 ? b.lo[2] / 2 - 1 : 0) + blockIdx.z;
   if (cx > b.hi[0] / 2 + 1 || cy > b.hi[1] / 2 + 1 || (D == 3 && cz > b.hi[2] / 2 + 1)) return;
-  const bool covered = cx >= b.lo[0] / 2 && cx <= b.hi[0] / 2 && cy >= b.lo[1] / 2 && cy <= b.hi[1] / 2 &&
-                       (D == 2 || (cz >= b.lo[2] / 2 && cz <= b.hi[2] / 2));
-  if (covered) return;
+  if (covered_by<D>(gf, b, vm, cx, cy, cz)) return;
   const int p[3] = {cx - co.x, cy - co.y, D == 3 ? cz - co.z : 0};
   const long long n = lin(gc, p[0], p[1], p[2]);
   const int cls = row_class(gc, p);
   if (cls == ROW_DIR) return;
   R acc[D], dg[D];
-  rows_at<D, K, R>(gc, Cc, InjU<D, K, R>{ef, gc, gf, co, b}, n, p, cls, acc, dg);
+  rows_at<D, K, R>(gc, Cc, InjU<D, K, R>{ef, gc, gf, co, b, vm}, n, p, cls, acc, dg);
   for (int i = 0; i < D; i++) rc[i * gc.N + n] -= acc[i];
 }
 
-// Squared 2-norm partials of r over non-Dirichlet rows, excluding the nodes
-// of array box [xlo, xhi] (covered by a finer level; empty if xlo > xhi).
+// Squared 2-norm partials of r over the composite rows of one level: its
+// valid nodes (own_vm; the base grid: non-Dirichlet rows) that the next
+// finer level (child_b, child_vm over child_g; none if child_vm is null)
+// does not cover.  co: global index of the level's array index 0.
 template <int D>
-__global__ __launch_bounds__(256) void k_masked_norm(Geom g, const double *__restrict__ r, int3 xlo, int3 xhi,
-                                                     double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_masked_norm(Geom g, const double *__restrict__ r, const unsigned char *own_vm,
+                                                     int3 co, Geom child_g, Box child_b,
+                                                     const unsigned char *child_vm, double *__restrict__ partial,
+                                                     const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
@@ -1472,10 +1522,12 @@ __global__ __launch_bounds__(256) void k_masked_norm(Geom g, const double *__res
   double s = 0.0;
   if (x < g.m[0] && y < g.m[1]) {
     const int p[3] = {x, y, z};
-    const bool cov = x >= xlo.x && x <= xhi.x && y >= xlo.y && y <= xhi.y && (D == 2 || (z >= xlo.z && z <= xhi.z));
-    if (!cov && row_class(g, p) != ROW_DIR)
+    const long long n = lin(g, x, y, z);
+    const bool own = own_vm ? own_vm[n] != 0 : row_class(g, p) != ROW_DIR;
+    const bool cov = child_vm && covered_by<D>(child_g, child_b, child_vm, x + co.x, y + co.y, z + co.z);
+    if (own && !cov)
       for (int i = 0; i < D; i++) {
-        const double v = r[i * g.N + lin(g, x, y, z)];
+        const double v = r[i * g.N + n];
         s += v * v;
       }
   }

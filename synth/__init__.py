@@ -451,15 +451,93 @@ def _even_ceil(v):
     return int(np.ceil(v / 2.0)) * 2
 
 
+def blocks_from_tags(tagged: np.ndarray, origin, dim: int, parent_valid, parent_origin, domain_m=None,
+                     block: int = 16, max_cells: int = 32, buffer: int = 2):
+    """Boxes of the next finer level covering tagged coarse nodes, the way a
+    block-structured hierarchy is built (Sec. 1): tags grown by `buffer`
+    coarse cells, mapped to fine nodes, covered by blocks of `block` cells
+    on a lattice of `block` cells, merged 2^dim at a time into blocks of
+    `max_cells` (= 2 block) where all of them are selected.  A block is kept
+    only if, grown by two coarse cells, it consists of valid coarse nodes
+    (proper nesting); for the base grid (parent_valid None) it must lie two
+    coarse cells inside the domain of `domain_m` nodes per axis.
+
+    tagged: bool array [z][y][x] over coarse array indices, origin = coarse
+    index of array index 0; parent_valid: bool array of the coarse level's
+    valid nodes (same layout, parent_origin) or None.
+    Returns (lo, hi) boxes of fine node indices, 2D boxes with lo[2] = hi[2] = 0."""
+    idx = np.argwhere(tagged)                      # (z, y, x) rows
+    origin = tuple(int(v) for v in origin)
+    parent_origin = tuple(int(v) for v in parent_origin)
+    if idx.size == 0:
+        return []
+    sel = set()
+    r = range(-buffer, buffer + 1)
+    for z, y, x in idx:
+        J = (x + origin[0], y + origin[1], z + origin[2])
+        for dz in (r if dim == 3 else (0,)):
+            for dy in r:
+                for dx in r:
+                    q = (2 * (J[0] + dx), 2 * (J[1] + dy), 2 * (J[2] + dz) if dim == 3 else 0)
+                    sel.add(tuple(q[a] // block if a < dim else 0 for a in range(3)))
+    def nested(lo, hi):
+        c0 = [lo[a] // 2 - 2 for a in range(dim)]
+        c1 = [hi[a] // 2 + 2 for a in range(dim)]
+        if parent_valid is None:
+            return all(c0[a] >= 0 and c1[a] <= domain_m[a] - 1 for a in range(dim))
+        sl = []
+        for a in (2, 1, 0):
+            if a >= dim:
+                sl.append(slice(None))
+                continue
+            i0, i1 = c0[a] - parent_origin[a], c1[a] - parent_origin[a]
+            if i0 < 0 or i1 >= parent_valid.shape[2 - a]:
+                return False
+            sl.append(slice(i0, i1 + 1))
+        return bool(parent_valid[tuple(sl)].all())
+
+    def box_of(b, size):
+        return (tuple(int(b[a] * size) if a < dim else 0 for a in range(3)),
+                tuple(int((b[a] + 1) * size) if a < dim else 0 for a in range(3)))
+
+    ratio = max_cells // block
+    boxes = []
+    merged = set()
+    for bk in sorted(sel):
+        sup = tuple(bk[a] // ratio if a < dim else 0 for a in range(3))
+        if sup in merged:
+            continue
+        subs = [tuple(sup[a] * ratio + ((o // ratio ** a) % ratio) if a < dim else 0 for a in range(3))
+                for o in range(ratio ** dim)]
+        if all(sb in sel for sb in subs) and nested(*box_of(sup, max_cells)):
+            merged.add(sup)
+            boxes.append(box_of(sup, max_cells))
+    for bk in sorted(sel):
+        sup = tuple(bk[a] // ratio if a < dim else 0 for a in range(3))
+        if sup not in merged and nested(*box_of(bk, block)):
+            boxes.append(box_of(bk, block))
+    return boxes
+
+
+def _bbox(boxes, dim):
+    lo = tuple(min(b[0][a] for b in boxes) if a < dim else 0 for a in range(3))
+    hi = tuple(max(b[1][a] for b in boxes) if a < dim else 0 for a in range(3))
+    return lo, hi
+
+
 def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float = 0.01, floor: float = 1e-4,
-                opening: float = 1e-3, tag: float = 0.1) -> AmrProblem:
+                opening: float = 1e-3, tag: float = 0.1, blocks: bool = True, block: int = 16,
+                max_cells: int = 32) -> AmrProblem:
     """Diffuse penny crack in an isotropic matrix (mu=1, lambda=1.5) on
     [0,1]^3: moduli scaled by 1 - (1 - floor) eta, eta = sech^2(d / width),
     d the distance to the disc (centre (0.5,0.5,0.5), normal z); opening
     displacement +-opening/2 in z on the z faces, x/y faces traction-free.
-    Level k >= 1 is one box: the bounding box of the level-(k-1) nodes where
-    |grad eta| h > tag, grown by two coarse cells, refined, clipped so it
-    nests inside level k-1 with two coarse cells to spare."""
+    Level k >= 1 refines the level-(k-1) nodes where |grad eta| h > tag
+    (Sec. 4.2 tagging on the gradient of the crack field).  blocks=True: the
+    tags (grown by two coarse cells) are covered by blocks of `block` cells
+    on a `block`-cell lattice, merged into `max_cells` blocks where possible
+    (blocks_from_tags); blocks=False: one box, the tags' bounding box grown by
+    two coarse cells, clipped to nest in level k-1."""
     def eta_of(x, y, z):
         rho = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
         d = np.sqrt(np.maximum(rho - radius, 0.0) ** 2 + (z - 0.5) ** 2)
@@ -473,7 +551,7 @@ def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float 
 
     base = Problem(dim=3, n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                    bc=(TRACTION, TRACTION, TRACTION, TRACTION, DIRICHLET, DIRICHLET), kind="iso", C=np.zeros(0),
-                   name=f"penny_{n}_{levels}L")
+                   name=f"penny_{n}_{levels}L" + ("_blocks" if blocks else ""))
 
     def moduli(x, y, z):
         s = 1.0 - (1.0 - floor) * eta_of(x, y, z)
@@ -486,40 +564,67 @@ def penny_crack(n: int = 65, levels: int = 3, radius: float = 0.2, width: float 
         a = np.zeros((3,) + base.face_shape(f))
         a[2] = v
         base.face[f] = a
-    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name, boxlists=[] if blocks else None)
     prev = (tuple([0, 0, 0]), tuple(m - 1 for m in base.m))
     for k in range(1, levels):
         h_prev = amr.level_h(k - 1)[0]
-        lo_p, hi_p = prev
-        idx = [np.arange(lo_p[a], hi_p[a] + 1) for a in range(3)]
+        if k == 1:
+            origin = (0, 0, 0)
+            idx = [np.arange(0, base.m[a]) for a in range(3)]
+            pvalid = None
+        else:
+            plo, phi = amr.boxes[k - 2]
+            origin = tuple(plo[a] - 1 for a in range(3))
+            idx = [np.arange(plo[a] - 1, phi[a] + 2) for a in range(3)]
+            pvalid = amr.valid_mask(k - 1)
         X = base.lo[0] + h_prev * idx[0][None, None, :]
         Y = base.lo[1] + h_prev * idx[1][None, :, None]
         Z = base.lo[2] + h_prev * idx[2][:, None, None]
         tagged = grad_eta(X, Y, Z, h_prev) * h_prev > tag
+        if pvalid is not None:
+            tagged &= pvalid
         if not tagged.any():
             break
-        zz, yy, xx = np.nonzero(tagged)
-        t_lo = [idx[0][xx.min()], idx[1][yy.min()], idx[2][zz.min()]]
-        t_hi = [idx[0][xx.max()], idx[1][yy.max()], idx[2][zz.max()]]
-        lo, hi = [], []
-        for a in range(3):
-            # tagged bounding box grown by two coarse cells, refined
-            l_f = _even_floor(2 * (t_lo[a] - 2))
-            h_f = _even_ceil(2 * (t_hi[a] + 2))
-            l_f = max(l_f, 2 * (lo_p[a] + 2))
-            h_f = min(h_f, 2 * (hi_p[a] - 2))
-            lo.append(l_f)
-            hi.append(h_f)
-        amr.boxes.append((tuple(lo), tuple(hi)))
+        if blocks:
+            bl = blocks_from_tags(tagged, origin, 3, pvalid, origin, base.m, block, max_cells)
+            if not bl:
+                break
+            amr.boxlists.append(bl)
+            amr.boxes.append(_bbox(bl, 3))
+        else:
+            zz, yy, xx = np.nonzero(tagged)
+            t_lo = [idx[0][xx.min()], idx[1][yy.min()], idx[2][zz.min()]]
+            t_hi = [idx[0][xx.max()], idx[1][yy.max()], idx[2][zz.max()]]
+            lo_p, hi_p = prev
+            lo, hi = [], []
+            for a in range(3):
+                # tagged bounding box grown by two coarse cells, refined
+                l_f = _even_floor(2 * (t_lo[a] - 2))
+                h_f = _even_ceil(2 * (t_hi[a] + 2))
+                l_f = max(l_f, 2 * (lo_p[a] + 2))
+                h_f = min(h_f, 2 * (hi_p[a] - 2))
+                lo.append(l_f)
+                hi.append(h_f)
+            amr.boxes.append((tuple(lo), tuple(hi)))
+            prev = (tuple(lo), tuple(hi))
         Xf, Yf, Zf = amr.box_coords(k)
-        amr.C.append(moduli(Xf, Yf, Zf))
+        amr.C.append(np.ascontiguousarray(moduli(Xf, Yf, Zf)))
         amr.eps0.append(None)
         amr.b.append(None)
-        prev = (tuple(lo), tuple(hi))
     return amr
 
 
-def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2, kind: str = "iso") -> AmrProblem:
+# L-shaped refined levels of smooth_amr(..., shape="L") for a 17-node base:
+# level 1 is two boxes meeting along y = 14, level 2 two boxes meeting along
+# y = 24 (each box grown by two coarse cells lies in the level above).
+L_SHAPE_BOXES = {
+    1: [((6, 6, 6), (26, 14, 26)), ((6, 14, 6), (14, 26, 26))],
+    2: [((16, 16, 16), (48, 24, 48)), ((16, 24, 16), (24, 48, 48))],
+}
+
+
+def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2, kind: str = "iso",
+               shape: str = "box") -> AmrProblem:
     """Small composite test problem: smooth moduli (analytic, sampled on
     every level), body force, mixed Dirichlet/traction faces, and centred
     nested boxes (each half the previous box's width).  kind "iso": (lambda,
@@ -560,9 +665,24 @@ def smooth_amr(dim: int = 2, levels: int = 2, n: int = 17, seed: int = 2, kind: 
     nc = 2 if kind == "iso" else len(lu)
     base.C = np.ascontiguousarray(np.broadcast_to(fields(x, y, z), (nc,) + shp))
     base.b = np.ascontiguousarray(np.broadcast_to(body(x, y, z), (dim,) + shp))
-    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name)
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name,
+                     boxlists=[] if shape == "L" else None)
+    if shape == "L":
+        assert n == 17 and levels <= 3
+        amr.name += "_L"
     lo_p, hi_p = [0] * 3, [m - 1 for m in base.m]
     for lev in range(1, levels):
+        if shape == "L":
+            bl = [(tuple(lo[a] if a < dim else 0 for a in range(3)), tuple(hi[a] if a < dim else 0 for a in range(3)))
+                  for lo, hi in L_SHAPE_BOXES[lev]]
+            amr.boxlists.append(bl)
+            amr.boxes.append(_bbox(bl, dim))
+            X, Y, Z = amr.box_coords(lev)
+            mshape = tuple(len(v.ravel()) for v in (Z, Y, X))
+            amr.C.append(np.ascontiguousarray(np.broadcast_to(fields(X, Y, Z), (nc,) + mshape)))
+            amr.eps0.append(None)
+            amr.b.append(np.ascontiguousarray(np.broadcast_to(body(X, Y, Z), (dim,) + mshape)))
+            continue
         lo, hi = [0, 0, 0], [0, 0, 0]
         for a in range(dim):
             span = hi_p[a] - lo_p[a]
@@ -628,6 +748,116 @@ def eshelby_amr_2d(n0: int = 129, levels: int = 3, radius: float = 0.1, width_ce
         amr.eps0.append(np.ascontiguousarray(np.broadcast_to(ek, (3,) + mshape)).astype(np.float64))
         amr.b.append(None)
     return amr
+
+
+class Microstructure2D:
+    """2D polycrystal of the AMR performance study (Sec. 5.1 "AMR
+    performance", phase-field microstructure case): `grains` Voronoi grains
+    in [0,1]^2 (seeds U[0,1]^2 from default_rng(seed)), each a cubic crystal
+    (C11=1.68, C12=1.21, C44=0.75) rotated about z by a uniform angle, plane
+    strain.  Order parameters eta_n = g_n / sum g, g_n = tanh step of the
+    distance to the bisector between the node's nearest seed and seed n,
+    diffuse over `width` (physical); moduli C = sum eta_n C_n (mixture rule,
+    Sec. 4.3).  Evaluated at any points."""
+
+    def __init__(self, grains: int = 10, seed: int = 2010, width: float = 0.01):
+        rng = np.random.default_rng(seed)
+        self.centers = rng.random((grains, 2))
+        th = 2.0 * np.pi * rng.random(grains)
+        cub = cubic_voigt(*CUBIC)
+        Cs = []
+        for t in th:
+            R = np.array([[np.cos(t), -np.sin(t), 0.0], [np.sin(t), np.cos(t), 0.0], [0.0, 0.0, 1.0]])
+            Cs.append(upper_tri(plane_strain_voigt(rotate_voigt(cub, R))))
+        self.grainC = np.stack(Cs)          # [G][6]
+        self.width = width
+
+    def eta(self, x, y):
+        """Order parameters [G][...] at points (x, y) (broadcast arrays)."""
+        x, y = np.broadcast_arrays(x, y)
+        cx = self.centers[:, 0].reshape((-1,) + (1,) * x.ndim)
+        cy = self.centers[:, 1].reshape((-1,) + (1,) * x.ndim)
+        dx, dy = x[None] - cx, y[None] - cy
+        d2 = dx * dx + dy * dy
+        a = np.argmin(d2, axis=0)
+        d2a = np.take_along_axis(d2, a[None], 0)[0]
+        pax, pay = self.centers[a, 0], self.centers[a, 1]
+        sep = np.sqrt((cx - pax[None]) ** 2 + (cy - pay[None]) ** 2)
+        delta = np.where(sep > 0, (d2 - d2a[None]) / (2.0 * np.maximum(sep, 1e-300)), -np.inf)
+        g = _tanh_step(delta / (0.5 * self.width))
+        return g / g.sum(axis=0, keepdims=True)
+
+    def moduli(self, x, y):
+        e = self.eta(x, y)
+        return np.einsum("g...,gc->c...", e, self.grainC)
+
+    def tags(self, x, y, h, tag=0.1):
+        """|grad eta_n| h > tag for some n (central differences of width h)."""
+        gx = (self.eta(x + h, y) - self.eta(x - h, y)) / (2 * h)
+        gy = (self.eta(x, y + h) - self.eta(x, y - h)) / (2 * h)
+        return (np.sqrt(gx * gx + gy * gy) * h > tag).any(axis=0)
+
+
+def _microstructure_base(n0, ms, shear, name):
+    base = Problem(dim=2, n=(n0, n0, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+                   bc=(TRACTION, TRACTION, DIRICHLET, DIRICHLET, PERIODIC, PERIODIC), kind="aniso", C=np.zeros(0),
+                   name=name)
+    x, y, _ = base.coords()
+    base.C = np.ascontiguousarray(ms.moduli(np.broadcast_to(x, (1, n0, n0)), np.broadcast_to(y, (1, n0, n0))))
+    top = np.zeros((2,) + base.face_shape(3))
+    top[0] = shear
+    base.face[3] = top
+    return base
+
+
+def microstructure_amr_2d(n_finest: int = 513, levels: int = 3, grains: int = 10, seed: int = 2010,
+                          width_cells: float = 4.0, shear: float = 1e-3, tag: float = 0.1) -> AmrProblem:
+    """The AMR performance study's microstructure case at a fixed finest
+    resolution: base grid of (n_finest - 1) / 2^(levels-1) + 1 nodes per axis,
+    levels - 1 refined levels of 16/32-cell blocks covering the nodes where
+    some |grad eta_n| |dx| > tag (Sec. 4.3 tagging criterion), grown by two
+    cells and properly nested.  Diffuse width `width_cells` finest cells.
+    Bottom clamped, top sheared by `shear` in x, sides traction-free."""
+    nf = n_finest - 1
+    n0 = nf // 2 ** (levels - 1) + 1
+    assert (n0 - 1) * 2 ** (levels - 1) == nf
+    ms = Microstructure2D(grains, seed, width_cells / nf)
+    base = _microstructure_base(n0, ms, shear, f"microstructure_amr_{n_finest}_{levels}L")
+    amr = AmrProblem(base=base, boxes=[], C=[], eps0=[], b=[], name=base.name, boxlists=[])
+    for k in range(1, levels):
+        h_prev = amr.level_h(k - 1)[0]
+        if k == 1:
+            origin = (0, 0, 0)
+            idx = [np.arange(0, base.m[a]) for a in range(2)]
+            pvalid = None
+        else:
+            plo, phi = amr.boxes[k - 2]
+            origin = (plo[0] - 1, plo[1] - 1, 0)
+            idx = [np.arange(plo[a] - 1, phi[a] + 2) for a in range(2)]
+            pvalid = amr.valid_mask(k - 1)
+        X = (h_prev * idx[0])[None, None, :]
+        Y = (h_prev * idx[1])[None, :, None]
+        tagged = ms.tags(X, Y, h_prev, tag)
+        if pvalid is not None:
+            tagged &= pvalid
+        bl = blocks_from_tags(tagged, origin, 2, pvalid, origin, base.m) if tagged.any() else []
+        if not bl:
+            break
+        amr.boxlists.append(bl)
+        amr.boxes.append(_bbox(bl, 2))
+        Xk, Yk, _ = amr.box_coords(k)
+        shp = (1, Yk.size, Xk.size)
+        amr.C.append(np.ascontiguousarray(ms.moduli(np.broadcast_to(Xk, shp), np.broadcast_to(Yk, shp))))
+        amr.eps0.append(None)
+        amr.b.append(None)
+    return amr
+
+
+def microstructure_uniform_2d(n_finest: int = 513, grains: int = 10, seed: int = 2010, width_cells: float = 4.0,
+                              shear: float = 1e-3) -> Problem:
+    """The same microstructure on one uniform grid of n_finest nodes per axis."""
+    ms = Microstructure2D(grains, seed, width_cells / (n_finest - 1))
+    return _microstructure_base(n_finest, ms, shear, f"microstructure_uniform_{n_finest}")
 
 
 def eshelby_uniform_2d(n0: int = 129, levels: int = 3, **kw) -> Problem:

@@ -148,7 +148,7 @@ int main(void) {
   double *u = (double *)malloc(sizeof(double) * 3 * m[0] * m[1] * m[2]);
   double *sig = (double *)malloc(sizeof(double) * 6 * m[0] * m[1] * m[2]);
   CHECK(emg_get_displacement(p, u, 0), EMG_OK);
-  CHECK(emg_get_stress(p, sig, 0), EMG_OK);
+  CHECK(emg_get_stress(p, 0, sig, 0), EMG_OK);
   CHECK(emg_get_von_mises(p, sig, 0), EMG_OK);
   free(u);
   free(sig);
@@ -166,10 +166,18 @@ int main(void) {
   /* AMR: base 33^3 non-periodic, two nested boxes, FP64 and mixed */
   emg_domain da = domain(3, 33, EMG_MOD_ISO, 0);
   emg_problem *pa = make_problem(ctx, &da);
-  const int64_t lo1[3] = {16, 16, 16}, hi1[3] = {48, 48, 48};
+  /* level 1 as two boxes meeting at y = 32 (their union is one box), level 2 one box */
+  const emg_box b1[2] = {{{16, 16, 16}, {48, 32, 48}}, {{16, 32, 16}, {48, 48, 48}}};
   const int64_t lo2[3] = {48, 48, 48}, hi2[3] = {80, 80, 80};
-  CHECK(emg_amr_add_level(pa, lo1, hi1), EMG_OK);
+  CHECK(emg_set_level_boxes(pa, 2, b1, 2), EMG_ESTATE);   /* levels are added in order */
+  CHECK(emg_set_level_boxes(pa, 1, b1, 2), EMG_OK);
   CHECK(emg_amr_add_level(pa, lo2, hi2), EMG_OK);
+  int64_t nvalid = 0;
+  CHECK(emg_amr_level_valid(pa, 1, NULL, &nvalid), EMG_OK);
+  if (nvalid != 33LL * 33 * 33) {
+    fprintf(stderr, "FAIL: level 1 has %lld valid nodes\n", (long long)nvalid);
+    failures++;
+  }
   for (int k = 1; k <= 2; k++) {
     int64_t bm[3];
     CHECK(emg_amr_level_shape(pa, k, bm), EMG_OK);
@@ -182,6 +190,14 @@ int main(void) {
   CHECK(emg_solve(pa, &o, &st), EMG_OK);
   o.precision = EMG_MIXED;
   CHECK(emg_solve(pa, &o, &st), EMG_OK);
+  for (int k = 0; k <= 2; k++) {   /* stress on the base grid and on both refined levels */
+    int64_t sm[3] = {33, 33, 33};
+    if (k) CHECK(emg_amr_level_shape(pa, k, sm), EMG_OK);
+    double *sk = (double *)malloc(sizeof(double) * 6 * sm[0] * sm[1] * sm[2]);
+    CHECK(emg_get_stress(pa, k, sk, 0), EMG_OK);
+    free(sk);
+  }
+  CHECK(emg_get_stress(pa, 3, sig, 0), EMG_EINVAL);
   CHECK(emg_problem_destroy(pa), EMG_OK);
 
   /* server: 12 requests of two sizes through 3 slots */

@@ -29,7 +29,10 @@ def ctx(emg):
 
 CASES = {"2d_2L": (2, 2, 17), "2d_3L": (2, 3, 17), "3d_2L": (3, 2, 9), "3d_2L_17": (3, 2, 17),
          # anisotropic moduli (21 / 6 stored constants) on every level
-         "2d_3L_aniso": (2, 3, 33, 5, "aniso"), "3d_2L_aniso": (3, 2, 17, 5, "aniso")}
+         "2d_3L_aniso": (2, 3, 33, 5, "aniso"), "3d_2L_aniso": (3, 2, 17, 5, "aniso"),
+         # two boxes per refined level (L-shaped unions with reentrant corners)
+         "2d_3L_Lshape": (2, 3, 17, 2, "iso", "L"), "3d_3L_Lshape": (3, 3, 17, 2, "iso", "L"),
+         "3d_3L_Lshape_aniso": (3, 3, 17, 2, "aniso", "L")}
 
 
 def _state(prob, comp, u):
@@ -122,7 +125,7 @@ def test_penny_crack_three_levels(emg, ctx):
     FP64 and mixed precision: each GPU solution satisfies the oracle's
     composite system to 1e-10, and the two agree to 1e-8."""
     ap = synth.penny_crack(n=33, levels=3, floor=1e-2, width=0.05)
-    print(f"[gpu] penny crack 33^3 boxes={ap.boxes}", flush=True)
+    print(f"[gpu] penny crack 33^3, boxes per level {[len(ap.level_boxes(k)) for k in (1, 2)]}", flush=True)
     comp = amr.from_problem(ap)
     r0 = comp.norm(comp.residual(comp.initial()))
     sols = {}
@@ -153,18 +156,59 @@ def test_amr_rejects_bad_boxes(emg, ctx):
     prob.amr_add_level((8, 8, 0), (24, 24, 0))
     st = prob.solve(raise_on_error=False)
     assert st["status"] == emg.EMG_ESTATE          # refined level without moduli
+    with pytest.raises(emg.EmgError) as ei:        # levels are added in order
+        prob.set_level_boxes(3, [((20, 20, 0), (28, 28, 0))])
+    assert ei.value.status == emg.EMG_ESTATE
+    prob.close()
+    # several boxes: a level-2 box reaching into the notch of an L-shaped level 1
+    prob = emg.Problem.from_spec(ctx, ap.base)
+    prob.set_level_boxes(1, [((8, 8, 0), (24, 16, 0)), ((8, 16, 0), (16, 24, 0))])
+    mask, nvalid = prob.amr_level_valid(1)
+    assert nvalid == 17 * 9 + 9 * 9 - 9 and int(mask.sum()) == nvalid
+    with pytest.raises(emg.EmgError) as ei:
+        prob.set_level_boxes(2, [((24, 24, 0), (36, 36, 0))])
+    assert ei.value.status == emg.EMG_EINVAL
+    prob.set_level_boxes(2, [((20, 20, 0), (28, 28, 0)), ((36, 20, 0), (44, 28, 0))])
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["3d_2L_aniso", "3d_3L_Lshape_aniso", "2d_3L_Lshape"])
+def test_stress_on_refined_levels(emg, ctx, name):
+    """emg_get_stress on every level: from the oracle's composite solution
+    (set on every level, ghosts included) the GPU stress equals
+    oracle.stress on the level's array at every valid node (1e-12); after a
+    GPU solve, within 1e-7 of it."""
+    ap, comp, uref, _ = _reference(name)
+    d = ap.base.dim
+    prob = emg.Problem.from_amr(ctx, ap)
+    prob.solve(rtol=1e-10, max_cycles=300)
+    after = [prob.stress(level=k) for k in range(len(uref))]
+    _state(prob, comp, uref)
+    print(f"[gpu] stress on refined levels {name}", flush=True)
+    for k in range(len(uref)):
+        g = comp.grid(k)
+        E = comp.E0 if k == 0 else comp.fines[k - 1].eps0
+        ref = oracle.stress(g, comp.C(k), E, uref[k])
+        got = prob.stress(level=k)
+        v = np.ones(ref.shape[1:], dtype=bool) if k == 0 else comp.fines[k - 1].valid_mask
+        scale = np.abs(ref[:, v]).max()
+        assert np.abs(got[:, v] - ref[:, v]).max() <= 1e-12 * scale, k
+        assert np.abs(after[k][:, v] - ref[:, v]).max() <= 1e-7 * scale, k
     prob.close()
 
 
 @pytest.mark.parametrize("base", ["V", "F"])
-@pytest.mark.parametrize("case", [(2, 3, 65, 4), (3, 2, 17, 2), (3, 2, 17, 5, "aniso")])
+@pytest.mark.parametrize("case", [(2, 3, 65, 4), (3, 2, 17, 2), (3, 2, 17, 5, "aniso"), (2, 3, 17, 2, "iso", "L"),
+                                  (3, 3, 17, 2, "aniso", "L")])
 def test_composite_cycle_iterates_match_oracle(emg, ctx, case, base):
     """Element by element: after 1, 2 and 5 composite cycles from the
     initial state, the GPU's composite unknowns (valid fine nodes, uncovered
     coarse nodes) equal the oracle's composite cycle iterates (base grid
-    corrected by a V- or an F-cycle)."""
+    corrected by a V- or an F-cycle; one box per level, or two boxes per
+    level forming an L)."""
     dim, levels, n, seed = case[:4]
-    ap = synth.smooth_amr(dim=dim, levels=levels, n=n, seed=seed, kind=case[4] if len(case) > 4 else "iso")
+    ap = synth.smooth_amr(dim=dim, levels=levels, n=n, seed=seed, kind=case[4] if len(case) > 4 else "iso",
+                          shape=case[5] if len(case) > 5 else "box")
     comp = amr.from_problem(ap)
     masks = comp.unknown_masks()
     u = comp.initial()

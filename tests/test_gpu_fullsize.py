@@ -121,12 +121,15 @@ def test_polycrystal257_sphere_solves_full_size(emg, ctx):
 
 
 def test_penny_crack_amr_65_full_size(emg, ctx):
-    """Penny crack, 65^3 base, three levels, FP64 and mixed precision: each
-    GPU composite solution satisfies the oracle's composite system to
+    """The penny crack as benchmarked: 65^3 base, three levels of 16/32-cell
+    blocks (40 and 80 boxes) tagged where |grad eta| h > 0.1, diffuse width
+    0.01, moduli capped at 1 % inside the crack; FP64 and mixed precision:
+    each GPU composite solution satisfies the oracle's composite system to
     1.2e-10; the mixed solution's error against the FP64 one is reported and
     held to 1e-8."""
-    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.05)
-    print(f"[gpu] penny crack, 65^3 base: boxes={ap.boxes}", flush=True)
+    ap = synth.penny_crack(n=65, levels=3, floor=1e-2, width=0.01)
+    assert [len(ap.level_boxes(k)) for k in (1, 2)] == [40, 80]
+    print(f"[gpu] penny crack, 65^3 base: {ap.composite_nodes()} composite nodes", flush=True)
     comp = amr.from_problem(ap)
     r0 = comp.norm(comp.residual(comp.initial()))
     sols = {}
