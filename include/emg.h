@@ -361,36 +361,53 @@ emg_status emg_amr_residual(emg_problem *p, int level, double *r_dev, double *no
  * problem's stream: `reps` back-to-back launches in the launch configuration
  * the solve uses are captured into one HIP graph (as the solve's cycles are),
  * replayed once untimed and once between two HIP events.  kernel: 0 = Jacobi
- * sweep, 1 = residual with full-weighting restriction, 2 = interpolation.
+ * sweep, 1 = residual, 2 = interpolation from level+1 onto the level with the
+ * correction added, 3 = full-weighting restriction from the level to level+1
+ * (fused with level+1's zero-start sweep where the cycle fuses them).
  * EMG_EINVAL for reps < 1, an unknown kernel or a missing coarser level. */
 emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms);
 
 /* ---- autotuner ----
- * Picks, by measurement instead of the cost model, how the Jacobi sweep and
- * residual of Sec. 3.1 are launched on each level; the operation itself is
- * unchanged (a launch configuration, not a step of the method).  For every
- * multigrid level of a 3D anisotropic problem wide enough for the
- * z-marching pass (at least 64 x 4 interior nodes per plane and 8 planes),
- * times the Jacobi sweep in `precision` (EMG_FP64: FP64 passes, EMG_MIXED:
- * the FP32 ones) with the tile kernel and with the z-marching pass at every
- * chunk count leaving at least 8 planes per chunk, each as `reps` launches
- * captured into a graph (best of two replays), and records the fastest in a
- * process-wide table keyed by device architecture, precision, level extents
- * and periodic axes.  Every later plan of any problem with such a level
- * (solves, batches, servers) takes the recorded choice; emg_level_zmarch
- * reports it.  All variants compute bit-identical results, so tuning changes
- * timing only.  Levels already in the table are skipped unless `retune` is
- * nonzero.  The problem's recorded solve graphs are dropped (re-recorded at
- * the next solve); graphs of servers already running keep their plans.
- * If the environment variable EMG_TUNE_CACHE names a file, the table is
- * read from it at first use and rewritten after each call that measured a
- * level: a JSON object of "arch/fp64|fp32/m0xm1xm2/p<mask>" -> chunks per
- * column (0 = tile kernel; mask bit a set for a periodic axis a); entries
- * out of range for their level are ignored.  *tuned (optional) receives the
- * number of levels measured (0 for 2D or isotropic problems, which have one
- * variant).  EMG_EINVAL for reps outside 1..1000 or when the cache file
- * cannot be written (the table itself is updated). */
+ * Picks, by measurement instead of the cost model, how the steps of the
+ * cycle of Sec. 3.1 are launched on each level; the operations themselves are
+ * unchanged (launch configurations, not steps of the method).  For every
+ * multigrid level, in `precision` (EMG_FP64: FP64 passes, EMG_MIXED: the FP32
+ * ones): the Jacobi sweep with the tile kernel in tiles of 64 x 4, 64 x 2,
+ * 128 x 2 and 32 x 8 nodes and, on 3D anisotropic levels wide enough (at least
+ * 64 x 4 interior nodes per plane and 8 planes), with the z-marching pass at
+ * every chunk count leaving at least 8 planes per chunk; and, on levels with a
+ * coarser one, the restriction from the level and the interpolation onto it in
+ * the same four tile shapes.  Each variant is timed as `reps` launches
+ * captured into a graph (best of two replays), and the fastest of each kind is
+ * recorded in a process-wide table keyed by device architecture, precision,
+ * level extents, periodic axes and moduli kind.  Every later plan of any
+ * problem with such a level takes the recorded choices (emg_solve; batched
+ * and served solves take the z-marching choice and keep 64 x 4 tiles);
+ * emg_level_zmarch and emg_level_tiles report them.  All variants compute the
+ * same values node by node; the norm partials of a level-0 sweep are summed
+ * per tile, so a different tile shape can change the convergence test's
+ * last bits (never the iterates).  Levels already in the table are skipped
+ * unless `retune` is nonzero.  The problem's recorded solve graphs are
+ * dropped (re-recorded at the next solve); graphs of servers already running
+ * keep their plans.  If the environment variable EMG_TUNE_CACHE names a file,
+ * the table is read from it at first use and rewritten after each call that
+ * measured a level: a JSON object of
+ * "arch/fp64|fp32/m0xm1xm2/p<mask>[/iso][/r|/i]" -> value, mask bit a set for
+ * a periodic axis a; for the stencil pass the value is the chunks per column
+ * of the z-marching pass (> 0), 0 for the tile kernel in 64 x 4 tiles, or
+ * -1, -2, -3 for the tile kernel in 64 x 2, 128 x 2, 32 x 8 tiles; for the
+ * restriction ("/r") and interpolation ("/i") it is the tile shape 0..3 in
+ * that order; entries out of range for their level are ignored.  *tuned
+ * (optional) receives the number of levels measured.  EMG_EINVAL for reps
+ * outside 1..1000 or when the cache file cannot be written (the table itself
+ * is updated). */
 emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int *tuned);
+/* Launch shapes a level uses in `precision`: tile shape of the tile kernel
+ * (0 = 64 x 4, 1 = 64 x 2, 2 = 128 x 2, 3 = 32 x 8; 0 when the level runs the
+ * z-marching pass), of the restriction from the level and of the
+ * interpolation onto it (-1 on the coarsest level).  Outputs may be NULL. */
+emg_status emg_level_tiles(emg_problem *p, int level, int precision, int *stencil, int *restriction,
+                           int *interpolation);
 /* Empties the process-wide table; the EMG_TUNE_CACHE file, if any, is read
  * again at the next lookup. */
 emg_status emg_autotune_reset(void);

@@ -109,6 +109,7 @@ _SIGS = {
     "emg_server_now": ([c_void_p, P(c_double)], c_int),
     "emg_server_destroy": ([c_void_p], c_int),
     "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
+    "emg_level_tiles": ([c_void_p, c_int, c_int, P(c_int), P(c_int), P(c_int)], c_int),
     "emg_set_level_boxes": ([c_void_p, c_int, c_void_p, c_int], c_int),
     "emg_amr_level_valid": ([c_void_p, c_int, c_void_p, P(c_int64)], c_int),
     "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
@@ -434,6 +435,14 @@ class Problem:
         c = c_int()
         check(lib.emg_level_zmarch(self.handle, level, _PREC[precision], ctypes.byref(c)), "emg_level_zmarch")
         return c.value
+
+    def level_tiles(self, level: int = 0, precision="fp64"):
+        """(stencil, restriction, interpolation) tile shapes of a level:
+        0 = 64x4, 1 = 64x2, 2 = 128x2, 3 = 32x8 (-1: none)."""
+        a, b, c = c_int(), c_int(), c_int()
+        check(lib.emg_level_tiles(self.handle, level, _PREC[precision], ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(c)), "emg_level_tiles")
+        return a.value, b.value, c.value
 
     def num_levels(self) -> int:
         n = c_int()

@@ -138,7 +138,11 @@ struct emg_problem {
   double *sig = nullptr, *svm = nullptr;   // stress (Voigt) and von Mises output buffers
   hipStream_t own = nullptr, stream = nullptr;
   bool moduli_set = false, setup_done = false, mixed_ready = false, rhs_ready = false;
-  int force_nzc = -1;   // >= 0: stencil-pass variant under measurement by emg_autotune
+  // launch variants under measurement by emg_autotune (-1: none): stencil
+  // pass (z-march chunks > 0, tile kernel 0, other tile shapes -shape),
+  // restriction and interpolation tile shapes
+  bool force_stencil = false;
+  int force_v = 0, force_rs = -1, force_ps = -1;
   int inner = 1;        // FP32 cycles per mixed refinement step (set by emg_solve for its duration)
   std::vector<void *> allocs;
   size_t bytes = 0;
@@ -250,12 +254,15 @@ const std::string &tune_arch_locked(TuneTable &t, int device) {
   return it->second;
 }
 
-// Key of a 3D anisotropic level; caller holds the table's lock.
-std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g) {
+// Key of a level; caller holds the table's lock.  what: "" for the stencil
+// pass, "/r" for the restriction from the level, "/i" for the interpolation
+// onto it; isotropic levels carry "/iso".
+std::string tune_key_locked(TuneTable &t, int device, int rbytes, const Geom &g, int kind = MOD_ANISO,
+                            const char *what = "") {
   const std::string &arch = tune_arch_locked(t, device);
-  char buf[160];
-  snprintf(buf, sizeof buf, "%s/%s/%dx%dx%d/p%d", arch.c_str(), rbytes == 8 ? "fp64" : "fp32", g.m[0], g.m[1],
-           g.m[2], g.per[0] | (g.per[1] << 1) | (g.per[2] << 2));
+  char buf[192];
+  snprintf(buf, sizeof buf, "%s/%s/%dx%dx%d/p%d%s%s", arch.c_str(), rbytes == 8 ? "fp64" : "fp32", g.m[0], g.m[1],
+           g.m[2], g.per[0] | (g.per[1] << 1) | (g.per[2] << 2), kind == MOD_ISO ? "/iso" : "", what);
   return buf;
 }
 
@@ -285,7 +292,7 @@ void tune_load_locked(TuneTable &t) {
       const char *a = s.c_str() + k + 1;
       char *end = nullptr;
       const long v = strtol(a, &end, 10);
-      if (end != a && v >= 0 && v <= 4096) t.table[key] = (int)v;
+      if (end != a && v >= -(TS_COUNT - 1) && v <= 4096) t.table[key] = (int)v;
     }
   }
 }
@@ -307,21 +314,25 @@ bool tune_save_locked(const TuneTable &t) {
   return ok && rename(tmp.c_str(), path) == 0;
 }
 
-// The z-marching pass needs a workgroup row of interior nodes (64 x 4 tiles
-// fully inside the level in x and y) and at least 8 planes per chunk; a table
-// value outside that range is ignored.
-bool zm_valid(const Geom &g, int nzc) {
+// Stencil-pass variants: the z-marching pass needs a workgroup row of
+// interior nodes (64 x 4 tiles fully inside the level in x and y) and at
+// least 8 planes per chunk; tile shapes -1..-3; a table value outside that
+// range is ignored.
+bool zm_valid(const Geom &g, int nzc, int kind = MOD_ANISO) {
   const Split sp = split_of(g);
-  if (nzc == 0) return true;
-  return g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 && nzc <= sp.ntz / 8;
+  if (nzc <= 0) return nzc > -TS_COUNT;
+  return kind == MOD_ANISO && g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 &&
+         nzc <= sp.ntz / 8;
 }
 
-bool tune_find(int device, int rbytes, const Geom &g, int *nzc) {
+bool tune_find(int device, int rbytes, const Geom &g, int *nzc, int kind = MOD_ANISO, const char *what = "") {
   TuneTable &t = tune_table();
   std::lock_guard<std::mutex> lk(t.mu);
   tune_load_locked(t);
-  auto it = t.table.find(tune_key_locked(t, device, rbytes, g));
-  if (it == t.table.end() || !zm_valid(g, it->second)) return false;
+  auto it = t.table.find(tune_key_locked(t, device, rbytes, g, kind, what));
+  if (it == t.table.end()) return false;
+  const bool ok = *what ? (it->second >= 0 && it->second < TS_COUNT) : zm_valid(g, it->second, kind);
+  if (!ok) return false;
   *nzc = it->second;
   return true;
 }
@@ -331,17 +342,58 @@ bool tune_find(int device, int rbytes, const Geom &g, int *nzc) {
 // which takes 3D anisotropic levels with enough columns x chunks of >= 8
 // planes to give every CU a workgroup (FP64: one per CU, FP32: two); smaller
 // levels keep the tile kernel, which spreads them over more workgroups.
+// The stencil-pass variant of a level: > 0 z-march chunks, 0 the tile
+// kernel in 64 x 4 tiles, < 0 the tile kernel in tile shape -v.
 template <typename R>
-int zm_plan(const emg_problem *p, const Geom &g) {
-  if (p->D != 3 || p->K != MOD_ANISO) return 0;
-  if (p->force_nzc >= 0) return p->force_nzc;
+int stencil_plan(const emg_problem *p, const Geom &g) {
+  if (p->force_stencil) return p->force_v;
   int tuned;
-  if (tune_find(p->ctx->device, (int)sizeof(R), g, &tuned)) return tuned;
+  if (tune_find(p->ctx->device, (int)sizeof(R), g, &tuned, p->K)) return tuned;
+  if (p->D != 3 || p->K != MOD_ANISO) return 0;
   const int target = sizeof(R) == 8 ? 256 : 512;
   const int nzc = zm_chunks(g, target);
   if (nzc == 0) return 0;
   const Split sp = split_of(g);
   return (long long)sp.ntx * sp.nty * nzc >= target / 2 ? nzc : 0;
+}
+template <typename R>
+int zm_plan(const emg_problem *p, const Geom &g) {
+  return std::max(0, stencil_plan<R>(p, g));
+}
+// Tile shape of a stencil pass on the tile kernel (TS_64x4 when z-marched).
+template <typename R>
+int tile_plan(const emg_problem *p, const Geom &g) {
+  return std::max(0, -stencil_plan<R>(p, g));
+}
+// Norm-partial slots of the first sweep of a level: the tile kernel's blocks
+// in its tile shape (the z-marching pass fills the 64 x 4 slots).
+template <typename R>
+long long plan_blocks(const emg_problem *p, const Geom &g) {
+  return split_shape(g, tile_plan<R>(p, g)).blocks;
+}
+// Tile shape of the restriction from a level (what "/r") or of the
+// interpolation onto it ("/i").
+template <typename R>
+int xfer_plan(const emg_problem *p, const Geom &g, bool restriction) {
+  const int forced = restriction ? p->force_rs : p->force_ps;
+  if (forced >= 0) return forced;
+  int tuned;
+  if (tune_find(p->ctx->device, (int)sizeof(R), g, &tuned, p->K, restriction ? "/r" : "/i")) return tuned;
+  return TS_64x4;
+}
+dim3 grid_shape(const Geom &g, int s) {
+  return dim3((g.m[0] + ts_x(s) - 1) / ts_x(s), (g.m[1] + ts_y(s) - 1) / ts_y(s), g.m[2]);
+}
+dim3 block_shape(int s) { return dim3(ts_x(s), ts_y(s), 1); }
+// Calls f(integral_constant<TX>, integral_constant<TY>) for tile shape s.
+template <class F>
+void dispatch_shape(int s, F &&f) {
+  switch (s) {
+    case TS_64x2: f(std::integral_constant<int, 64>{}, std::integral_constant<int, 2>{}); break;
+    case TS_128x2: f(std::integral_constant<int, 128>{}, std::integral_constant<int, 2>{}); break;
+    case TS_32x8: f(std::integral_constant<int, 32>{}, std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 64>{}, std::integral_constant<int, 4>{}); break;
+  }
 }
 
 template <typename R, int MODE, typename TO>
@@ -365,10 +417,19 @@ void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *
                        omega, partial, ctl, nzc);
     return;
   }
+  const int ts = MODE == MODE_APPLY ? TS_64x4 : tile_plan<R>(p, L.g);
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0, p->stream, L.g,
-                       moduli<R>(L), u, f, out, omega, partial, ctl);
+    if constexpr (MODE == MODE_APPLY) {
+      hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0, p->stream,
+                         L.g, moduli<R>(L), u, f, out, omega, partial, ctl);
+    } else {
+      dispatch_shape(ts, [&](auto Xc, auto Yc) {
+        constexpr int TX = decltype(Xc)::value, TY = decltype(Yc)::value;
+        hipLaunchKernelGGL((k_stencil<D, K, R, MODE, TO, TX, TY>), dim3((unsigned)split_tiles<TX, TY>(L.g).blocks),
+                           dim3(TX, TY, 1), 0, p->stream, L.g, moduli<R>(L), u, f, out, omega, partial, ctl);
+      });
+    }
   });
 }
 
@@ -383,18 +444,30 @@ void launch_jacobi_zero(emg_problem *p, const Level &L, const R *f, R *out, R om
 
 template <typename RI, typename RO>
 void launch_restrict(emg_problem *p, const Level &Lf, const Level &Lc, const RI *rf, RO *fc, const Ctl *ctl) {
-  if (p->D == 2)
-    hipLaunchKernelGGL((k_restrict<2, RI, RO>), grid_of(Lc.g), kBlock, 0, p->stream, Lf.g, Lc.g, rf, fc, ctl);
-  else
-    hipLaunchKernelGGL((k_restrict<3, RI, RO>), grid_of(Lc.g), kBlock, 0, p->stream, Lf.g, Lc.g, rf, fc, ctl);
+  const int s = xfer_plan<RI>(p, Lf.g, true);
+  dispatch_shape(s, [&](auto Xc, auto Yc) {
+    constexpr int TX = decltype(Xc)::value, TY = decltype(Yc)::value;
+    if (p->D == 2)
+      hipLaunchKernelGGL((k_restrict<2, RI, RO, TX, TY>), grid_shape(Lc.g, s), block_shape(s), 0, p->stream, Lf.g,
+                         Lc.g, rf, fc, ctl);
+    else
+      hipLaunchKernelGGL((k_restrict<3, RI, RO, TX, TY>), grid_shape(Lc.g, s), block_shape(s), 0, p->stream, Lf.g,
+                         Lc.g, rf, fc, ctl);
+  });
 }
 
 template <typename RC, typename RF>
 void launch_prolong(emg_problem *p, const Level &Lc, const Level &Lf, const RC *ec, RF *uf, const Ctl *ctl) {
-  if (p->D == 2)
-    hipLaunchKernelGGL((k_prolong_add<2, RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
-  else
-    hipLaunchKernelGGL((k_prolong3_lds<RC, RF>), grid_of(Lf.g), kBlock, 0, p->stream, Lc.g, Lf.g, ec, uf, ctl);
+  const int s = xfer_plan<RF>(p, Lf.g, false);
+  dispatch_shape(s, [&](auto Xc, auto Yc) {
+    constexpr int TX = decltype(Xc)::value, TY = decltype(Yc)::value;
+    if (p->D == 2)
+      hipLaunchKernelGGL((k_prolong_add<2, RC, RF, TX, TY>), grid_shape(Lf.g, s), block_shape(s), 0, p->stream, Lc.g,
+                         Lf.g, ec, uf, ctl);
+    else
+      hipLaunchKernelGGL((k_prolong3_lds<RC, RF, TX, TY>), grid_shape(Lf.g, s), block_shape(s), 0, p->stream, Lc.g,
+                         Lf.g, ec, uf, ctl);
+  });
 }
 
 template <typename RI, typename RO>
@@ -570,18 +643,26 @@ int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcy
 // the callee's cycle from zero starts after that sweep.  Returns whether it
 // was fused.
 template <typename R>
-bool restrict_down(emg_problem *p, int l, R omega) {
+bool restrict_down(emg_problem *p, int l, R omega, const Ctl *ctl) {
   Level &Lv = p->lv[l], &Lc = p->lv[l + 1];
   if (l + 1 == (int)p->lv.size() - 1) {
-    launch_restrict<R, R>(p, Lv, Lc, rbuf<R>(Lv), fbuf<R>(Lc), p->ctl);
+    launch_restrict<R, R>(p, Lv, Lc, rbuf<R>(Lv), fbuf<R>(Lc), ctl);
     return false;
   }
+  const int s = xfer_plan<R>(p, Lv.g, true);
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_restrict_jz<D, K, R>), grid_of(Lc.g), kBlock, 0, p->stream, Lv.g, Lc.g,
-                       (const R *)rbuf<R>(Lv), fbuf<R>(Lc), moduli<R>(Lc), vbuf<R>(Lc, 0), omega, p->ctl);
+    dispatch_shape(s, [&](auto Xc, auto Yc) {
+      constexpr int TX = decltype(Xc)::value, TY = decltype(Yc)::value;
+      hipLaunchKernelGGL((k_restrict_jz<D, K, R, TX, TY>), grid_shape(Lc.g, s), block_shape(s), 0, p->stream, Lv.g,
+                         Lc.g, (const R *)rbuf<R>(Lv), fbuf<R>(Lc), moduli<R>(Lc), vbuf<R>(Lc, 0), omega, ctl);
+    });
   });
   return true;
+}
+template <typename R>
+bool restrict_down(emg_problem *p, int l, R omega) {
+  return restrict_down<R>(p, l, omega, p->ctl);
 }
 
 // Cycle on level l for the correction of the right-hand side f_l: from zero
@@ -638,7 +719,7 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc
   Level &L0 = p->lv[0];
   int cur = 0;
   launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[0], L0.f64, L0.u64[1], omega, p->partial, p->ctl);
-  launch_check(p, stencil_blocks(L0.g), 0);
+  launch_check(p, plan_blocks<double>(p, L0.g), 0);
   cur = 1;
   for (int s = 1; s < nu1; s++) {
     launch_stencil<double, MODE_JACOBI, double>(p, L0, L0.u64[cur], L0.f64, L0.u64[cur ^ 1], omega, nullptr, p->ctl);
@@ -687,7 +768,7 @@ void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc)
   } else {
     launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
   }
-  launch_check(p, stencil_blocks(L0.g), 0);
+  launch_check(p, plan_blocks<double>(p, L0.g), 0);
   int cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, -1, nzc > 0);
   for (int i = 1; i < p->inner; i++) cb = coarse_cycle<float>(p, 0, nu1, nu2, omega, fcyc, cb);
   // a continuing cycle flips the buffer nu1 + nu2 times: with an odd count
@@ -1956,7 +2037,8 @@ emg_status emg_problem_create(emg_ctx *ctx, const emg_domain *dom, emg_problem *
   }
   emg_status s;
   if ((s = dalloc(p, &p->Ainv, (size_t)nbot * nbot)) != EMG_OK) return bail(s);
-  p->npartial = std::max(grid_blocks(gs[0]), stencil_blocks(gs[0]));
+  p->npartial = grid_blocks(gs[0]);   // room for the partials of every tile shape of the stencil pass
+  for (int ts = 0; ts < TS_COUNT; ts++) p->npartial = std::max(p->npartial, split_shape(gs[0], ts).blocks);
   if ((s = dalloc(p, &p->partial, (size_t)p->npartial)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->ctl, 1)) != EMG_OK) return bail(s);
   if ((s = dalloc(p, &p->status, 4)) != EMG_OK) return bail(s);
@@ -2113,7 +2195,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   }
   if (opt.warm_start && p->fine.empty()) {
     launch_stencil<double, MODE_RESID, double>(p, L0, lift, L0.f64, L0.r64, 0.0, p->partial, nullptr);
-    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, stencil_blocks(L0.g), p->ctl);
+    hipLaunchKernelGGL(k_set_r0, dim3(1), dim3(1024), 0, p->stream, p->partial, plan_blocks<double>(p, L0.g), p->ctl);
   }
   if (opt.precision == EMG_MIXED) launch_fill<float>(p, nd0, L0.u32[mixed_result_buf(p, opt.nu1, opt.nu2)], 0.0f);
   HIPCK(hipGetLastError());
@@ -2384,15 +2466,19 @@ static emg_status time_level_kernel(emg_problem *p, int kernel, int level, int p
         launch_stencil<double, MODE_JACOBI, double>(p, L, L.u64[0], L.f64, L.u64[1], 2.0 / 3.0, nullptr, nullptr);
       else if (kernel == 1)
         launch_stencil<double, MODE_RESID, double>(p, L, L.u64[0], L.f64, L.r64, 0.0, nullptr, nullptr);
-      else
+      else if (kernel == 2)
         launch_prolong<double, double>(p, p->lv[level + 1], L, p->lv[level + 1].u64[0], L.u64[1], nullptr);
+      else
+        (void)restrict_down<double>(p, level, 2.0 / 3.0, nullptr);
     } else {
       if (kernel == 0)
         launch_stencil<float, MODE_JACOBI, float>(p, L, L.u32[0], L.f32, L.u32[1], 2.0f / 3.0f, nullptr, nullptr);
       else if (kernel == 1)
         launch_stencil<float, MODE_RESID, float>(p, L, L.u32[0], L.f32, L.r32, 0.0f, nullptr, nullptr);
-      else
+      else if (kernel == 2)
         launch_prolong<float, float>(p, p->lv[level + 1], L, p->lv[level + 1].u32[0], L.u32[1], nullptr);
+      else
+        (void)restrict_down<float>(p, level, 2.0f / 3.0f, nullptr);
     }
   };
   // The launches are captured into one graph, as the solve's cycles are, and
@@ -2427,8 +2513,8 @@ static emg_status time_level_kernel(emg_problem *p, int kernel, int level, int p
 emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision, int reps, double *avg_ms) {
   TRY(level_prep(p, level, precision));
   if (reps < 1 || !avg_ms) return fail(EMG_EINVAL, "bad reps or output");
-  if ((kernel == 1 || kernel == 2) && level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
-  if (kernel < 0 || kernel > 2) return fail(EMG_EINVAL, "unknown kernel id");
+  if ((kernel == 2 || kernel == 3) && level + 1 >= (int)p->lv.size()) return fail(EMG_EINVAL, "no coarser level");
+  if (kernel < 0 || kernel > 3) return fail(EMG_EINVAL, "unknown kernel id");
   TRY(time_level_kernel(p, kernel, level, precision, reps, avg_ms));
   return finish(p);
 }
@@ -2439,37 +2525,72 @@ emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int
   if (tuned) *tuned = 0;
   TRY(level_prep(p, 0, precision));
   if (reps < 1 || reps > 1000) return fail(EMG_EINVAL, "bad reps");
-  if (p->D != 3 || p->K != MOD_ANISO) return EMG_OK;
   const int rb = precision == EMG_FP64 ? 8 : 4;
   TuneTable &t = tune_table();
   int count = 0;
-  for (int l = 0; l < (int)p->lv.size(); l++) {
+  // best of two graph replays of `reps` launches of `kernel` on level l
+  auto measure = [&](int kernel, int l, double *ms) -> emg_status {
+    double a = 0.0, b = 0.0;
+    TRY(time_level_kernel(p, kernel, l, precision, reps, &a));
+    TRY(time_level_kernel(p, kernel, l, precision, reps, &b));
+    *ms = std::min(a, b);
+    return EMG_OK;
+  };
+  auto record = [&](const Geom &g, const char *what, int v) {
+    std::lock_guard<std::mutex> lk(t.mu);
+    tune_load_locked(t);
+    t.table[tune_key_locked(t, p->ctx->device, rb, g, p->K, what)] = v;
+  };
+  const int L = (int)p->lv.size();
+  for (int l = 0; l < L; l++) {
     const Geom &g = p->lv[l].g;
     const Split sp = split_of(g);
-    if (!zm_valid(g, 1)) continue;   // no z-marching variant on this level
     int have;
-    if (!retune && tune_find(p->ctx->device, rb, g, &have)) continue;
-    double best_ms = 0.0;
-    int best = -1;
-    for (int c = 0; c <= sp.ntz / 8; c++) {
-      double ms = 0.0, ms2 = 0.0;
-      p->force_nzc = c;
-      emg_status st = time_level_kernel(p, 0, l, precision, reps, &ms);
-      if (st == EMG_OK) st = time_level_kernel(p, 0, l, precision, reps, &ms2);
-      p->force_nzc = -1;
-      if (st != EMG_OK) return st;
-      ms = ms2 < ms ? ms2 : ms;
-      if (best < 0 || ms < best_ms) {
-        best = c;
-        best_ms = ms;
+    bool measured = false;
+    // stencil pass: the tile kernel in each tile shape, the z-marching pass at each chunk count
+    if (retune || !tune_find(p->ctx->device, rb, g, &have, p->K)) {
+      std::vector<int> cands;
+      for (int s = 0; s < TS_COUNT; s++) cands.push_back(-s);
+      if (zm_valid(g, 1, p->K))
+        for (int c = 1; c <= sp.ntz / 8; c++) cands.push_back(c);
+      double best_ms = 0.0;
+      int best = 0;
+      for (size_t i = 0; i < cands.size(); i++) {
+        double ms = 0.0;
+        p->force_stencil = true;
+        p->force_v = cands[i];
+        const emg_status st = measure(0, l, &ms);
+        p->force_stencil = false;
+        if (st != EMG_OK) return st;
+        if (i == 0 || ms < best_ms) {
+          best = cands[i];
+          best_ms = ms;
+        }
       }
+      record(g, "", best);
+      measured = true;
     }
-    {
-      std::lock_guard<std::mutex> lk(t.mu);
-      tune_load_locked(t);
-      t.table[tune_key_locked(t, p->ctx->device, rb, g)] = best;
+    // restriction from level l and interpolation onto it: tile shapes
+    for (int xf = 0; xf < 2 && l + 1 < L; xf++) {
+      const bool restriction = xf == 0;
+      if (!retune && tune_find(p->ctx->device, rb, g, &have, p->K, restriction ? "/r" : "/i")) continue;
+      double best_ms = 0.0;
+      int best = 0;
+      for (int s = 0; s < TS_COUNT; s++) {
+        double ms = 0.0;
+        (restriction ? p->force_rs : p->force_ps) = s;
+        const emg_status st = measure(restriction ? 3 : 2, l, &ms);
+        (restriction ? p->force_rs : p->force_ps) = -1;
+        if (st != EMG_OK) return st;
+        if (s == 0 || ms < best_ms) {
+          best = s;
+          best_ms = ms;
+        }
+      }
+      record(g, restriction ? "/r" : "/i", best);
+      measured = true;
     }
-    count++;
+    if (measured) count++;
   }
   destroy_graphs(p);   // recorded with the earlier plans
   if (tuned) *tuned = count;
@@ -2478,6 +2599,25 @@ emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int
     if (!tune_save_locked(t)) return fail(EMG_EINVAL, "cannot write the EMG_TUNE_CACHE file");
   }
   return finish(p);
+}
+
+emg_status emg_level_tiles(emg_problem *p, int level, int precision, int *stencil, int *restriction,
+                           int *interpolation) {
+  if (!p) return fail(EMG_EINVAL, "null problem");
+  if (level < 0 || level >= (int)p->lv.size()) return fail(EMG_EINVAL, "no such level");
+  if (precision != EMG_FP64 && precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  const Geom &g = p->lv[level].g;
+  const bool last = level + 1 >= (int)p->lv.size();
+  if (precision == EMG_FP64) {
+    if (stencil) *stencil = tile_plan<double>(p, g);
+    if (restriction) *restriction = last ? -1 : xfer_plan<double>(p, g, true);
+    if (interpolation) *interpolation = last ? -1 : xfer_plan<double>(p, g, false);
+  } else {
+    if (stencil) *stencil = tile_plan<float>(p, g);
+    if (restriction) *restriction = last ? -1 : xfer_plan<float>(p, g, true);
+    if (interpolation) *interpolation = last ? -1 : xfer_plan<float>(p, g, false);
+  }
+  return EMG_OK;
 }
 
 emg_status emg_autotune_reset(void) {

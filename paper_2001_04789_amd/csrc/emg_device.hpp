@@ -488,6 +488,16 @@ __device__ __forceinline__ void block_sum_256(double v, double *dst) {
   if (t == 0) *dst = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
+// Sum of v over a 128-thread block (two wavefronts), written by thread 0 to *dst.
+__device__ __forceinline__ void block_sum_128(double v, double *dst) {
+  __shared__ double ws[2];
+  const int t = threadIdx.x + threadIdx.y * blockDim.x;
+  v = wave_sum(v);
+  if ((t & 63) == 0) ws[t >> 6] = v;
+  __syncthreads();
+  if (t == 0) *dst = ws[0] + ws[1];
+}
+
 // Sum of v over a 1024-thread block (16 wavefronts), result to *dst from thread 0.
 __device__ __forceinline__ void block_sum_1024(double v, double *dst) {
   __shared__ double ws[16];

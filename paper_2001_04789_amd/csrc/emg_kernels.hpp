@@ -12,6 +12,13 @@ enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2 };
 
 constexpr int BX = 64, BY = 4;
 
+// Tile shapes (x extent x y extent of one plane) of the tile kernel and of
+// the restriction and interpolation launches, chosen per level by the
+// autotuner; 64 x 4 unless tuned (batched launches always use 64 x 4).
+enum { TS_64x4 = 0, TS_64x2 = 1, TS_128x2 = 2, TS_32x8 = 3, TS_COUNT = 4 };
+__host__ __device__ constexpr int ts_x(int s) { return s == TS_128x2 ? 128 : (s == TS_32x8 ? 32 : 64); }
+__host__ __device__ constexpr int ts_y(int s) { return s == TS_64x4 ? 4 : (s == TS_32x8 ? 8 : 2); }
+
 __device__ __forceinline__ bool skip(const Ctl *ctl) { return ctl != nullptr && ctl->done != 0; }
 
 __device__ __forceinline__ long long block_linear() {
@@ -52,7 +59,8 @@ struct Split {
   long long blocks;     // sblocks + inner
 };
 
-__host__ __device__ inline Split split_of(const Geom &g) {
+template <int TX = BX, int TY = BY>
+__host__ __device__ inline Split split_tiles(const Geom &g) {
   Split s;
   long long box = 1;
   bool empty = false;
@@ -72,8 +80,8 @@ __host__ __device__ inline Split split_of(const Geom &g) {
     box *= b > 0 ? b : 0;
   }
   if (!empty) {
-    s.ntx = (s.hi[0] - s.lo[0] + BX) / BX;
-    s.nty = (s.hi[1] - s.lo[1] + BY) / BY;
+    s.ntx = (s.hi[0] - s.lo[0] + TX) / TX;
+    s.nty = (s.hi[1] - s.lo[1] + TY) / TY;
     s.ntz = s.hi[2] - s.lo[2] + 1;
     s.inner = (long long)s.ntx * s.nty * s.ntz;
     s.shell = g.N - box;
@@ -82,9 +90,19 @@ __host__ __device__ inline Split split_of(const Geom &g) {
     s.inner = 0;
     s.shell = g.N;
   }
-  s.sblocks = (s.shell + 255) / 256;
+  s.sblocks = (s.shell + TX * TY - 1) / (TX * TY);
   s.blocks = s.sblocks + s.inner;
   return s;
+}
+__host__ __device__ inline Split split_of(const Geom &g) { return split_tiles<BX, BY>(g); }
+// host: the split of a tile shape chosen at run time
+inline Split split_shape(const Geom &g, int shape) {
+  switch (shape) {
+    case TS_64x2: return split_tiles<64, 2>(g);
+    case TS_128x2: return split_tiles<128, 2>(g);
+    case TS_32x8: return split_tiles<32, 8>(g);
+    default: return split_tiles<64, 4>(g);
+  }
 }
 
 // Coordinates of shell node s: the planes below the box (z < lo), then for
@@ -170,18 +188,18 @@ __device__ __forceinline__ void finish_rows(long long N, long long n, int cls, c
 // MASK (refined AMR levels): nodes of the interior box whose byte in vm is 0
 // (not valid: ghosts and nodes outside every box of the level) take the
 // Dirichlet row instead, as the outer ring of the level's array does.
-template <int D, int K, typename R, int MODE, typename TO, bool MASK = false>
+template <int D, int K, typename R, int MODE, typename TO, bool MASK = false, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict__ C, const R *__restrict__ u,
                                              const R *__restrict__ f, TO *__restrict__ out, R omega,
                                              double *__restrict__ pslot, long long t,
                                              const unsigned char *__restrict__ vm = nullptr) {
   static_assert(!MASK || MODE != MODE_APPLY, "masked passes are residuals and sweeps");
-  const Split sp = split_of(g);
+  const Split sp = split_tiles<TX, TY>(g);
   double nrm = 0.0;
   if (t >= sp.sblocks) {
     const long long it = t - sp.sblocks;
     const int tx = int(it % sp.ntx), ty = int((it / sp.ntx) % sp.nty), tz = int(it / ((long long)sp.ntx * sp.nty));
-    const int x = sp.lo[0] + tx * BX + threadIdx.x, y = sp.lo[1] + ty * BY + threadIdx.y, z = sp.lo[2] + tz;
+    const int x = sp.lo[0] + tx * TX + threadIdx.x, y = sp.lo[1] + ty * TY + threadIdx.y, z = sp.lo[2] + tz;
     if (x <= sp.hi[0] && y <= sp.hi[1]) {
       // 32-bit node indexing (level sizes are checked at creation: N < 2^31)
       const unsigned m0 = g.m[0], m01 = (unsigned)g.m[0] * g.m[1];
@@ -221,7 +239,7 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
       }
     }
   } else {
-    const long long s = t * 256 + threadIdx.x + BX * threadIdx.y;
+    const long long s = t * (TX * TY) + threadIdx.x + TX * threadIdx.y;
     if (s < sp.shell) {
       int p[3];
       shell_node(g, sp, s, p);
@@ -232,7 +250,10 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
       finish_rows<MODE, D, R, TO>(g.N, n, cls, acc, dg, u, f, out, omega, nrm);
     }
   }
-  if (pslot) block_sum_256(nrm, pslot);
+  if (pslot) {
+    if constexpr (TX * TY == 256) block_sum_256(nrm, pslot);
+    else block_sum_128(nrm, pslot);
+  }
 }
 
 // The tile kernel on a refined AMR level: rows of nodes that are not valid
@@ -250,13 +271,15 @@ __global__ __launch_bounds__(256, 2) void k_stencil_mask(Geom g, const R *__rest
 // order (an XCD-contiguous order of the tiles measured 3-4 % slower); at
 // least two wavefronts per SIMD (the FP64 anisotropic path would otherwise
 // take just over the 256 registers of that occupancy).
-template <int D, int K, typename R, int MODE, typename TO>
-__global__ __launch_bounds__(256, 2) void k_stencil(Geom g, const R *__restrict__ C, const R *__restrict__ u,
-                                                 const R *__restrict__ f, TO *__restrict__ out, R omega,
-                                                 double *__restrict__ partial, const Ctl *__restrict__ ctl) {
+template <int D, int K, typename R, int MODE, typename TO, int TX = BX, int TY = BY>
+__global__ __launch_bounds__(TX * TY, 2) void k_stencil(Geom g, const R *__restrict__ C,
+                                                                    const R *__restrict__ u, const R *__restrict__ f,
+                                                                    TO *__restrict__ out, R omega,
+                                                                    double *__restrict__ partial,
+                                                                    const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   const long long t = blockIdx.x;
-  body_stencil<D, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
+  body_stencil<D, K, R, MODE, TO, false, TX, TY>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
 }
 
 // ---- z-marching interior pass (3D, anisotropic moduli) ----
@@ -728,10 +751,10 @@ __device__ __forceinline__ void fw_weights(const Geom &gc, const Geom &gf, const
 // Full-weighting restriction (tensor product of [1/4, 1/2, 1/4]); along an
 // axis on whose end the coarse node sits only the coincident fine node
 // enters; Dirichlet coarse rows get 0.
-template <int D, typename RI, typename RO>
+template <int D, typename RI, typename RO, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, const RI *__restrict__ rf,
                                               RO *__restrict__ fc, int tx, int ty, int tz) {
-  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
+  const int x = tx * TX + threadIdx.x, y = ty * TY + threadIdx.y, z = tz;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -764,13 +787,13 @@ __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, co
   for (int i = 0; i < D; i++) fc[i * gc.N + nc] = RO(acc[i]);
 }
 
-template <int D, typename RI, typename RO>
-__global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf, RO *__restrict__ fc,
-                                                  const Ctl *__restrict__ ctl) {
+template <int D, typename RI, typename RO, int TX = BX, int TY = BY>
+__global__ __launch_bounds__(TX * TY) void k_restrict(Geom gf, Geom gc, const RI *__restrict__ rf,
+                                                      RO *__restrict__ fc, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  body_restrict<D, RI, RO>(gf, gc, rf, fc, tx_, ty_, tz_);
+  body_restrict<D, RI, RO, TX, TY>(gf, gc, rf, fc, tx_, ty_, tz_);
 }
 
 // Restriction fused with the coarse level's first Jacobi sweep from zero
@@ -778,14 +801,14 @@ __global__ __launch_bounds__(256) void k_restrict(Geom gf, Geom gc, const RI *__
 // k_restrict followed by k_jacobi_zero, one launch instead of two.  The
 // diagonal's moduli loads are issued with the fine residual's, so the two
 // latencies overlap.
-template <int D, int K, typename R>
-__global__ __launch_bounds__(256) void k_restrict_jz(Geom gf, Geom gc, const R *__restrict__ rf, R *__restrict__ fc,
+template <int D, int K, typename R, int TX = BX, int TY = BY>
+__global__ __launch_bounds__(TX * TY) void k_restrict_jz(Geom gf, Geom gc, const R *__restrict__ rf, R *__restrict__ fc,
                                                      const R *__restrict__ Cc, R *__restrict__ xc, R omega,
                                                      const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
+  const int x = tx_ * TX + threadIdx.x, y = ty_ * TY + threadIdx.y, z = tz_;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -829,10 +852,10 @@ __global__ __launch_bounds__(256) void k_restrict_jz(Geom gf, Geom gc, const R *
 
 // u_fine += bilinear/trilinear interpolation of the coarse correction;
 // Dirichlet fine rows untouched.
-template <int D, typename RC, typename RF>
+template <int D, typename RC, typename RF, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_prolong(const Geom &gc, const Geom &gf, const RC *__restrict__ ec,
                                              RF *__restrict__ uf, int tx, int ty, int tz) {
-  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
+  const int x = tx * TX + threadIdx.x, y = ty * TY + threadIdx.y, z = tz;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
   const int p[3] = {x, y, z};
@@ -869,33 +892,32 @@ __device__ __forceinline__ void body_prolong(const Geom &gc, const Geom &gf, con
   for (int i = 0; i < D; i++) uf[i * gf.N + n] += RF(acc[i]);
 }
 
-template <int D, typename RC, typename RF>
-__global__ __launch_bounds__(256) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
-                                                     const Ctl *__restrict__ ctl) {
+template <int D, typename RC, typename RF, int TX = BX, int TY = BY>
+__global__ __launch_bounds__(TX * TY) void k_prolong_add(Geom gc, Geom gf, const RC *__restrict__ ec,
+                                                         RF *__restrict__ uf, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  body_prolong<D, RC, RF>(gc, gf, ec, uf, tx_, ty_, tz_);
+  body_prolong<D, RC, RF, TX, TY>(gc, gf, ec, uf, tx_, ty_, tz_);
 }
 
-// 3D interpolation with the coarse values of a fine 64 x 4 tile staged in
-// LDS: the tile needs coarse x in [x0/2, x0/2 + 32], y in [y0/2, y0/2 + 2]
-// and planes z/2, z/2 + 1 (198 nodes), loaded once by the first 198 threads
-// instead of 8 loads per component by every fine node.  Coarse coordinates
+// 3D interpolation with the coarse values of a fine TX x TY tile staged in
+// LDS: the tile needs coarse x in [x0/2, x0/2 + TX/2], y in [y0/2, y0/2 +
+// TY/2] and planes z/2, z/2 + 1 (198 nodes for 64 x 4), loaded once by the
+// threads of the tile instead of 8 loads per component by every fine node.  Coarse coordinates
 // wrap on periodic axes and clamp otherwise (clamped values only enter with
 // weight 0 or for fine nodes outside the grid).  The sum per fine node is
 // that of body_prolong, term by term.
-template <typename RC, typename RF>
-__global__ __launch_bounds__(256) void k_prolong3_lds(Geom gc, Geom gf, const RC *__restrict__ ec, RF *__restrict__ uf,
-                                                      const Ctl *__restrict__ ctl) {
+template <typename RC, typename RF, int TX = BX, int TY = BY>
+__global__ __launch_bounds__(TX * TY) void k_prolong3_lds(Geom gc, Geom gf, const RC *__restrict__ ec,
+                                                          RF *__restrict__ uf, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  constexpr int CX = BX / 2 + 1, CY = BY / 2 + 1, CP = CX * CY * 2;
+  constexpr int CX = TX / 2 + 1, CY = TY / 2 + 1, CP = CX * CY * 2;
   __shared__ RC sE[3][CP];
   int tx_, ty_, tz_;
   tile_of(tx_, ty_, tz_);
-  const int x0 = tx_ * BX, y0 = ty_ * BY, z = tz_;
-  const int t = threadIdx.x + BX * threadIdx.y;
-  if (t < CP) {
+  const int x0 = tx_ * TX, y0 = ty_ * TY, z = tz_;
+  for (int t = threadIdx.x + TX * threadIdx.y; t < CP; t += TX * TY) {
     const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
     int c[3] = {x0 / 2 + cx, y0 / 2 + cy, z / 2 + cz};
 #pragma unroll

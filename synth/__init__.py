@@ -1046,7 +1046,8 @@ def serving_trace(count: int = 512, seed: int = 2005, rate: float = 200.0, varia
     1/rate; size log-uniform in [33, 129] nodes per axis rounded in log space
     to the nearest of 33, 49, 65, 97, 129; even ids are 3D spherical
     inclusions, odd ids polycrystals; each request draws one of ``variants``
-    pre-generated inputs of its type and size."""
+    inputs of its type and size, or (variants = 0) an input of its own,
+    seeded from its id."""
     rng = np.random.default_rng(seed)
     logs = np.log(np.array(SERVE_SIZES, dtype=np.float64))
     t = 0.0
@@ -1055,9 +1056,31 @@ def serving_trace(count: int = 512, seed: int = 2005, rate: float = 200.0, varia
         t += rng.exponential(1.0 / rate)
         s = rng.uniform(logs[0], logs[-1])
         n = SERVE_SIZES[int(np.argmin(np.abs(logs - s)))]
-        v = int(rng.integers(variants))
+        v = int(rng.integers(variants)) if variants > 0 else i
         out.append(ServeRequest(t, "inclusion" if i % 2 == 0 else "polycrystal", n, v))
     return out
+
+
+def _serving_worker(key):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        return key, serving_problem(*key)
+
+
+def serving_inputs(trace, workers: int = 16):
+    """The inputs of a trace's distinct (type, n, variant) keys, generated in
+    `workers` processes (each key's input is the same however it is made);
+    yields (key, Problem) as they complete."""
+    import concurrent.futures
+    import multiprocessing
+    keys = sorted({(r.kind, r.n, r.variant) for r in trace}, key=lambda k: -k[1])
+    if workers <= 1:
+        for k in keys:
+            yield k, serving_problem(*k)
+        return
+    with concurrent.futures.ProcessPoolExecutor(workers, mp_context=multiprocessing.get_context("fork")) as ex:
+        for k, p in ex.map(_serving_worker, keys, chunksize=2):
+            yield k, p
 
 
 def serving_problem(kind: str, n: int, variant: int, seed: int = 2005) -> Problem:

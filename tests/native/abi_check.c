@@ -1,7 +1,7 @@
 /* The C ABI (include/emg.h) driven from plain C, with no Python in between:
  * a context; single-level FP64 / mixed (one and two FP32 cycles per
  * refinement step) / F-cycle solves with a warm start;
- * the autotuner on a level too narrow for its variants;
+ * the autotuner (tile shapes of every level) and a solve on its plan;
  * displacement, stress and von Mises read-back; a ragged batch of three
  * problems; a three-level AMR problem in both precisions; a server taking
  * twelve requests of two sizes through three slots; an invalid domain.
@@ -135,12 +135,21 @@ int main(void) {
   o.cycle = EMG_FCYCLE;
   o.warm_start = 1;
   CHECK(emg_solve(p, &o, &st), EMG_OK);
-  int ntuned = -1;   /* 32 x 32 x 33 stored nodes: too narrow for the z-marching variants */
+  int ntuned = -1, nlev = 0;   /* every level has tile-shape variants (no z-march: too narrow) */
+  CHECK(emg_num_levels(p, &nlev), EMG_OK);
   CHECK(emg_autotune(p, EMG_FP64, 5, 0, &ntuned), EMG_OK);
-  if (ntuned != 0) {
-    fprintf(stderr, "FAIL autotune measured %d levels\n", ntuned);
+  if (ntuned != nlev) {
+    fprintf(stderr, "FAIL autotune measured %d of %d levels\n", ntuned, nlev);
     failures++;
   }
+  int zm = -1, ts = -1, rs = -1, is = -1;
+  CHECK(emg_level_zmarch(p, 0, EMG_FP64, &zm), EMG_OK);
+  CHECK(emg_level_tiles(p, 0, EMG_FP64, &ts, &rs, &is), EMG_OK);
+  if (zm != 0 || ts < 0 || ts > 3 || rs < 0 || rs > 3 || is < 0 || is > 3) {
+    fprintf(stderr, "FAIL tuned plan of level 0: zm %d tiles %d %d %d\n", zm, ts, rs, is);
+    failures++;
+  }
+  CHECK(emg_solve(p, &o, &st), EMG_OK);   /* a solve on the tuned plan */
   CHECK(emg_autotune(p, EMG_FP64, 0, 0, &ntuned), EMG_EINVAL);
   CHECK(emg_autotune_reset(), EMG_OK);
   int64_t m[3];

@@ -280,3 +280,32 @@ def test_eshelby_amr_efficiency_case(emg, ctx):
     print(f"[gpu] eshelby AMR: cycles {st['cycles']} composite nodes {ap.composite_nodes()} vs {pu.nodes}, "
           f"base diff vs uniform {diff:.3e}", flush=True)
     assert diff <= 2e-2 and 5 * ap.composite_nodes() <= pu.nodes
+
+
+def test_microstructure_amr_efficiency_case(emg, ctx):
+    """Microstructure half of the AMR study at a small size (finest 129^2,
+    base 33^2, two levels of blocks along the grain boundaries): the GPU
+    composite solution satisfies the oracle's composite system to 1.2e-10 in
+    the oracle's cycle count, and its base-grid values stay within 5 % of
+    the uniform finest-grid GPU solution."""
+    ap = synth.microstructure_amr_2d(129, 3)
+    assert all(len(ap.level_boxes(k)) > 1 for k in (1, 2))
+    comp = amr.from_problem(ap)
+    _, hist = comp.solve(tol=1e-10, max_cycles=300)
+    prob = emg.Problem.from_amr(ctx, ap)
+    st = prob.solve(rtol=1e-10, max_cycles=300)
+    u = _gpu_solution(prob, len(ap.boxes) + 1)
+    prob.close()
+    rel = comp.norm(comp.residual(u)) / comp.norm(comp.residual(comp.initial()))
+    print(f"[gpu] microstructure AMR: boxes {[len(ap.level_boxes(k)) for k in (1, 2)]} cycles {st['cycles']} "
+          f"(oracle {len(hist) - 1}) oracle rel residual {rel:.2e}", flush=True)
+    assert st["converged"] and rel <= 1.2e-10 and abs(st["cycles"] - (len(hist) - 1)) <= 1
+    pu = synth.microstructure_uniform_2d(129)
+    pf = emg.Problem.from_spec(ctx, pu)
+    pf.solve(rtol=1e-10, max_cycles=300)
+    uf = pf.displacement()[:, :, ::4, ::4]
+    pf.close()
+    diff = float(np.abs(u[0] - uf).max() / np.abs(uf).max())
+    print(f"[gpu] microstructure AMR vs uniform 129^2: base diff {diff:.3e}, nodes {ap.composite_nodes()} vs "
+          f"{pu.nodes}", flush=True)
+    assert diff <= 5e-2
