@@ -184,8 +184,7 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *opts, emg_solve_stats
  * and the moduli of the solve (covered nodes averaged from level k+1);
  * values are the stress of the composite solution at valid nodes (central
  * differences: their neighbours are valid or ghosts); at other nodes they
- * are those of the interpolated coarse field (3-point one-sided on the
- * array's outer ring).  EMG_EINVAL for a level that does not exist. */
+ * are not defined.  EMG_EINVAL for a level that does not exist. */
 emg_status emg_get_displacement(emg_problem *p, double *u, int on_device);
 emg_status emg_set_displacement(emg_problem *p, const double *u, int on_device);
 emg_status emg_get_stress(emg_problem *p, int level, double *sigma, int on_device);
@@ -330,8 +329,10 @@ emg_status emg_server_destroy(emg_server *s);
  * The relative residual is the 2-norm over all composite rows.  With a warm
  * start the reference norm is the warm iterate's own residual.  After a solve
  * emg_get_displacement returns the base grid (covered nodes injected) and
- * emg_amr_get_displacement a level's array with its other nodes
- * interpolated. */
+ * emg_amr_get_displacement a level's array: valid nodes and their ghosts
+ * (interpolated); the cycle only works on the 64 x 4 tiles of the array that
+ * hold such nodes, and the other nodes keep what was last written there (0
+ * after emg_set_level_boxes). */
 typedef struct {
   int64_t lo[3], hi[3];   /* inclusive node box in its level's index space (2D: lo[2] = hi[2] = 0) */
 } emg_box;

@@ -78,6 +78,10 @@ struct Level {
   float *u32[2] = {nullptr, nullptr};
   float *f32 = nullptr, *r32 = nullptr;
   const unsigned char *vm = nullptr;   // refined AMR level: valid-node mask (masked tile passes)
+  const int *act_st = nullptr;         //   interior tiles of the stencil split holding valid nodes or ghosts
+  long long nact_st = 0;
+  const int *act_gr = nullptr;         //   grid_of tiles holding valid nodes or ghosts
+  long long nact_gr = 0;
 };
 
 // One refined AMR level: valid nodes = the union of `boxes`, stored over
@@ -88,6 +92,8 @@ struct Fine {
   std::vector<Box> boxes;
   std::vector<unsigned char> hmask;   // host copy of vm (nesting checks of the next level)
   unsigned char *vm = nullptr;
+  int *act_st = nullptr, *act_gr = nullptr;   // active tiles (see Level)
+  long long nact_st = 0, nact_gr = 0;
   double *sig = nullptr;              // stress output buffer (allocated on first use)
   long long nvalid = 0, ncov = 0;     // valid nodes; coarse nodes they cover
   double *C = nullptr, *eps = nullptr, *body = nullptr;
@@ -403,8 +409,9 @@ void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *
     if (L.vm) {   // refined AMR level: tile kernel with the valid-node mask (no norm partials)
       dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
         constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-        hipLaunchKernelGGL((k_stencil_mask<D, K, R, MODE, TO>), dim3((unsigned)stencil_blocks(L.g)), kBlock, 0,
-                           p->stream, L.g, moduli<R>(L), u, f, out, omega, L.vm, ctl);
+        const Split sp = split_of(L.g);
+        hipLaunchKernelGGL((k_stencil_mask<D, K, R, MODE, TO>), dim3((unsigned)(sp.sblocks + L.nact_st)), kBlock, 0,
+                           p->stream, L.g, moduli<R>(L), u, f, out, omega, L.vm, L.act_st, sp.sblocks, ctl);
       });
       return;
     }
@@ -437,8 +444,8 @@ template <typename R>
 void launch_jacobi_zero(emg_problem *p, const Level &L, const R *f, R *out, R omega, const Ctl *ctl) {
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
-    hipLaunchKernelGGL((k_jacobi_zero<D, K, R>), grid_of(L.g), kBlock, 0, p->stream, L.g, moduli<R>(L), f, out, omega,
-                       ctl, L.vm);
+    hipLaunchKernelGGL((k_jacobi_zero<D, K, R>), L.act_gr ? dim3((unsigned)L.nact_gr) : grid_of(L.g), kBlock, 0,
+                       p->stream, L.g, moduli<R>(L), f, out, omega, ctl, L.vm, L.act_gr);
   });
 }
 
@@ -590,6 +597,7 @@ emg_status ensure_mixed(emg_problem *p) {
       TRY(dalloc(p, &F.t32, nd));
       TRY(dalloc(p, &F.e32[0], nd));
       TRY(dalloc(p, &F.e32[1], nd));
+      for (float *a : {F.rr32, F.t32, F.e32[0], F.e32[1]}) launch_fill<float>(p, (long long)nd, a, 0.0f);
     }
     launch_cast<double, float>(p, (long long)p->nc * F.g.SC, F.C, F.C32, nullptr);
   }
@@ -788,6 +796,8 @@ dim3 covered_grid(emg_problem *p, const Box &b, int grow) {
               (b.hi[1] / 2 - b.lo[1] / 2 + 1 + 2 * grow + BY - 1) / BY,
               p->D == 3 ? b.hi[2] / 2 - b.lo[2] / 2 + 1 + 2 * grow : 1);
 }
+// launch grid of a refined level's active tiles (grid_of order, 1D)
+dim3 act_grid(const Fine &F) { return dim3((unsigned)std::max<long long>(F.nact_gr, 1)); }
 // a box level seen through the single-level launch helpers
 Level box_level(const Fine &F) {
   Level L;
@@ -795,6 +805,10 @@ Level box_level(const Fine &F) {
   L.C64 = F.C;
   L.C32 = F.C32;
   L.vm = F.vm;
+  L.act_st = F.act_st;
+  L.nact_st = F.nact_st;
+  L.act_gr = F.act_gr;
+  L.nact_gr = F.nact_gr;
   return L;
 }
 
@@ -810,8 +824,8 @@ void amr_sync(emg_problem *p, double *u0, const Ctl *ctl) {
   for (int k = 1; k <= Lf; k++) {
     Fine &F = p->fine[k - 1];
     const double *uc = k == 1 ? u0 : p->fine[k - 2].u;
-    hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 1, ctl);
+    hipLaunchKernelGGL((k_interp<D, double>), act_grid(F), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, F.vm, F.act_gr, uc, F.u, (double *)nullptr, 1, ctl);
   }
 }
 
@@ -864,7 +878,8 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
   for (int k = Lf; k >= 1; k--) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
-    hipLaunchKernelGGL((k_ghost_fill<D, double>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.vm, F.rr, 0.0, p->ctl);
+    hipLaunchKernelGGL((k_ghost_fill<D, double>), act_grid(F), kBlock, 0, p->stream, F.g, F.vm, F.act_gr, F.rr, 0.0,
+                       p->ctl);
     launch_jacobi_zero<double>(p, B, F.rr, F.e[0], omega, p->ctl);
     int c = 0;
     for (int s = 1; s < nu1; s++) {
@@ -891,8 +906,8 @@ void record_amr_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc)
     Level B = box_level(F);
     const double *ec = k == 1 ? L0.u64[cb] : p->fine[k - 2].e[cur[k - 1]];
     int c = cur[k];
-    hipLaunchKernelGGL((k_interp<D, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, F.vm, ec, F.e[c], F.rr, 2, p->ctl);
+    hipLaunchKernelGGL((k_interp<D, double>), act_grid(F), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, F.vm, F.act_gr, ec, F.e[c], F.rr, 2, p->ctl);
     for (int s = 0; s < nu2; s++) {
       launch_stencil<double, MODE_JACOBI, double>(p, B, F.e[c], F.rr, F.e[c ^ 1], omega, nullptr, p->ctl);
       c ^= 1;
@@ -929,7 +944,8 @@ void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool 
   for (int k = Lf; k >= 1; k--) {
     Fine &F = p->fine[k - 1];
     Level B = box_level(F);
-    hipLaunchKernelGGL((k_ghost_fill<D, float>), grid_of(F.g), kBlock, 0, p->stream, F.g, F.vm, F.rr32, 0.0f, p->ctl);
+    hipLaunchKernelGGL((k_ghost_fill<D, float>), act_grid(F), kBlock, 0, p->stream, F.g, F.vm, F.act_gr, F.rr32, 0.0f,
+                       p->ctl);
     launch_jacobi_zero<float>(p, B, F.rr32, F.e32[0], omega, p->ctl);
     int c = 0;
     for (int s = 1; s < nu1; s++) {
@@ -956,8 +972,8 @@ void record_amr_cycle_mixed(emg_problem *p, int nu1, int nu2, float omega, bool 
     Level B = box_level(F);
     const float *ec = k == 1 ? L0.u32[cb] : p->fine[k - 2].e32[cur[k - 1]];
     int c = cur[k];
-    hipLaunchKernelGGL((k_interp<D, float>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
-                       F.g, F.b, F.vm, ec, F.e32[c], F.rr32, 2, p->ctl);
+    hipLaunchKernelGGL((k_interp<D, float>), act_grid(F), kBlock, 0, p->stream, parent_geom(p, k), parent_origin(p, k),
+                       F.g, F.b, F.vm, F.act_gr, ec, F.e32[c], F.rr32, 2, p->ctl);
     for (int s = 0; s < nu2; s++) {
       launch_stencil<float, MODE_JACOBI, float>(p, B, F.e32[c], F.rr32, F.e32[c ^ 1], omega, nullptr, p->ctl);
       c ^= 1;
@@ -2175,11 +2191,11 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
         Fine &F = p->fine[k - 1];
         const double *uc = k == 1 ? p->amr_u0 : p->fine[k - 2].u;
         if (p->D == 2)
-          hipLaunchKernelGGL((k_interp<2, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
-                             parent_origin(p, k), F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+          hipLaunchKernelGGL((k_interp<2, double>), act_grid(F), kBlock, 0, p->stream, parent_geom(p, k),
+                             parent_origin(p, k), F.g, F.b, F.vm, F.act_gr, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
         else
-          hipLaunchKernelGGL((k_interp<3, double>), grid_of(F.g), kBlock, 0, p->stream, parent_geom(p, k),
-                             parent_origin(p, k), F.g, F.b, F.vm, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
+          hipLaunchKernelGGL((k_interp<3, double>), act_grid(F), kBlock, 0, p->stream, parent_geom(p, k),
+                             parent_origin(p, k), F.g, F.b, F.vm, F.act_gr, uc, F.u, (double *)nullptr, 0, (const Ctl *)nullptr);
       }
     }
     // with a warm start the reference norm is the warm iterate's composite residual
@@ -3012,6 +3028,51 @@ static emg_status add_refined_level(emg_problem *p, int level, const emg_box *bo
                       (p->D == 2 || (F.b.lo[2] - 1 + z) % 2 == 0);
     if (even) F.ncov++;
   }
+  // active tiles: those holding a valid node or a node next to one (a ghost);
+  // passes over the level skip the others, whose nodes no valid row reads
+  {
+    std::vector<unsigned char> near((size_t)F.g.N, 0);
+    const int m0 = F.g.m[0], m1 = F.g.m[1], m2 = F.g.m[2];
+    const int zr = p->D == 3 ? 1 : 0;
+    for (int z = 0; z < m2; z++)
+      for (int y = 0; y < m1; y++)
+        for (int x = 0; x < m0; x++) {
+          if (!F.hmask[((size_t)z * m1 + y) * m0 + x]) continue;
+          for (int dz = -zr; dz <= zr; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+              for (int dx = -1; dx <= 1; dx++) {
+                const int X = x + dx, Y = y + dy, Z = z + dz;
+                if (X >= 0 && X < m0 && Y >= 0 && Y < m1 && Z >= 0 && Z < m2) near[((size_t)Z * m1 + Y) * m0 + X] = 1;
+              }
+        }
+    auto any_near = [&](int x0, int x1, int y0, int y1, int z) {
+      for (int y = y0; y <= std::min(y1, m1 - 1); y++)
+        for (int x = x0; x <= std::min(x1, m0 - 1); x++)
+          if (near[((size_t)z * m1 + y) * m0 + x]) return true;
+      return false;
+    };
+    std::vector<int> gr, st;
+    const int gx = (m0 + BX - 1) / BX, gy = (m1 + BY - 1) / BY;
+    for (int z = 0; z < m2; z++)
+      for (int ty = 0; ty < gy; ty++)
+        for (int tx = 0; tx < gx; tx++)
+          if (any_near(tx * BX, tx * BX + BX - 1, ty * BY, ty * BY + BY - 1, z)) gr.push_back((z * gy + ty) * gx + tx);
+    const Split sp = split_of(F.g);
+    for (int tz = 0; tz < sp.ntz; tz++)
+      for (int ty = 0; ty < sp.nty; ty++)
+        for (int tx = 0; tx < sp.ntx; tx++) {
+          const int x0 = sp.lo[0] + tx * BX, y0 = sp.lo[1] + ty * BY;
+          if (any_near(x0, std::min(x0 + BX - 1, sp.hi[0]), y0, std::min(y0 + BY - 1, sp.hi[1]), sp.lo[2] + tz))
+            st.push_back((tz * sp.nty + ty) * sp.ntx + tx);
+        }
+    F.nact_gr = (long long)gr.size();
+    F.nact_st = (long long)st.size();
+    TRY(dalloc(p, &F.act_gr, std::max<size_t>(gr.size(), 1)));
+    TRY(dalloc(p, &F.act_st, std::max<size_t>(st.size(), 1)));
+    HIPCK(hipMemcpyAsync(F.act_gr, gr.data(), sizeof(int) * gr.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCK(hipMemcpyAsync(F.act_st, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));   // the host vectors go out of scope
+  }
   const size_t nd = (size_t)p->D * F.g.N;
   TRY(dalloc(p, &F.vm, (size_t)F.g.N));
   HIPCK(hipMemcpyAsync(F.vm, F.hmask.data(), (size_t)F.g.N, hipMemcpyHostToDevice, p->stream));
@@ -3022,6 +3083,9 @@ static emg_status add_refined_level(emg_problem *p, int level, const emg_box *bo
   TRY(dalloc(p, &F.t, nd));
   TRY(dalloc(p, &F.e[0], nd));
   TRY(dalloc(p, &F.e[1], nd));
+  // nodes outside the active tiles are never written by the cycle: start
+  // every per-node array at zero so they stay finite
+  for (double *a : {F.f, F.rr, F.t, F.e[0], F.e[1]}) launch_fill<double>(p, (long long)nd, a, 0.0);
   if (!p->amr_u0) {
     const size_t nd0 = (size_t)p->D * p->lv[0].g.N;
     TRY(dalloc(p, &p->amr_u0, nd0));

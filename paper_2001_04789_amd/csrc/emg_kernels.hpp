@@ -43,6 +43,21 @@ __device__ __forceinline__ unsigned tile_of(int &tx, int &ty, int &tz) {
   return L;
 }
 
+// Tile of this block from a list of active tiles (refined AMR levels: the
+// 64 x 4 tiles of a plane that hold valid nodes or their ghosts), or the
+// XCD-aware order over the whole grid when act is null.
+__device__ __forceinline__ void tile_in(const int *__restrict__ act, int m0, int m1, int &tx, int &ty, int &tz) {
+  if (!act) {
+    tile_of(tx, ty, tz);
+    return;
+  }
+  const int gx = (m0 + BX - 1) / BX, gy = (m1 + BY - 1) / BY;
+  const int L = act[blockIdx.x];
+  tx = L % gx;
+  ty = (L / gx) % gy;
+  tz = L / (gx * gy);
+}
+
 // Work decomposition of a stencil pass over one level.  The interior box
 // holds the nodes whose rows are interior rows with in-range or periodically
 // wrapped neighbours: per axis the full range if periodic, else 1..m-2.  The
@@ -257,14 +272,19 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
 }
 
 // The tile kernel on a refined AMR level: rows of nodes that are not valid
-// (vm[n] == 0) are Dirichlet rows.
+// (vm[n] == 0) are Dirichlet rows.  Blocks: the shell blocks, then the
+// interior tiles listed in act (those holding valid nodes or ghosts; the
+// other nodes are never read).
 template <int D, int K, typename R, int MODE, typename TO>
 __global__ __launch_bounds__(256, 2) void k_stencil_mask(Geom g, const R *__restrict__ C, const R *__restrict__ u,
                                                       const R *__restrict__ f, TO *__restrict__ out, R omega,
                                                       const unsigned char *__restrict__ vm,
+                                                      const int *__restrict__ act, long long sblocks,
                                                       const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
-  body_stencil<D, K, R, MODE, TO, true>(g, C, u, f, out, omega, nullptr, blockIdx.x, vm);
+  const long long b = blockIdx.x;
+  const long long t = b < sblocks ? b : sblocks + act[b - sblocks];
+  body_stencil<D, K, R, MODE, TO, true>(g, C, u, f, out, omega, nullptr, t, vm);
 }
 
 // One launch of split_of(g).blocks workgroups (64 x 4 threads) in dispatch
@@ -719,10 +739,11 @@ __device__ __forceinline__ void body_jacobi_zero(const Geom &g, const R *__restr
 template <int D, int K, typename R>
 __global__ __launch_bounds__(256) void k_jacobi_zero(Geom g, const R *__restrict__ C, const R *__restrict__ f,
                                                      R *__restrict__ out, R omega, const Ctl *__restrict__ ctl,
-                                                     const unsigned char *__restrict__ vm) {
+                                                     const unsigned char *__restrict__ vm,
+                                                     const int *__restrict__ act) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
+  tile_in(act, g.m[0], g.m[1], tx_, ty_, tz_);
   body_jacobi_zero<D, K, R>(g, C, f, out, omega, tx_, ty_, tz_, vm);
 }
 
@@ -1387,18 +1408,19 @@ __global__ __launch_bounds__(256) void k_average_cf(Geom gc, int3 co, Geom gf, B
   }
 }
 
-// Bi/trilinear interpolation of a coarse field at the nodes of the fine array.
+// Bi/trilinear interpolation of a coarse field at the nodes of the fine
+// array (of the tiles in act: those holding valid nodes or ghosts).
 //   mode 0: dst = interp at every node
 //   mode 1: dst = interp at nodes that are not valid
 //   mode 2: dst += interp at valid nodes, dst = interp at the others
 // dst2 (optional): = interp at nodes that are not valid.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b, Mask vm, const R *__restrict__ uc,
-                                                R *__restrict__ dst, R *__restrict__ dst2, int mode,
-                                                const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b, Mask vm, const int *__restrict__ act,
+                                                const R *__restrict__ uc, R *__restrict__ dst, R *__restrict__ dst2,
+                                                int mode, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
+  tile_in(act, gf.m[0], gf.m[1], tx_, ty_, tz_);
   const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const int p[3] = {x, y, z};
@@ -1437,11 +1459,11 @@ __global__ __launch_bounds__(256) void k_interp(Geom gc, int3 co, Geom gf, Box b
 
 // Rows of a refined level's array that are not valid <- v.
 template <int D, typename R>
-__global__ __launch_bounds__(256) void k_ghost_fill(Geom gf, Mask vm, R *__restrict__ a, R v,
-                                                    const Ctl *__restrict__ ctl) {
+__global__ __launch_bounds__(256) void k_ghost_fill(Geom gf, Mask vm, const int *__restrict__ act, R *__restrict__ a,
+                                                    R v, const Ctl *__restrict__ ctl) {
   if (skip(ctl)) return;
   int tx_, ty_, tz_;
-  tile_of(tx_, ty_, tz_);
+  tile_in(act, gf.m[0], gf.m[1], tx_, ty_, tz_);
   const int x = tx_ * BX + threadIdx.x, y = ty_ * BY + threadIdx.y, z = tz_;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const long long n = lin(gf, x, y, z);
