@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--serve-light-requests", type=int, default=160)
     ap.add_argument("--serve-nu", type=int, default=4, help="pre/post Jacobi sweeps per level of the served solves "
                     "(the served stream fixes no sweep count; V(4,4) serves more solves/s than V(2,2))")
+    ap.add_argument("--serve-inner", type=int, default=2, help="FP32 cycles per FP64 refinement step of the "
+                    "served solves")
     ap.add_argument("--amr", type=int, default=1, help="run the AMR blocks (0 = skip)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
@@ -362,7 +364,7 @@ def serve(emg, torch, ctx, args, count, rate, pool, gen_s):
     outs = [out_for(pool[(r.kind, r.n, r.variant)][0]) for r in trace]
     torch.cuda.synchronize()
     srv = emg.Server(ctx, max_slots=args.serve_slots, rtol=1e-10, max_cycles=400, precision="mixed",
-                     nu1=args.serve_nu, nu2=args.serve_nu)
+                     nu1=args.serve_nu, nu2=args.serve_nu, inner_cycles=args.serve_inner)
     passes = {}
     for name in ("cold", "warm"):
         base = srv.now()
@@ -386,7 +388,8 @@ def serve(emg, torch, ctx, args, count, rate, pool, gen_s):
                         "mean_cycles": float(np.mean([i["cycles"] for i in infos]))}
     srv.close()
     out = {"requests": len(trace), "rate_req_per_s": rate, "slots": args.serve_slots, "precision": "mixed",
-           "smoothing": f"V({args.serve_nu},{args.serve_nu})", "offered_span_s": trace[-1].t,
+           "smoothing": f"V({args.serve_nu},{args.serve_nu})", "inner_cycles": args.serve_inner,
+           "offered_span_s": trace[-1].t,
            "inputs": f"{len(trace)} distinct inputs seeded from the request ids, resident in HBM "
                      f"(pool generated in {gen_s:.0f} s on the host)",
            "domain_shapes": len({(r.kind, r.n) for r in trace})}
@@ -395,7 +398,7 @@ def serve(emg, torch, ctx, args, count, rate, pool, gen_s):
     return out
 
 
-def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4)):
+def amr_efficiency(emg, ctx, synth, n0=129, levels=(2, 3, 4, 5, 6)):
     """AMR against the uniform grid of the same finest resolution (the 2D
     disc of inclusion_2d, refined boxes around it): composite and uniform node
     counts, FP64 solve times to 1e-10 (second solve of each, after setup),
