@@ -398,8 +398,12 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
  * of the z-marching pass (> 0), 0 for the tile kernel in 64 x 4 tiles, or
  * -1, -2, -3 for the tile kernel in 64 x 2, 128 x 2, 32 x 8 tiles; for the
  * restriction ("/r") and interpolation ("/i") it is the tile shape 0..3 in
- * that order; entries out of range for their level are ignored.  *tuned
- * (optional) receives the number of levels measured.  EMG_EINVAL for reps
+ * that order; entries out of range for their level are ignored.  Problems
+ * with at least two levels below level 0 of at most 1024 nodes each also get
+ * "<level 0 key>/tail" (see emg_tail_levels): the V(2,2) correction on those levels timed
+ * as one fused launch and as a launch per pass, the value being their count
+ * if fused was faster, else 0.  *tuned (optional) receives the number of
+ * levels measured.  EMG_EINVAL for reps
  * outside 1..1000 or when the cache file cannot be written (the table itself
  * is updated). */
 emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int *tuned);
@@ -412,6 +416,21 @@ emg_status emg_level_tiles(emg_problem *p, int level, int precision, int *stenci
 /* Empties the process-wide table; the EMG_TUNE_CACHE file, if any, is read
  * again at the next lookup. */
 emg_status emg_autotune_reset(void);
+/* Fused coarse tail (multigrid level sequence, Sec. 3.1): the cycle on the
+ * smallest levels -- zero-start sweep, sweeps, residual, restriction, bottom
+ * solve, interpolation and sweeps of each of them, in the order the cycle
+ * visits them -- can run as ONE launch of one workgroup per problem instead
+ * of a launch per pass, with the same values node for node (bit-identical
+ * solves).  *levels receives how many levels, counted from the coarsest, the
+ * cycles of `precision` (EMG_FP64, EMG_MIXED: the FP32 cycles) fuse that way;
+ * 0 (every pass its own launch) unless the table holds an entry
+ * "arch/fp64|fp32/m0xm1xm2/p<mask>[/iso]/tail" -> count keyed by level 0
+ * (see emg_autotune, which times the fused and the separate launches of the
+ * levels below level 0 with at most 1024 nodes each and records the faster;
+ * EMG_TUNE_CACHE).  Counts beyond the levels below level 0 are clipped to
+ * them.  It applies to emg_solve, batched and served solves; graphs recorded
+ * before a change keep their plans. */
+emg_status emg_tail_levels(emg_problem *p, int precision, int *levels);
 
 #ifdef __cplusplus
 }

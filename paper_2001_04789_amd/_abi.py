@@ -110,6 +110,7 @@ _SIGS = {
     "emg_server_destroy": ([c_void_p], c_int),
     "emg_amr_add_level": ([c_void_p, P(c_int64), P(c_int64)], c_int),
     "emg_level_tiles": ([c_void_p, c_int, c_int, P(c_int), P(c_int), P(c_int)], c_int),
+    "emg_tail_levels": ([c_void_p, c_int, P(c_int)], c_int),
     "emg_set_level_boxes": ([c_void_p, c_int, c_void_p, c_int], c_int),
     "emg_amr_level_valid": ([c_void_p, c_int, c_void_p, P(c_int64)], c_int),
     "emg_amr_num_levels": ([c_void_p, P(c_int)], c_int),
@@ -443,6 +444,12 @@ class Problem:
         check(lib.emg_level_tiles(self.handle, level, _PREC[precision], ctypes.byref(a), ctypes.byref(b),
                                   ctypes.byref(c)), "emg_level_tiles")
         return a.value, b.value, c.value
+
+    def tail_levels(self, precision="fp64") -> int:
+        """Coarsest levels whose cycle runs as one fused launch (0: none)."""
+        c = c_int()
+        check(lib.emg_tail_levels(self.handle, _PREC[precision], ctypes.byref(c)), "emg_tail_levels")
+        return c.value
 
     def num_levels(self) -> int:
         n = c_int()

@@ -149,6 +149,7 @@ struct emg_problem {
   // restriction and interpolation tile shapes
   bool force_stencil = false;
   int force_v = 0, force_rs = -1, force_ps = -1;
+  int force_tail = -1;   // fused-tail depth under measurement (-1: none)
   int inner = 1;        // FP32 cycles per mixed refinement step (set by emg_solve for its duration)
   std::vector<void *> allocs;
   size_t bytes = 0;
@@ -161,6 +162,14 @@ struct emg_problem {
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
+  // step lists of the fused coarse tail (device BLists, one per precision,
+  // smoothing counts, cycle type and first tail level; kept until destroy:
+  // captured graphs hold their addresses)
+  struct TailList {
+    int rbytes, nu1, nu2, fcyc, start, res;
+    const BList *dev;
+  };
+  std::vector<TailList> tails;
   // block-structured AMR: refined levels 1.. (empty = single level)
   std::vector<Fine> fine;
   double *amr_u0 = nullptr, *amr_f0 = nullptr, *amr_partial = nullptr;
@@ -337,7 +346,9 @@ bool tune_find(int device, int rbytes, const Geom &g, int *nzc, int kind = MOD_A
   tune_load_locked(t);
   auto it = t.table.find(tune_key_locked(t, device, rbytes, g, kind, what));
   if (it == t.table.end()) return false;
-  const bool ok = *what ? (it->second >= 0 && it->second < TS_COUNT) : zm_valid(g, it->second, kind);
+  const bool ok = strcmp(what, "/tail") == 0 ? it->second >= 0
+                 : *what                    ? (it->second >= 0 && it->second < TS_COUNT)
+                                            : zm_valid(g, it->second, kind);
   if (!ok) return false;
   *nzc = it->second;
   return true;
@@ -651,9 +662,9 @@ int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcy
 // the callee's cycle from zero starts after that sweep.  Returns whether it
 // was fused.
 template <typename R>
-bool restrict_down(emg_problem *p, int l, R omega, const Ctl *ctl) {
+bool restrict_down(emg_problem *p, int l, R omega, const Ctl *ctl, bool plain = false) {
   Level &Lv = p->lv[l], &Lc = p->lv[l + 1];
-  if (l + 1 == (int)p->lv.size() - 1) {
+  if (plain || l + 1 == (int)p->lv.size() - 1) {
     launch_restrict<R, R>(p, Lv, Lc, rbuf<R>(Lv), fbuf<R>(Lc), ctl);
     return false;
   }
@@ -669,8 +680,133 @@ bool restrict_down(emg_problem *p, int l, R omega, const Ctl *ctl) {
   return true;
 }
 template <typename R>
-bool restrict_down(emg_problem *p, int l, R omega) {
-  return restrict_down<R>(p, l, omega, p->ctl);
+bool restrict_down(emg_problem *p, int l, R omega, bool plain = false) {
+  return restrict_down<R>(p, l, omega, p->ctl, plain);
+}
+
+// ---- fused coarse tail (k_tail) ----
+constexpr long long kTailNodes = 1024;   // levels of at most this many nodes go into the tail
+constexpr int kTailGrid = 64;            // workgroups of a batched tail launch (problems grid-strided)
+
+// Candidate depth of the fused tail: the levels below level 0 with at most
+// kTailNodes nodes each, counted from the bottom, if there are at least two
+// (a bottom solve alone gains nothing from fusing), else 0.
+int tail_candidate(const emg_problem *p) {
+  const int L = (int)p->lv.size();
+  int k = 0;
+  while (k < L - 1 && p->lv[L - 1 - k].g.N <= kTailNodes) k++;
+  return k >= 2 ? k : 0;
+}
+
+// Levels in the fused coarse tail of a problem's cycles (0: none): the depth
+// under measurement, else the table's (key of level 0 with "/tail"), else 0.
+// The default is no fusion: on MI355X one workgroup walking the small levels
+// (about 17 us per step, its loads not hidden by other wavefronts) is slower
+// than a launch per pass spread over many CUs (5-10 us each), at every size
+// measured; emg_autotune times both for a problem and records the faster.
+template <typename R>
+int tail_levels(const emg_problem *p) {
+  const int L = (int)p->lv.size();
+  if (p->force_tail >= 0) return std::min(p->force_tail, L - 1);
+  int tuned;
+  if (tune_find(p->ctx->device, (int)sizeof(R), p->lv[0].g, &tuned, p->K, "/tail")) return std::min(tuned, L - 1);
+  return 0;
+}
+
+// Step list of the cycle on levels l.. (from zero; buffers as coarse_cycle /
+// coarse_correction use them, restrictions unfused), appended to v; returns
+// the buffer holding the result, as they do.
+template <typename R>
+int tail_cycle(emg_problem *p, int l, int nu1, int nu2, bool fcyc, int cur, std::vector<BEnt> &v);
+template <typename R>
+int tail_correction(emg_problem *p, int l, int nu1, int nu2, bool fcyc, std::vector<BEnt> &v) {
+  if (!fcyc) return tail_cycle<R>(p, l, nu1, nu2, false, -1, v);
+  const int b = tail_cycle<R>(p, l, nu1, nu2, true, -1, v);
+  if (l == (int)p->lv.size() - 1) return b;
+  return tail_cycle<R>(p, l, nu1, nu2, false, b, v);
+}
+template <typename R>
+int tail_cycle(emg_problem *p, int l, int nu1, int nu2, bool fcyc, int cur, std::vector<BEnt> &v) {
+  const int L = (int)p->lv.size();
+  Level &Lv = p->lv[l];
+  auto ent = [&](int kind, const void *a, const void *b, void *out) {
+    BEnt e{};
+    e.kind = kind;
+    e.g = Lv.g;
+    e.C = moduli<R>(Lv);
+    e.a = a;
+    e.b = b;
+    e.out = out;
+    e.ctl = p->ctl;
+    return e;
+  };
+  if (l == L - 1) {
+    BEnt e = ent(BK_BOTTOM, fbuf<R>(Lv), nullptr, vbuf<R>(Lv, 0));
+    e.Ainv = p->Ainv;
+    e.nbot = p->nbot;
+    v.push_back(e);
+    return 0;
+  }
+  int s0 = 0;
+  if (cur < 0) {
+    v.push_back(ent(BK_JZERO, fbuf<R>(Lv), nullptr, vbuf<R>(Lv, 0)));
+    cur = 0;
+    s0 = 1;
+  }
+  for (int s = s0; s < nu1; s++, cur ^= 1) v.push_back(ent(BK_JACOBI, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1)));
+  v.push_back(ent(BK_RESID, vbuf<R>(Lv, cur), fbuf<R>(Lv), rbuf<R>(Lv)));
+  Level &Lc = p->lv[l + 1];
+  BEnt r = ent(BK_RESTRICT, rbuf<R>(Lv), nullptr, fbuf<R>(Lc));
+  r.g2 = Lc.g;
+  v.push_back(r);
+  const int cb = tail_correction<R>(p, l + 1, nu1, nu2, fcyc, v);
+  BEnt q = ent(BK_PROLONG, vbuf<R>(Lc, cb), nullptr, vbuf<R>(Lv, cur));
+  q.g2 = Lc.g;
+  v.push_back(q);
+  for (int s = 0; s < nu2; s++, cur ^= 1) v.push_back(ent(BK_JACOBI, vbuf<R>(Lv, cur), fbuf<R>(Lv), vbuf<R>(Lv, cur ^ 1)));
+  return cur;
+}
+
+// The problem's tail list for the current choice if the cycle's level l
+// starts the tail and the list was prepared, else null (per-launch path).
+template <typename R>
+const emg_problem::TailList *tail_at(const emg_problem *p, int l, int nu1, int nu2, bool fcyc) {
+  const int k = tail_levels<R>(p);
+  if (k == 0 || l != (int)p->lv.size() - k) return nullptr;
+  for (auto &t : p->tails)
+    if (t.rbytes == (int)sizeof(R) && t.start == l && t.nu1 == nu1 && t.nu2 == nu2 && t.fcyc == (int)fcyc) return &t;
+  return nullptr;
+}
+
+// Builds and uploads the tail list for the current choice (not while a
+// stream is captured: it allocates and copies).
+template <typename R>
+emg_status prepare_tail(emg_problem *p, int nu1, int nu2, bool fcyc) {
+  const int k = tail_levels<R>(p);
+  if (k == 0) return EMG_OK;
+  const int start = (int)p->lv.size() - k;
+  if (tail_at<R>(p, start, nu1, nu2, fcyc)) return EMG_OK;
+  std::vector<BEnt> v;
+  const int res = tail_correction<R>(p, start, nu1, nu2, fcyc, v);
+  std::vector<char> host(blist_bytes((int)v.size()), 0);
+  BList *h = (BList *)host.data();
+  h->n = (int)v.size();
+  h->total = 1;   // one problem, tile0 = 0
+  for (size_t j = 0; j < v.size(); j++) h->e[j] = v[j];
+  char *dev = nullptr;
+  TRY(dalloc(p, &dev, host.size()));
+  HIPCK(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, p->stream));
+  HIPCK(hipStreamSynchronize(p->stream));
+  p->tails.push_back({(int)sizeof(R), nu1, nu2, (int)fcyc, start, res, (const BList *)dev});
+  return EMG_OK;
+}
+
+template <typename R>
+void launch_tail(emg_problem *p, const BList *L, R omega, unsigned grid) {
+  dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
+    constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+    hipLaunchKernelGGL((k_tail<D, K, R>), dim3(grid), dim3(TL_THREADS), 0, p->stream, L, omega);
+  });
 }
 
 // Cycle on level l for the correction of the right-hand side f_l: from zero
@@ -698,7 +834,7 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, in
     cur ^= 1;
   }
   launch_stencil<R, MODE_RESID, R>(p, Lv, vbuf<R>(Lv, cur), fbuf<R>(Lv), rbuf<R>(Lv), omega, nullptr, p->ctl);
-  const bool jz = restrict_down<R>(p, l, omega);
+  const bool jz = restrict_down<R>(p, l, omega, tail_at<R>(p, l + 1, nu1, nu2, fcyc) != nullptr);
   const int cb = coarse_correction<R>(p, l + 1, nu1, nu2, omega, fcyc, jz);
   launch_prolong<R, R>(p, p->lv[l + 1], Lv, vbuf<R>(p->lv[l + 1], cb), vbuf<R>(Lv, cur), p->ctl);
   for (int s = 0; s < nu2; s++) {
@@ -714,6 +850,10 @@ int coarse_cycle(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, in
 // needs; f_l itself is only read).
 template <typename R>
 int coarse_correction(emg_problem *p, int l, int nu1, int nu2, R omega, bool fcyc, bool jz_done) {
+  if (const auto *t = tail_at<R>(p, l, nu1, nu2, fcyc)) {   // the whole correction in one launch
+    launch_tail<R>(p, t->dev, omega, 1);
+    return t->res;
+  }
   if (!fcyc) return coarse_cycle<R>(p, l, nu1, nu2, omega, false, -1, jz_done);
   const int b = coarse_cycle<R>(p, l, nu1, nu2, omega, true, -1, jz_done);
   if (l == (int)p->lv.size() - 1) return b;   // exact bottom solve: the V-cycle would repeat it
@@ -734,7 +874,7 @@ void record_fp64_cycle(emg_problem *p, int nu1, int nu2, double omega, bool fcyc
     cur ^= 1;
   }
   launch_stencil<double, MODE_RESID, double>(p, L0, L0.u64[cur], L0.f64, L0.r64, omega, nullptr, p->ctl);
-  const bool jz = restrict_down<double>(p, 0, omega);
+  const bool jz = restrict_down<double>(p, 0, omega, tail_at<double>(p, 1, nu1, nu2, fcyc) != nullptr);
   const int cb = coarse_correction<double>(p, 1, nu1, nu2, omega, fcyc, jz);
   launch_prolong<double, double>(p, p->lv[1], L0, p->lv[1].u64[cb], L0.u64[cur], p->ctl);
   for (int s = 0; s < nu2; s++) {
@@ -1083,6 +1223,7 @@ struct Step {
 struct BatchPlan {
   std::vector<Step> steps;
   std::vector<std::vector<BEnt>> lists;
+  std::vector<char> tail;          // per list: a coarse-tail list (several entries per problem)
   std::vector<int> sig;            // step sequence signature (graph reuse)
 };
 
@@ -1147,6 +1288,7 @@ struct Planner {
         }
         plan.steps.push_back({kind, gr.first, gr.second, f32, (int)plan.lists.size(), z == 1});
         plan.lists.push_back(std::move(v));
+        plan.tail.push_back(0);
         plan.sig.push_back((kind * 64 + gr.first * 8 + gr.second * 2 + (f32 ? 1 : 0)) * 2 + z);
       }
     }
@@ -1155,13 +1297,50 @@ struct Planner {
   template <typename R>
   static R *U(Level &L, int b) { return vbuf<R>(L, b); }
 
-  // coarse levels l >= 1 of the correction V-cycle (all problems with l < L_p)
+  // first level of a problem's fused coarse tail (its level count if none)
+  template <typename R>
+  static int tstart(const emg_problem *p) {
+    const int k = tail_levels<R>(p);
+    return (int)p->lv.size() - k;
+  }
+
+  // one launch per group: every problem's fused coarse tail (a V-cycle from
+  // zero on its tail levels), entries grouped by problem
+  template <typename R>
+  void tail(int nu1, int nu2) {
+    constexpr bool F = std::is_same<R, float>::value;
+    for (auto &gr : groups) {
+      std::vector<BEnt> es;
+      long long q = 0;
+      for (auto *p : probs) {
+        if (p->D != gr.first || p->K != gr.second) continue;
+        const int T = tstart<R>(p);
+        if (T >= (int)p->lv.size()) continue;
+        std::vector<BEnt> v;
+        (void)tail_correction<R>(p, T, nu1, nu2, false, v);
+        v[0].gx = v[0].gy = v[0].gz = 1;   // list total = problems
+        for (auto &e : v) {
+          e.tile0 = q;
+          es.push_back(e);
+        }
+        q++;
+      }
+      if (es.empty()) continue;
+      plan.steps.push_back({BK_TAIL, gr.first, gr.second, F, (int)plan.lists.size()});
+      plan.lists.push_back(std::move(es));
+      plan.tail.push_back(1);
+      plan.sig.push_back((BK_TAIL * 64 + gr.first * 8 + gr.second * 2 + (F ? 1 : 0)) * 2);
+    }
+  }
+
+  // coarse levels l >= 1 of the correction V-cycle (all problems with l < L_p),
+  // down to each problem's fused tail, which runs between the two sweeps
   template <typename R>
   void down_up(int nu1, int nu2) {
     constexpr bool F = std::is_same<R, float>::value;
     for (int d = 1; d < maxdepth; d++) {
       step(BK_BOTTOM, F, [&](emg_problem *p, BEnt &e) {
-        if (d != (int)p->lv.size() - 1) return false;
+        if (d != (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
         Level &L = p->lv[d];
         e = BEnt{};
         e.g = L.g;
@@ -1175,7 +1354,7 @@ struct Planner {
         return true;
       });
       step(BK_JZERO, F, [&](emg_problem *p, BEnt &e) {
-        if (d >= (int)p->lv.size() - 1) return false;
+        if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
         Level &L = p->lv[d];
         e = ent_level(L.g);
         e.C = moduli<R>(L);
@@ -1187,7 +1366,7 @@ struct Planner {
       int cur = 0;
       for (int s2 = 1; s2 < nu1; s2++, cur ^= 1)
         step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
-          if (d >= (int)p->lv.size() - 1) return false;
+          if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
           Level &L = p->lv[d];
           e = ent_level(L.g);
           e.C = moduli<R>(L);
@@ -1198,7 +1377,7 @@ struct Planner {
           return true;
         });
       step(BK_RESID, F, [&](emg_problem *p, BEnt &e) {
-        if (d >= (int)p->lv.size() - 1) return false;
+        if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
         Level &L = p->lv[d];
         e = ent_level(L.g);
         e.C = moduli<R>(L);
@@ -1209,7 +1388,7 @@ struct Planner {
         return true;
       });
       step(BK_RESTRICT, F, [&](emg_problem *p, BEnt &e) {
-        if (d >= (int)p->lv.size() - 1) return false;
+        if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
         Level &L = p->lv[d], &Lc = p->lv[d + 1];
         e = ent_level(Lc.g);
         e.g = L.g;
@@ -1220,12 +1399,13 @@ struct Planner {
         return true;
       });
     }
+    tail<R>(nu1, nu2);
     // up: deepest first
     const int post_cur = (nu1 - 1) & 1;   // buffer after the pre-sweeps of a coarse level
     const int end_cur = (nu1 - 1 + nu2) & 1;
     for (int d = maxdepth - 2; d >= 1; d--) {
       step(BK_PROLONG, F, [&](emg_problem *p, BEnt &e) {
-        if (d >= (int)p->lv.size() - 1) return false;
+        if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
         Level &L = p->lv[d], &Lc = p->lv[d + 1];
         const int cb = (d + 1 == (int)p->lv.size() - 1) ? 0 : end_cur;
         e = ent_level(L.g);
@@ -1238,7 +1418,7 @@ struct Planner {
       int cur = post_cur;
       for (int s2 = 0; s2 < nu2; s2++, cur ^= 1)
         step(BK_JACOBI, F, [&](emg_problem *p, BEnt &e) {
-          if (d >= (int)p->lv.size() - 1) return false;
+          if (d >= (int)p->lv.size() - 1 || d >= tstart<R>(p)) return false;
           Level &L = p->lv[d];
           e = ent_level(L.g);
           e.C = moduli<R>(L);
@@ -1381,6 +1561,7 @@ struct Planner {
     for (auto &e : es) e.tile0 = t++;
     plan.steps.push_back({-1, 0, 0, false, (int)plan.lists.size()});
     plan.lists.push_back(std::move(es));
+    plan.tail.push_back(0);
     plan.sig.push_back(-1);
   }
 
@@ -1468,78 +1649,103 @@ void launch_batch_zm(hipStream_t st, int kind, bool f32, const BList *L, double 
   }
 }
 
-// Device copy of a plan's work lists (capacity-sized, fixed addresses).
+// Device copy of a plan's work lists (capacity-sized, fixed addresses): the
+// one-entry-per-problem lists at one stride, then the coarse-tail lists
+// (several entries per problem) at their own, so that neither inflates the
+// other.  A plan's i-th list of each kind always sits at the same address
+// while the pool keeps its size, which is what captured graphs rely on.
 struct BatchDev {
   char *buf = nullptr;
   size_t bytes = 0;
-  int nlists = 0, cap = 0;
+  int nlists = 0, cap = 0;     // regular lists: count and entries each
+  int ntails = 0, tcap = 0;    // tail lists
+  std::vector<const BList *> addr;   // per plan list
   std::vector<char> host;
-  const BList *list(int i) const { return (const BList *)(buf + (size_t)i * blist_bytes(cap)); }
+  const BList *list(int i) const { return addr[i]; }
 };
+
+struct ListSizes {
+  int nl = 0, cap = 1, nt = 0, tcap = 1;
+};
+ListSizes list_sizes(const BatchPlan &plan) {
+  ListSizes z;
+  for (size_t i = 0; i < plan.lists.size(); i++) {
+    const int n = (int)plan.lists[i].size();
+    if (plan.tail[i]) {
+      z.nt++;
+      z.tcap = std::max(z.tcap, n);
+    } else {
+      z.nl++;
+      z.cap = std::max(z.cap, n);
+    }
+  }
+  return z;
+}
+
+// Lays the plan's lists out in dev (its sizes already large enough) and
+// copies them to the device.
+emg_status write_lists(const BatchPlan &plan, BatchDev &dev, hipStream_t st) {
+  const size_t stride = blist_bytes(dev.cap), tstride = blist_bytes(dev.tcap);
+  const size_t toff = (size_t)dev.nlists * stride;
+  dev.addr.assign(plan.lists.size(), nullptr);
+  int il = 0, it = 0;
+  for (size_t i = 0; i < plan.lists.size(); i++) {
+    const size_t off = plan.tail[i] ? toff + (size_t)it++ * tstride : (size_t)il++ * stride;
+    BList *h = (BList *)(dev.host.data() + off);
+    const auto &es = plan.lists[i];
+    h->n = (int)es.size();
+    h->total = 0;
+    for (size_t j = 0; j < es.size(); j++) {
+      h->e[j] = es[j];
+      h->total += (long long)es[j].gx * es[j].gy * es[j].gz;
+    }
+    dev.addr[i] = (const BList *)(dev.buf + off);
+  }
+  if (il) HIPCK(hipMemcpyAsync(dev.buf, dev.host.data(), (size_t)il * stride, hipMemcpyHostToDevice, st));
+  if (it) HIPCK(hipMemcpyAsync(dev.buf + toff, dev.host.data() + toff, (size_t)it * tstride, hipMemcpyHostToDevice, st));
+  return EMG_OK;
+}
 
 // Writes the plan's lists into the device pool (reallocated, and *grew set,
 // only if it is too small: list addresses are what captured graphs hold).
 emg_status upload_plan(const BatchPlan &plan, BatchDev &dev, hipStream_t st, int min_cap = 16, int min_lists = 1,
                        bool *grew = nullptr) {
-  int cap = 1;
-  for (auto &l : plan.lists) cap = std::max(cap, (int)l.size());
-  const int nl = (int)plan.lists.size();
+  const ListSizes z = list_sizes(plan);
   if (grew) *grew = false;
-  if (!dev.buf || nl > dev.nlists || cap > dev.cap) {
+  if (!dev.buf || z.nl > dev.nlists || z.cap > dev.cap || z.nt > dev.ntails || z.tcap > dev.tcap) {
     if (grew) *grew = dev.buf != nullptr;
     if (dev.buf) {
       HIPCK(hipStreamSynchronize(st));
       HIPCK(hipFree(dev.buf));
+      dev.buf = nullptr;
     }
-    dev.nlists = std::max(std::max(nl, 1), min_lists);
-    dev.cap = std::max(cap, min_cap);
-    dev.bytes = (size_t)dev.nlists * blist_bytes(dev.cap);
+    dev.nlists = std::max(std::max(z.nl, 1), std::max(min_lists, dev.nlists));
+    dev.cap = std::max(std::max(z.cap, min_cap), dev.cap);
+    dev.ntails = std::max(std::max(z.nt, 1), dev.ntails);
+    dev.tcap = std::max(z.tcap, dev.tcap);
+    dev.bytes = (size_t)dev.nlists * blist_bytes(dev.cap) + (size_t)dev.ntails * blist_bytes(dev.tcap);
     HIPCK(hipMalloc((void **)&dev.buf, dev.bytes));
     dev.host.assign(dev.bytes, 0);
   }
-  const size_t stride = blist_bytes(dev.cap);
-  for (int i = 0; i < nl; i++) {
-    BList *h = (BList *)(dev.host.data() + (size_t)i * stride);
-    const auto &es = plan.lists[i];
-    h->n = (int)es.size();
-    h->total = 0;
-    for (size_t j = 0; j < es.size(); j++) {
-      h->e[j] = es[j];
-      h->total += (long long)es[j].gx * es[j].gy * es[j].gz;
-    }
-  }
-  HIPCK(hipMemcpyAsync(dev.buf, dev.host.data(), (size_t)nl * stride, hipMemcpyHostToDevice, st));
-  return EMG_OK;
+  return write_lists(plan, dev, st);
 }
 
 // Writes the plan's lists into fixed device memory of `bytes` bytes (no
 // allocation); EMG_EINVAL if they do not fit.
 emg_status upload_plan_fixed(const BatchPlan &plan, void *base, size_t bytes, BatchDev &dev, hipStream_t st) {
-  int cap = 1;
-  for (auto &l : plan.lists) cap = std::max(cap, (int)l.size());
-  const int nl = std::max(1, (int)plan.lists.size());
-  const size_t need = (size_t)nl * blist_bytes(cap);
+  const ListSizes z = list_sizes(plan);
+  dev.nlists = std::max(1, z.nl);
+  dev.cap = z.cap;
+  dev.ntails = z.nt;
+  dev.tcap = z.tcap;
+  const size_t need = (size_t)dev.nlists * blist_bytes(dev.cap) + (size_t)dev.ntails * blist_bytes(dev.tcap);
   if (need > bytes)
     return fail(EMG_EINVAL, "the batch's work lists need " + std::to_string(need) + " bytes, more than the " +
                                 std::to_string(bytes) + " of the allocation-free scratch");
   dev.buf = (char *)base;
-  dev.nlists = nl;
-  dev.cap = cap;
   dev.bytes = need;
   dev.host.assign(need, 0);
-  const size_t stride = blist_bytes(cap);
-  for (int i = 0; i < (int)plan.lists.size(); i++) {
-    BList *h = (BList *)(dev.host.data() + (size_t)i * stride);
-    const auto &es = plan.lists[i];
-    h->n = (int)es.size();
-    h->total = 0;
-    for (size_t j = 0; j < es.size(); j++) {
-      h->e[j] = es[j];
-      h->total += (long long)es[j].gx * es[j].gy * es[j].gz;
-    }
-  }
-  HIPCK(hipMemcpyAsync(dev.buf, dev.host.data(), need, hipMemcpyHostToDevice, st));
-  return EMG_OK;
+  return write_lists(plan, dev, st);
 }
 
 // check_grid: workgroups of the batched convergence checks (grid-strided
@@ -1553,6 +1759,14 @@ void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, dou
     }
     if (s.zm) {
       launch_batch_zm(st, s.kind, s.f32, L, omega);
+      continue;
+    }
+    if (s.kind == BK_TAIL) {
+      dispatch(s.D, s.K, [&](auto Dc, auto Kc) {
+        constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
+        if (s.f32) hipLaunchKernelGGL((k_tail<D, K, float>), dim3(kTailGrid), dim3(TL_THREADS), 0, st, L, (float)omega);
+        else hipLaunchKernelGGL((k_tail<D, K, double>), dim3(kTailGrid), dim3(TL_THREADS), 0, st, L, omega);
+      });
       continue;
     }
     if (s.D == 2 && s.K == MOD_ISO) launch_batch_kind<2, MOD_ISO>(st, s.kind, s.f32, L, omega);
@@ -2171,6 +2385,8 @@ emg_status emg_solve(emg_problem *p, const emg_solve_opts *o, emg_solve_stats *s
   TRY(setup(p));
   if (opt.precision == EMG_MIXED) TRY(ensure_mixed(p));
   TRY(assemble_rhs(p));
+  TRY(prepare_tail<double>(p, opt.nu1, opt.nu2, opt.cycle == EMG_FCYCLE));   // FP64 cycles (and fallback)
+  if (opt.precision == EMG_MIXED) TRY(prepare_tail<float>(p, opt.nu1, opt.nu2, opt.cycle == EMG_FCYCLE));
   Level &L0 = p->lv[0];
   const long long nd0 = (long long)p->D * L0.g.N;
   Ctl c0{};
@@ -2368,6 +2584,13 @@ emg_status emg_level_zmarch(emg_problem *p, int level, int precision, int *chunk
   return EMG_OK;
 }
 
+emg_status emg_tail_levels(emg_problem *p, int precision, int *levels) {
+  if (!p || !levels) return fail(EMG_EINVAL, "null argument");
+  if (precision != EMG_FP64 && precision != EMG_MIXED) return fail(EMG_EINVAL, "bad precision");
+  *levels = precision == EMG_FP64 ? tail_levels<double>(p) : tail_levels<float>(p);
+  return EMG_OK;
+}
+
 emg_status emg_num_levels(emg_problem *p, int *levels) {
   if (!p || !levels) return fail(EMG_EINVAL, "null argument");
   *levels = (int)p->lv.size();
@@ -2484,8 +2707,10 @@ static emg_status time_level_kernel(emg_problem *p, int kernel, int level, int p
         launch_stencil<double, MODE_RESID, double>(p, L, L.u64[0], L.f64, L.r64, 0.0, nullptr, nullptr);
       else if (kernel == 2)
         launch_prolong<double, double>(p, p->lv[level + 1], L, p->lv[level + 1].u64[0], L.u64[1], nullptr);
-      else
+      else if (kernel == 3)
         (void)restrict_down<double>(p, level, 2.0 / 3.0, nullptr);
+      else
+        (void)coarse_correction<double>(p, level, 2, 2, 2.0 / 3.0, false, false);
     } else {
       if (kernel == 0)
         launch_stencil<float, MODE_JACOBI, float>(p, L, L.u32[0], L.f32, L.u32[1], 2.0f / 3.0f, nullptr, nullptr);
@@ -2493,8 +2718,10 @@ static emg_status time_level_kernel(emg_problem *p, int kernel, int level, int p
         launch_stencil<float, MODE_RESID, float>(p, L, L.u32[0], L.f32, L.r32, 0.0f, nullptr, nullptr);
       else if (kernel == 2)
         launch_prolong<float, float>(p, p->lv[level + 1], L, p->lv[level + 1].u32[0], L.u32[1], nullptr);
-      else
+      else if (kernel == 3)
         (void)restrict_down<float>(p, level, 2.0f / 3.0f, nullptr);
+      else
+        (void)coarse_correction<float>(p, level, 2, 2, 2.0f / 3.0f, false, false);
     }
   };
   // The launches are captured into one graph, as the solve's cycles are, and
@@ -2608,9 +2835,34 @@ emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int
     }
     if (measured) count++;
   }
+  // fused coarse tail: the V(2,2) correction on the candidate levels as one
+  // launch against a launch per pass (the control block is reset to running
+  // so that every launch does its work)
+  bool tail_measured = false;
+  const int kc = tail_candidate(p);
+  int have_tail;
+  if (kc >= 2 && (retune || !tune_find(p->ctx->device, rb, p->lv[0].g, &have_tail, p->K, "/tail"))) {
+    Ctl c0{};
+    c0.r0sq = -1.0;
+    c0.max_cycles = 1 << 30;
+    *p->ctl_host = c0;
+    HIPCK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(Ctl), hipMemcpyHostToDevice, p->stream));
+    struct TailReset {
+      emg_problem *p;
+      ~TailReset() { p->force_tail = -1; }
+    } tail_reset{p};
+    double sep = 0.0, fused = 0.0;
+    p->force_tail = 0;
+    TRY(measure(4, L - kc, &sep));
+    p->force_tail = kc;
+    TRY(precision == EMG_FP64 ? prepare_tail<double>(p, 2, 2, false) : prepare_tail<float>(p, 2, 2, false));
+    TRY(measure(4, L - kc, &fused));
+    record(p->lv[0].g, "/tail", fused < sep ? kc : 0);
+    tail_measured = true;
+  }
   destroy_graphs(p);   // recorded with the earlier plans
   if (tuned) *tuned = count;
-  if (count > 0) {
+  if (count > 0 || tail_measured) {
     std::lock_guard<std::mutex> lk(t.mu);
     if (!tune_save_locked(t)) return fail(EMG_EINVAL, "cannot write the EMG_TUNE_CACHE file");
   }

@@ -207,14 +207,15 @@ template <int D, int K, typename R, int MODE, typename TO, bool MASK = false, in
 __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict__ C, const R *__restrict__ u,
                                              const R *__restrict__ f, TO *__restrict__ out, R omega,
                                              double *__restrict__ pslot, long long t,
-                                             const unsigned char *__restrict__ vm = nullptr) {
+                                             const unsigned char *__restrict__ vm = nullptr,
+                                             const int lx = threadIdx.x, const int ly = threadIdx.y) {
   static_assert(!MASK || MODE != MODE_APPLY, "masked passes are residuals and sweeps");
   const Split sp = split_tiles<TX, TY>(g);
   double nrm = 0.0;
   if (t >= sp.sblocks) {
     const long long it = t - sp.sblocks;
     const int tx = int(it % sp.ntx), ty = int((it / sp.ntx) % sp.nty), tz = int(it / ((long long)sp.ntx * sp.nty));
-    const int x = sp.lo[0] + tx * TX + threadIdx.x, y = sp.lo[1] + ty * TY + threadIdx.y, z = sp.lo[2] + tz;
+    const int x = sp.lo[0] + tx * TX + lx, y = sp.lo[1] + ty * TY + ly, z = sp.lo[2] + tz;
     if (x <= sp.hi[0] && y <= sp.hi[1]) {
       // 32-bit node indexing (level sizes are checked at creation: N < 2^31)
       const unsigned m0 = g.m[0], m01 = (unsigned)g.m[0] * g.m[1];
@@ -254,7 +255,7 @@ __device__ __forceinline__ void body_stencil(const Geom &g, const R *__restrict_
       }
     }
   } else {
-    const long long s = t * (TX * TY) + threadIdx.x + TX * threadIdx.y;
+    const long long s = t * (TX * TY) + lx + TX * ly;
     if (s < sp.shell) {
       int p[3];
       shell_node(g, sp, s, p);
@@ -718,11 +719,12 @@ __global__ __launch_bounds__(256) void k_add_correction(long long n, double *__r
 }
 
 // First sweep from a zero initial guess: out = omega f / diag (Dirichlet: f).
-template <int D, int K, typename R>
+template <int D, int K, typename R, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_jacobi_zero(const Geom &g, const R *__restrict__ C, const R *__restrict__ f,
                                                  R *__restrict__ out, R omega, int tx, int ty, int tz,
-                                                 const unsigned char *__restrict__ vm = nullptr) {
-  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y, z = tz;
+                                                 const unsigned char *__restrict__ vm = nullptr,
+                                                 const int lx = threadIdx.x, const int ly = threadIdx.y) {
+  const int x = tx * TX + lx, y = ty * TY + ly, z = tz;
   if (x >= g.m[0] || y >= g.m[1]) return;
   const long long n = ((long long)z * g.m[1] + y) * g.m[0] + x;
   const int p[3] = {x, y, z};
@@ -774,8 +776,9 @@ __device__ __forceinline__ void fw_weights(const Geom &gc, const Geom &gf, const
 // enters; Dirichlet coarse rows get 0.
 template <int D, typename RI, typename RO, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_restrict(const Geom &gf, const Geom &gc, const RI *__restrict__ rf,
-                                              RO *__restrict__ fc, int tx, int ty, int tz) {
-  const int x = tx * TX + threadIdx.x, y = ty * TY + threadIdx.y, z = tz;
+                                              RO *__restrict__ fc, int tx, int ty, int tz,
+                                              const int lx = threadIdx.x, const int ly = threadIdx.y) {
+  const int x = tx * TX + lx, y = ty * TY + ly, z = tz;
   if (x >= gc.m[0] || y >= gc.m[1]) return;
   const long long nc = ((long long)z * gc.m[1] + y) * gc.m[0] + x;
   const int P[3] = {x, y, z};
@@ -875,8 +878,9 @@ __global__ __launch_bounds__(TX * TY) void k_restrict_jz(Geom gf, Geom gc, const
 // Dirichlet fine rows untouched.
 template <int D, typename RC, typename RF, int TX = BX, int TY = BY>
 __device__ __forceinline__ void body_prolong(const Geom &gc, const Geom &gf, const RC *__restrict__ ec,
-                                             RF *__restrict__ uf, int tx, int ty, int tz) {
-  const int x = tx * TX + threadIdx.x, y = ty * TY + threadIdx.y, z = tz;
+                                             RF *__restrict__ uf, int tx, int ty, int tz,
+                                             const int lx = threadIdx.x, const int ly = threadIdx.y) {
+  const int x = tx * TX + lx, y = ty * TY + ly, z = tz;
   if (x >= gf.m[0] || y >= gf.m[1]) return;
   const long long n = ((long long)z * gf.m[1] + y) * gf.m[0] + x;
   const int p[3] = {x, y, z};
@@ -1598,7 +1602,7 @@ namespace emg {
 
 enum {
   BK_JACOBI = 0, BK_JACOBI_NORM = 1, BK_RESID = 2, BK_JZERO = 3, BK_RESTRICT = 4, BK_PROLONG = 5, BK_BOTTOM = 6,
-  BK_COPY = 7, BK_ADDC = 8, BK_RESID_F32 = 9
+  BK_COPY = 7, BK_ADDC = 8, BK_RESID_F32 = 9, BK_TAIL = 10
 };
 
 struct BEnt {
@@ -1612,7 +1616,8 @@ struct BEnt {
   int gx, gy, gz;        // tiles of this entry
   long long tile0;       // first global tile
   long long nparts;      // norm partials of the problem (check entries)
-  int nzc, pad2;         // z-marching entries: chunks per column (tasks = columns x nzc + shell blocks)
+  int nzc;               // z-marching entries: chunks per column (tasks = columns x nzc + shell blocks)
+  int kind;              // coarse-tail entries: the step (BK_*)
 };
 
 struct BList {
@@ -1700,6 +1705,98 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_batch_zm(const 
     else
       body_stencil<3, MOD_ANISO, R, MODE, TO>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
                                               E.partial ? E.partial + (local - nwg) : nullptr, local - nwg);
+  }
+}
+
+// ---- fused coarse tail ----
+// The cycle on a problem's smallest levels (a few hundred nodes each) is one
+// launch: a workgroup of TL_WAVES wavefronts walks the problem's list of
+// steps -- zero-start sweep, sweeps, residual, restriction, bottom solve,
+// interpolation, in the order the per-launch cycle issues them -- with a
+// workgroup barrier between steps.  Each wavefront takes 8 x 8 tiles in turn
+// (lanes: x = lane % 8, y = lane / 8), which on these levels wastes fewer
+// lanes than 64 x 4 tiles; every node is computed by the same per-node body
+// as in the separate launches, so the values are bit-identical, and the
+// launch and dependent-load latency of each separate kernel (5-10 us, most of
+// such a level's time) is paid once.  Entries of a list are grouped by
+// problem (tile0 = the problem's index); workgroups take problems
+// grid-strided, so a fixed grid serves any batch.
+constexpr int TL_X = 8, TL_Y = 8, TL_WAVES = 8, TL_THREADS = 64 * TL_WAVES;
+
+// Rows of e = A^-1 f taken by one wavefront (rows w, w + nw, ...), four at a
+// time with all their loads in flight; per row the sum of body_bottom, term
+// by term and in its order.
+template <typename RI, typename RO>
+__device__ __forceinline__ void tail_bottom(const double *__restrict__ Ainv, int n, const RI *__restrict__ f,
+                                            RO *__restrict__ e, int w, int nw, int lane) {
+  for (int r0 = w; r0 < n; r0 += 4 * nw) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < n; j += 64) {
+      const double fj = double(f[j]);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int row = r0 + q * nw;
+        if (row < n) s[q] += Ainv[(long long)row * n + j] * fj;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int row = r0 + q * nw;
+      const double v = wave_sum(s[q]);
+      if (lane == 0 && row < n) e[row] = RO(v);
+    }
+  }
+}
+
+template <int D, int K, typename R>
+__global__ __launch_bounds__(TL_THREADS) void k_tail(const BList *__restrict__ L, R omega) {
+  const int n = L->n;
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int lx = lane % TL_X, ly = lane / TL_X;
+  for (long long q = blockIdx.x; q < L->total; q += gridDim.x) {
+    int lo = 0, hi = n;   // first entry of problem q
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (L->e[mid].tile0 < q) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= n || (L->e[lo].ctl && L->e[lo].ctl->done)) continue;
+    for (int i = lo; i < n && L->e[i].tile0 == q; i++) {
+      const BEnt &E = L->e[i];
+      const int kind = E.kind;
+      if (kind == BK_JACOBI || kind == BK_RESID) {
+        const long long nb = split_tiles<TL_X, TL_Y>(E.g).blocks;
+        for (long long t = w; t < nb; t += TL_WAVES) {
+          if (kind == BK_JACOBI)
+            body_stencil<D, K, R, MODE_JACOBI, R, false, TL_X, TL_Y>(E.g, (const R *)E.C, (const R *)E.a,
+                                                                   (const R *)E.b, (R *)E.out, omega, nullptr, t,
+                                                                   nullptr, lx, ly);
+          else
+            body_stencil<D, K, R, MODE_RESID, R, false, TL_X, TL_Y>(E.g, (const R *)E.C, (const R *)E.a,
+                                                                  (const R *)E.b, (R *)E.out, R(0), nullptr, t,
+                                                                  nullptr, lx, ly);
+        }
+      } else if (kind == BK_BOTTOM) {
+        tail_bottom<R, R>(E.Ainv, E.nbot, (const R *)E.a, (R *)E.out, w, TL_WAVES, lane);
+      } else {
+        // grid tiles of the level written: the level itself (zero-start
+        // sweep, interpolation onto it) or the coarse level (restriction)
+        const Geom &G = kind == BK_RESTRICT ? E.g2 : E.g;
+        const int gx = (G.m[0] + TL_X - 1) / TL_X, gy = (G.m[1] + TL_Y - 1) / TL_Y;
+        const long long nt = (long long)gx * gy * G.m[2];
+        for (long long t = w; t < nt; t += TL_WAVES) {
+          const int tx = int(t % gx), ty = int((t / gx) % gy), tz = int(t / ((long long)gx * gy));
+          if (kind == BK_JZERO)
+            body_jacobi_zero<D, K, R, TL_X, TL_Y>(E.g, (const R *)E.C, (const R *)E.a, (R *)E.out, omega, tx, ty, tz,
+                                                  nullptr, lx, ly);
+          else if (kind == BK_RESTRICT)
+            body_restrict<D, R, R, TL_X, TL_Y>(E.g, E.g2, (const R *)E.a, (R *)E.out, tx, ty, tz, lx, ly);
+          else
+            body_prolong<D, R, R, TL_X, TL_Y>(E.g2, E.g, (const R *)E.a, (R *)E.out, tx, ty, tz, lx, ly);
+        }
+      }
+      __syncthreads();   // this step's writes are visible to the whole workgroup
+    }
   }
 }
 

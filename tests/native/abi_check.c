@@ -149,6 +149,13 @@ int main(void) {
     fprintf(stderr, "FAIL tuned plan of level 0: zm %d tiles %d %d %d\n", zm, ts, rs, is);
     failures++;
   }
+  int tl = -1;   /* the tuner's choice: 8 x 8 x 9 and the bottom level fused (2) or not (0) */
+  CHECK(emg_tail_levels(p, EMG_FP64, &tl), EMG_OK);
+  if (tl != 0 && tl != 2) {
+    fprintf(stderr, "FAIL fused coarse tail of %d levels, expected 0 or 2\n", tl);
+    failures++;
+  }
+  CHECK(emg_tail_levels(p, 7, &tl), EMG_EINVAL);
   CHECK(emg_solve(p, &o, &st), EMG_OK);   /* a solve on the tuned plan */
   CHECK(emg_autotune(p, EMG_FP64, 0, 0, &ntuned), EMG_EINVAL);
   CHECK(emg_autotune_reset(), EMG_OK);

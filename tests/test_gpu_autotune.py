@@ -1,7 +1,8 @@
 """The autotuner (emg_autotune) picks by measurement, per level: the
 stencil pass (the tile kernel in tiles of 64x4, 64x2, 128x2 or 32x8 nodes,
 or the z-marching pass with some number of chunks per column), and the tile
-shapes of the restriction from the level and of the interpolation onto it.
+shapes of the restriction from the level and of the interpolation onto it;
+per problem, whether the cycle on its smallest levels runs fused.
 Every variant computes the same values node by node, so tuning changes
 timing only.  On a 65^3 polycrystal (periodic x and y: levels 64x64x65 and
 coarser), solves after tuning, and with every variant forced through the
@@ -61,14 +62,16 @@ def test_autotune_changes_timing_only(emg, ctx, tmp_path, monkeypatch):
         after = plans(prob)
         tiles = {p: [prob.level_tiles(l, p) for l in range(nlev)] for p in PRECS}
         table = json.loads(cache.read_text())
-        assert len(table) == 2 * (3 * nlev - 2)
+        assert len(table) == 2 * (3 * nlev - 2 + 1)   # + the fused-tail choice per precision
         for key, v in table.items():
             parts = key.split("/")
             arch, prec, shape, per = parts[:4]
             assert arch.startswith("gfx") and per == "p3"
             p = "fp64" if prec == "fp64" else "mixed"
             lev = [prob.level_shape(l)[0] for l in range(nlev)].index(tuple(int(x) for x in shape.split("x")))
-            if len(parts) == 4:          # stencil pass
+            if parts[4:] == ["tail"]:    # 8x8x9 and 4x4x5 fused, or not
+                assert lev == 0 and v in (0, 2) and prob.tail_levels(p) == v
+            elif len(parts) == 4:        # stencil pass
                 if v > 0:
                     assert after[p][lev] == v and tiles[p][lev][0] == 0
                 else:
