@@ -169,3 +169,39 @@ def test_tail_under_amr(emg, ctx, tmp_path, monkeypatch, dim):
         monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
         emg.autotune_reset()
         prob.close()
+
+
+def test_tail_in_server(emg, ctx, tmp_path, monkeypatch):
+    """Served requests (3 slots, admission at cycle boundaries) whose batched
+    cycles run the fused tail, forced for every domain of the stream, give
+    the displacement and cycle count of their solo solves without it."""
+    specs = [synth.polycrystal_3d(n=17, grains=8, seed=21),
+             synth.inclusion_3d(n=33, seed=5),
+             synth.inclusion_2d(n=65),
+             synth.polycrystal_3d(n=17, grains=8, seed=22),
+             synth.polycrystal_3d(n=33, grains=12, seed=23),
+             synth.inclusion_3d(n=17, seed=6)]
+    opts = dict(rtol=1e-10, max_cycles=400, precision="mixed", check_every=2)
+    cache = tmp_path / "tune.json"
+    emg.autotune_reset()
+    solo, entries = [], {}
+    for sp in specs:
+        p = emg.Problem.from_spec(ctx, sp)
+        st = p.solve(**opts)
+        solo.append((st["cycles"], p.displacement()))
+        entries.update(tail_keys(p, sp, candidate(p)))
+        p.close()
+    try:
+        force(emg, monkeypatch, cache, entries)
+        print(f"[gpu] tail server {len(specs)} requests", flush=True)
+        srv = emg.Server(ctx, max_slots=3, **opts)
+        tickets = [srv.submit(sp) for sp in specs]
+        for sp, t, (c, u) in zip(specs, tickets, solo):
+            got, info = srv.wait(t)
+            assert info["done"] and info["status"] == emg.EMG_OK, (sp.name, info)
+            assert info["cycles"] == c, (sp.name, info["cycles"], c)
+            assert np.array_equal(got.reshape(u.shape), u), sp.name
+        srv.close()
+    finally:
+        monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
+        emg.autotune_reset()
