@@ -547,23 +547,39 @@ emg_status setup(emg_problem *p) {
                        p->lv[l].C64);
   }
   HIPCK(hipGetLastError());
-  // coarsest operator: assemble [A | I], invert by Gauss-Jordan with partial pivoting
+  // coarsest operator: assemble [A | I], invert by blocked Gauss-Jordan with partial pivoting
   const Level &B = p->lv[L - 1];
   const int n = p->nbot;
-  double *M = nullptr;   // two n x 2n buffers: Gauss-Jordan steps go back and forth
-  HIPCK(hipMallocAsync((void **)&M, sizeof(double) * 4 * (size_t)n * n, p->stream));
+  const int pb = n * 16 <= GJB_LDS ? 16 : 12;   // panel width (n <= kMaxBottom = GJB_LDS / 12)
+  static_assert(kMaxBottom * 12 <= GJB_LDS, "coarsest level too large for a 12-column panel in LDS");
+  double *M = nullptr;   // two n x 2n buffers (panels go back and forth), the panel transform, the permutation
+  HIPCK(hipMallocAsync((void **)&M, sizeof(double) * (4 * (size_t)n * n + (size_t)n * pb + (n + 1) / 2), p->stream));
   double *Mb[2] = {M, M + 2 * (size_t)n * n};
+  double *Np = M + 4 * (size_t)n * n;
+  int *pi = (int *)(Np + (size_t)n * pb);
   dispatch(p->D, p->K, [&](auto Dc, auto Kc) {
     constexpr int D = decltype(Dc)::value, K = decltype(Kc)::value;
     hipLaunchKernelGGL((k_bottom_assemble<D, K>), dim3((n + 255) / 256, n), dim3(256), 0, p->stream, B.g, B.C64, Mb[0],
                        n);
   });
   hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, p->stream, 1LL, p->status, 0);
-  for (int k = 0; k < n; k++)
-    hipLaunchKernelGGL(k_gj_step, dim3(n), dim3(256), 0, p->stream, (const double *)Mb[k & 1], Mb[(k + 1) & 1], n, k,
-                       p->status);
+  int cur = 0;
+  for (int k = 0; k < n; k += pb) {
+    const int b = std::min(pb, n - k);
+    if (pb == 16)
+      hipLaunchKernelGGL(k_gjb_panel<16>, dim3(1), dim3(1024), 0, p->stream, (const double *)Mb[cur], n, k, b, Np, pi,
+                         p->status);
+    else
+      hipLaunchKernelGGL(k_gjb_panel<12>, dim3(1), dim3(1024), 0, p->stream, (const double *)Mb[cur], n, k, b, Np, pi,
+                         p->status);
+    const long long cols = 2LL * n - k - b;   // columns right of the panel
+    hipLaunchKernelGGL(k_gjb_update, dim3((unsigned)((cols + 255) / 256), (unsigned)((n + GJB_ROWS - 1) / GJB_ROWS)),
+                       dim3(256), 0,
+                       p->stream, (const double *)Mb[cur], Mb[cur ^ 1], n, k, b, (const double *)Np, (const int *)pi);
+    cur ^= 1;
+  }
   hipLaunchKernelGGL(k_gj_extract, dim3((unsigned)(((long long)n * n + 255) / 256)), dim3(256), 0, p->stream,
-                     Mb[n & 1], n, p->Ainv);
+                     Mb[cur], n, p->Ainv);
   HIPCK(hipGetLastError());
   int st = 0;
   HIPCK(hipMemcpyAsync(&st, p->status, sizeof(int), hipMemcpyDeviceToHost, p->stream));

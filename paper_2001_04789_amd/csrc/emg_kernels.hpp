@@ -1265,47 +1265,173 @@ __global__ __launch_bounds__(256) void k_bottom_assemble(Geom g, const double *_
   M[r * w + nunk + q] = (r == q) ? 1.0 : 0.0;
 }
 
-// Gauss-Jordan step k in one launch, out of place (M -> Mo, so no row is
-// read after another workgroup rewrote it): one workgroup per row finds the
-// pivot row pr of column k (largest |M[i][k]|, i >= k, lowest index on ties),
-// then writes its row of the swapped, scaled and eliminated matrix: row k =
-// M[pr] / M[pr][k]; row pr (if pr != k) and every other row i: M[i][j] -
-// M[i][k] (M[pr][j] / M[pr][k]) for j > k, column k and the columns left of it
-// unchanged (the right half ends as the inverse).  status[0] = 1 on a zero
-// pivot.
-__global__ __launch_bounds__(256) void k_gj_step(const double *__restrict__ M, double *__restrict__ Mo, int n, int k,
-                                                 int *status) {
-  __shared__ double bv[256];
-  __shared__ int bi[256];
-  const int t = threadIdx.x, row = blockIdx.x;
+// Blocked Gauss-Jordan on [A | I] (n x 2n, row stride 2n), panels of b
+// columns of the left half.  k_gjb_panel (one workgroup) runs the in-place
+// Gauss-Jordan steps with partial pivoting (largest |value| among the rows
+// not yet pivoted, lowest index on ties) on the panel's n x b values in LDS.
+// Those steps turn the panel into N, the transform they apply to any other
+// column x whose rows have been permuted alike: the panel's block rows become
+// N_block x_block, every other row i becomes x_i + N_i x_block.  It writes N
+// and the row permutation pi (row i of the swapped matrix is row pi[i] of the
+// input).  k_gjb_update applies that to every column right of the panel,
+// out of place.  Per panel two launches instead of b; the arithmetic is the
+// same elimination in another order.  status[0] = 1 on a zero pivot.
+constexpr int GJB_LDS = 18432;   // doubles of panel in LDS: n * b <= this
+
+// Panel of b <= B columns in LDS at row stride B; thread t owns column
+// t % B of the rows t / B + RS m.
+template <int B>
+__global__ __launch_bounds__(1024) void k_gjb_panel(const double *__restrict__ W, int n, int k, int b,
+                                                    double *__restrict__ Nout, int *__restrict__ pi,
+                                                    int *__restrict__ status) {
+  constexpr int RS = 1024 / B;   // rows per pass
+  __shared__ double Q[GJB_LDS];
+  __shared__ double cv[512];   // pivot candidates of threads 0..511
+  __shared__ int ci[512];
+  __shared__ int sp[1536];   // the permutation (written to pi at the end)
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int q = t % B, rg = t / B;
+  const bool own = rg < RS && q < b;
   const long long w = 2LL * n;
-  double best = -1.0;
-  int arg = k;
-  for (int i = k + t; i < n; i += 256) {
-    const double v = fabs(M[i * w + k]);
-    if (v > best) { best = v; arg = i; }
+  constexpr int MR = (1536 + RS - 1) / RS;   // passes of rows (n <= 1536), unrolled so the loads overlap
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < MR; m++) {
+      const int i = rg + m * RS;
+      if (i < n) Q[i * B + q] = W[(long long)i * w + k + q];
+    }
   }
-  bv[t] = best;
-  bi[t] = arg;
+  for (int i = t; i < n; i += 1024) sp[i] = i;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      if (bv[t + s] > bv[t] || (bv[t + s] == bv[t] && bi[t + s] < bi[t])) { bv[t] = bv[t + s]; bi[t] = bi[t + s]; }
+  for (int s = 0; s < b; s++) {
+    const int c = k + s;
+    // pivot: largest |value| of column s among rows >= c, lowest row on ties;
+    // candidates of 512 threads, reduced by one wavefront
+    if (t < 512) {
+      double best = -1.0;
+      int arg = c;
+      for (int i = c + t; i < n; i += 512) {
+        const double v = fabs(Q[i * B + s]);
+        if (v > best) {
+          best = v;
+          arg = i;
+        }
+      }
+      cv[t] = best;
+      ci[t] = arg;
     }
     __syncthreads();
+    if (wv == 0) {
+      double best = cv[lane];
+      int arg = ci[lane];
+      for (int h = 1; h < 8; h++) {
+        const double v = cv[lane + 64 * h];
+        const int i = ci[lane + 64 * h];
+        if (v > best || (v == best && i < arg)) {
+          best = v;
+          arg = i;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double bv = __shfl_xor(best, o);
+        const int bi = __shfl_xor(arg, o);
+        if (bv > best || (bv == best && bi < arg)) {
+          best = bv;
+          arg = bi;
+        }
+      }
+      if (lane == 0) ci[0] = arg;
+    }
+    __syncthreads();
+    const int r = ci[0];
+    if (r != c && t < b) {
+      const double a = Q[c * B + t];
+      Q[c * B + t] = Q[r * B + t];
+      Q[r * B + t] = a;
+    }
+    if (r != c && t == 0) {
+      const int a = sp[c];
+      sp[c] = sp[r];
+      sp[r] = a;
+    }
+    __syncthreads();
+    const double piv = Q[c * B + s];
+    if (t == 0 && piv == 0.0) status[0] = 1;
+    const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+    // other rows, other columns, with the pivot row scaled by inv
+    if (own && q != s) {   // chunks of 8 rows: all reads of a chunk in flight before its writes
+      const double rc = Q[c * B + q] * inv;
+      constexpr int CH = 8;
+#pragma unroll
+      for (int m0 = 0; m0 < MR; m0 += CH) {
+        double xs[CH], xq[CH];
+#pragma unroll
+        for (int h = 0; h < CH; h++) {
+          const int i = rg + (m0 + h) * RS;
+          xs[h] = m0 + h < MR && i < n ? Q[i * B + s] : 0.0;
+          xq[h] = m0 + h < MR && i < n ? Q[i * B + q] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < CH; h++) {
+          const int i = rg + (m0 + h) * RS;
+          if (m0 + h < MR && i < n && i != c) Q[i * B + q] = xq[h] - xs[h] * rc;
+        }
+      }
+    }
+    __syncthreads();
+    // pivot row scaled, pivot column -value / pivot, 1 / pivot at the pivot
+    for (int i = t; i < n; i += 1024)
+      if (i != c) Q[i * B + s] = -Q[i * B + s] * inv;
+    if (t < b) Q[c * B + t] = t == s ? inv : Q[c * B + t] * inv;
+    __syncthreads();
   }
-  const int pr = bi[0];
-  const double piv = M[pr * w + k];
-  if (row == 0 && t == 0 && piv == 0.0) status[0] = 1;
-  const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
-  const int src = row == k ? pr : (row == pr ? k : row);   // row of M that lands in this row
-  const double mik = M[src * w + k];
-  for (long long j = t; j < w; j += 256) {
-    const double a = M[src * w + j];
-    double v;
-    if (row == k) v = j >= k ? a * inv : a;
-    else v = j > k ? a - mik * (M[pr * w + j] * inv) : a;
-    Mo[row * w + j] = v;
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < MR; m++) {
+      const int i = rg + m * RS;
+      if (i < n) Nout[(long long)i * b + q] = Q[i * B + q];
+    }
+  }
+  for (int i = t; i < n; i += 1024) pi[i] = sp[i];
+}
+
+// Columns j >= k + b of W2 from W: y = the b pivot rows of column j after
+// the permutation; block rows N_block y, other rows x_pi[i] + N_i y.  Grid:
+// x = 256-column blocks, y = 16-row chunks (loads of a chunk in flight
+// together).
+constexpr int GJB_ROWS = 16;
+__global__ __launch_bounds__(256) void k_gjb_update(const double *__restrict__ W, double *__restrict__ W2, int n,
+                                                    int k, int b, const double *__restrict__ N,
+                                                    const int *__restrict__ pi) {
+  __shared__ double Ns[GJB_ROWS * 16];
+  __shared__ int ps[GJB_ROWS];
+  const int i0 = blockIdx.y * GJB_ROWS;
+  const long long w = 2LL * n;
+  for (int e = threadIdx.x; e < GJB_ROWS * b; e += 256) {
+    const int i = i0 + e / b;
+    Ns[e] = i < n ? N[(long long)i * b + e % b] : 0.0;
+  }
+  if (threadIdx.x < GJB_ROWS) ps[threadIdx.x] = i0 + (int)threadIdx.x < n ? pi[i0 + threadIdx.x] : 0;
+  __syncthreads();
+  const long long j = (long long)k + b + (long long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= w) return;
+  double y[16], x[GJB_ROWS];
+#pragma unroll
+  for (int s = 0; s < 16; s++) y[s] = s < b ? W[(long long)pi[k + s] * w + j] : 0.0;
+#pragma unroll
+  for (int r = 0; r < GJB_ROWS; r++) {
+    const int i = i0 + r;
+    x[r] = (i < n && (i < k || i >= k + b)) ? W[(long long)ps[r] * w + j] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < GJB_ROWS; r++) {
+    const int i = i0 + r;
+    if (i >= n) break;
+    double acc = x[r];
+#pragma unroll
+    for (int s = 0; s < 16; s++)
+      if (s < b) acc += Ns[r * b + s] * y[s];
+    W2[(long long)i * w + j] = acc;
   }
 }
 

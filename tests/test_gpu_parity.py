@@ -380,3 +380,37 @@ def test_warm_start_from_perturbed_solution(emg, ctx, precision):
     print(f"[gpu] warm start {precision}: cycles {st['cycles']} (cold {cold['cycles']}) err {err:.2e}", flush=True)
     assert st["converged"] and st["rel_res"] <= 1e-10 and err <= 1e-8
     prob.close()
+
+
+@pytest.mark.parametrize("n,kind,bc", [
+    ((49, 49, 49), "iso", ("traction", "traction", "traction", "traction", "dirichlet", "traction")),   # 7^3: 1029
+    ((49, 49, 49), "aniso", ("periodic", "periodic", "periodic", "periodic", "dirichlet", "dirichlet")),   # 6x6x7: 756
+    ((57, 57, 57), "iso", ("dirichlet", "traction", "traction", "traction", "traction", "traction")),   # 8^3: 1536
+])
+def test_large_bottom_inverse(emg, ctx, n, kind, bc):
+    """Domains whose coarsening stops early keep large coarsest levels (up to
+    the 1536-unknown limit); the blocked Gauss-Jordan inverse (panels of 16,
+    or 12 at 1536 unknowns) solves them like a dense LU solve of the oracle's
+    coarsest operator."""
+    spec = synth.random_problem(3, n, bc, kind, seed=5, with_body=True)
+    prob = emg.Problem.from_spec(ctx, spec)
+    g0 = oracle.Grid.of(spec)
+    grids = oracle.hierarchy(g0)
+    Cs = [spec.C]
+    for l in range(1, len(grids)):
+        Cs.append(oracle.coarsen_moduli(grids[l - 1], grids[l], Cs[-1]))
+    gb = grids[-1]
+    nb = 3 * int(np.prod(gb.m))
+    print(f"[gpu] bottom inverse {n} {kind}: {nb} unknowns", flush=True)
+    assert nb in (1029, 756, 1536)
+    rng = np.random.default_rng(11)
+    A = oracle.dense_matrix(gb, Cs[-1])
+    for _ in range(2):
+        fb = rng.standard_normal(gb.shape(3))
+        eb_ref = np.linalg.solve(A, fb.ravel()).reshape(fb.shape)
+        eb = torch.full(gb.shape(3), float("nan"), dtype=torch.float64, device=DEV)
+        prob.level_bottom_solve(dev(fb), eb)
+        assert rel_err(host(eb), eb_ref) <= 1e-9
+    st = prob.solve(rtol=1e-10, max_cycles=300)
+    assert st["converged"]
+    prob.close()
