@@ -84,6 +84,9 @@ def parse():
                     "(the served stream fixes no sweep count; V(4,4) serves more solves/s than V(2,2))")
     ap.add_argument("--serve-inner", type=int, default=2, help="FP32 cycles per FP64 refinement step of the "
                     "served solves")
+    ap.add_argument("--serve-check-every", type=int, default=1,
+                    help="refinement steps per graph replay of the served batch (admission and retirement "
+                         "happen between replays)")
     ap.add_argument("--amr", type=int, default=1, help="run the AMR blocks (0 = skip)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
@@ -364,7 +367,8 @@ def serve(emg, torch, ctx, args, count, rate, pool, gen_s):
     outs = [out_for(pool[(r.kind, r.n, r.variant)][0]) for r in trace]
     torch.cuda.synchronize()
     srv = emg.Server(ctx, max_slots=args.serve_slots, rtol=1e-10, max_cycles=400, precision="mixed",
-                     nu1=args.serve_nu, nu2=args.serve_nu, inner_cycles=args.serve_inner)
+                     nu1=args.serve_nu, nu2=args.serve_nu, inner_cycles=args.serve_inner,
+                     check_every=args.serve_check_every)
     passes = {}
     for name in ("cold", "warm"):
         base = srv.now()
@@ -389,6 +393,7 @@ def serve(emg, torch, ctx, args, count, rate, pool, gen_s):
     srv.close()
     out = {"requests": len(trace), "rate_req_per_s": rate, "slots": args.serve_slots, "precision": "mixed",
            "smoothing": f"V({args.serve_nu},{args.serve_nu})", "inner_cycles": args.serve_inner,
+           "check_every": args.serve_check_every,
            "offered_span_s": trace[-1].t,
            "inputs": f"{len(trace)} distinct inputs seeded from the request ids, resident in HBM "
                      f"(pool generated in {gen_s:.0f} s on the host)",
