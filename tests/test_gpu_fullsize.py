@@ -4,7 +4,8 @@ through the same C ABI calls and launch configuration as bench.py.
 
 At these sizes the oracle cannot run whole solves in seconds, so it checks:
   * one operator application / residual / Jacobi sweep of the finest level,
-    element by element, on a random field (129^3 polycrystal);
+    element by element, on a random field (129^3 polycrystal; 257^3
+    polycrystal with the sphere);
   * the GPU solutions of FP64 and mixed-precision solves through the
     oracle's own residual: relative residual <= 1.2e-10 (stopping test
     1e-10 plus the rounding of the recomputation), and the mixed solution
@@ -75,17 +76,25 @@ def check_solves(emg, ctx, spec, label):
     return out
 
 
-def test_polycrystal129_finest_level_steps(emg, ctx):
-    """129^3 polycrystal: the finest-level operator, residual and Jacobi
-    sweep (interior tiles and boundary shell) against the oracle, element by
-    element, in FP64 and FP32."""
-    spec = synth.polycrystal_3d(n=129, grains=16, seed=2002)
+@pytest.mark.parametrize("n", [129, 257])
+def test_polycrystal_finest_level_steps(emg, ctx, n):
+    """Finest-level operator, residual and Jacobi sweep (z-marching columns
+    and boundary shell, in the launch configuration the bench times: 4
+    chunks per column at 129^3, one 255-plane chunk at 257^3) against the
+    oracle, element by element, in FP64 and FP32: the 129^3 polycrystal and
+    the 257^3 polycrystal with the stiff eigenstrained sphere."""
+    if n == 129:
+        spec = synth.polycrystal_3d(n=129, grains=16, seed=2002)
+    else:
+        print("[gpu] generating the 257^3 polycrystal with a sphere", flush=True)
+        spec = synth.polycrystal_3d(n=257, grains=64, seed=2003, inclusion=(3.0, 2e-3))
     g = oracle.Grid.of(spec)
     prob = emg.Problem.from_spec(ctx, spec)
+    assert prob.level_zmarch(0, "fp64") == (4 if n == 129 else 1)
     rng = np.random.default_rng(11)
     u = 1e-3 * rng.standard_normal(g.shape(3))
     f = rng.standard_normal(g.shape(3))
-    print("[gpu] 129^3 polycrystal level steps: oracle", flush=True)
+    print(f"[gpu] {n}^3 polycrystal level steps: oracle", flush=True)
     ref = {"apply": oracle.apply(g, spec.C, u), "residual": oracle.residual(g, spec.C, u, f),
            "jacobi": oracle.jacobi(g, spec.C, u, f, 2.0 / 3.0)}
     for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("mixed", torch.float32, 2e-5)):
