@@ -221,7 +221,9 @@ emg_status emg_level_jacobi(emg_problem *p, int level, int precision, double ome
 emg_status emg_level_restrict(emg_problem *p, int level, int precision, const void *r_fine, void *f_coarse);
 /* u_fine (on `level`) += interpolation of e_coarse (on level+1); Dirichlet rows untouched */
 emg_status emg_level_prolong_add(emg_problem *p, int level, int precision, const void *e_coarse, void *u_fine);
-/* exact FP64 solve on the coarsest level: e = A^-1 f */
+/* exact FP64 solve on the coarsest level: e = A^-1 f, A^-1 the dense inverse built at setup by
+ * blocked Gauss-Jordan elimination with partial pivoting (the bottom of the cycle is not specified
+ * by the paper; a direct FP64 solve keeps it exact in both precisions) */
 emg_status emg_level_bottom_solve(emg_problem *p, int precision, const void *f, void *e);
 
 /* ---- ragged batches ----
