@@ -334,10 +334,10 @@ bool tune_save_locked(const TuneTable &t) {
 // least 8 planes per chunk; tile shapes -1..-3; a table value outside that
 // range is ignored.
 bool zm_valid(const Geom &g, int nzc, int kind = MOD_ANISO) {
+  (void)kind;   // both moduli kinds have a z-marching pass
   const Split sp = split_of(g);
   if (nzc <= 0) return nzc > -TS_COUNT;
-  return kind == MOD_ANISO && g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 &&
-         nzc <= sp.ntz / 8;
+  return g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 && nzc <= sp.ntz / 8;
 }
 
 bool tune_find(int device, int rbytes, const Geom &g, int *nzc, int kind = MOD_ANISO, const char *what = "") {
@@ -356,9 +356,11 @@ bool tune_find(int device, int rbytes, const Geom &g, int *nzc, int kind = MOD_A
 
 // Chunks per column of the z-marching pass for a level (0: tile kernel): the
 // variant under measurement, else the tuned choice, else the cost model,
-// which takes 3D anisotropic levels with enough columns x chunks of >= 8
-// planes to give every CU a workgroup (FP64: one per CU, FP32: two); smaller
-// levels keep the tile kernel, which spreads them over more workgroups.
+// which takes 3D levels with enough columns x chunks of >= 8 planes to give
+// every CU its resident workgroups (anisotropic FP64: one per CU, FP32: two;
+// isotropic, with a third of the LDS and fewer registers: twice that);
+// smaller levels keep the tile kernel, which spreads them over more
+// workgroups.
 // The stencil-pass variant of a level: > 0 z-march chunks, 0 the tile
 // kernel in 64 x 4 tiles, < 0 the tile kernel in tile shape -v.
 template <typename R>
@@ -366,8 +368,8 @@ int stencil_plan(const emg_problem *p, const Geom &g) {
   if (p->force_stencil) return p->force_v;
   int tuned;
   if (tune_find(p->ctx->device, (int)sizeof(R), g, &tuned, p->K)) return tuned;
-  if (p->D != 3 || p->K != MOD_ANISO) return 0;
-  const int target = sizeof(R) == 8 ? 256 : 512;
+  if (p->D != 3) return 0;
+  const int target = (sizeof(R) == 8 ? 256 : 512) * (p->K == MOD_ISO ? 2 : 1);
   const int nzc = zm_chunks(g, target);
   if (nzc == 0) return 0;
   const Split sp = split_of(g);
@@ -431,8 +433,12 @@ void launch_stencil(emg_problem *p, const Level &L, const R *u, const R *f, TO *
   if (nzc > 0) {
     const Split sp = split_of(L.g);
     const unsigned blocks = (unsigned)((long long)sp.ntx * sp.nty * nzc + sp.sblocks);
-    hipLaunchKernelGGL((k_stencil_zm<R, MODE, TO>), dim3(blocks), kBlock, 0, p->stream, L.g, moduli<R>(L), u, f, out,
-                       omega, partial, ctl, nzc);
+    if (p->K == MOD_ISO)
+      hipLaunchKernelGGL((k_stencil_zm<R, MODE, TO, MOD_ISO>), dim3(blocks), kBlock, 0, p->stream, L.g, moduli<R>(L),
+                         u, f, out, omega, partial, ctl, nzc, (float *)nullptr, 0.0f);
+    else
+      hipLaunchKernelGGL((k_stencil_zm<R, MODE, TO>), dim3(blocks), kBlock, 0, p->stream, L.g, moduli<R>(L), u, f,
+                         out, omega, partial, ctl, nzc, (float *)nullptr, 0.0f);
     return;
   }
   const int ts = MODE == MODE_APPLY ? TS_64x4 : tile_plan<R>(p, L.g);
@@ -920,9 +926,9 @@ void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc)
   const int eb = mixed_result_buf(p, nu1, nu2);
   hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
                      p->stream, nd0, L0.u64[0], L0.u32[eb], p->ctl);
-  // on z-marching levels the residual pass also writes the FP32 cycle's
-  // first sweep from zero (into u32[0]), which the cycle then skips
-  const int nzc = zm_plan<double>(p, L0.g);
+  // on anisotropic z-marching levels the residual pass also writes the FP32
+  // cycle's first sweep from zero (into u32[0]), which the cycle then skips
+  const int nzc = p->K == MOD_ANISO ? zm_plan<double>(p, L0.g) : 0;
   if (nzc > 0) {
     const Split sp = split_of(L0.g);
     const unsigned blocks = (unsigned)((long long)sp.ntx * sp.nty * nzc + sp.sblocks);
@@ -1646,23 +1652,30 @@ void launch_batch_kind(hipStream_t st, int kind, bool f32, const BList *L, doubl
 }
 
 // Batched z-marching pass: FP64 fills the CUs with one workgroup each, FP32
-// with two (LDS and registers); tasks are taken grid-strided.
-void launch_batch_zm(hipStream_t st, int kind, bool f32, const BList *L, double omega) {
-  const dim3 g64(256), g32(512), blk(BX, BY, 1);
+// with two, isotropic levels with twice that (LDS and registers); tasks are
+// taken grid-strided.
+template <int K>
+void launch_batch_zm_k(hipStream_t st, int kind, bool f32, const BList *L, double omega) {
+  constexpr int mul = K == MOD_ISO ? 2 : 1;
+  const dim3 g64(256 * mul), g32(512 * mul), blk(BX, BY, 1);
   switch (kind) {
     case BK_JACOBI:
     case BK_JACOBI_NORM:
-      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_JACOBI, float>), g32, blk, 0, st, L, (float)omega);
-      else hipLaunchKernelGGL((k_batch_zm<double, MODE_JACOBI, double>), g64, blk, 0, st, L, omega);
+      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_JACOBI, float, K>), g32, blk, 0, st, L, (float)omega);
+      else hipLaunchKernelGGL((k_batch_zm<double, MODE_JACOBI, double, K>), g64, blk, 0, st, L, omega);
       break;
     case BK_RESID:
-      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_RESID, float>), g32, blk, 0, st, L, 0.0f);
-      else hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, double>), g64, blk, 0, st, L, 0.0);
+      if (f32) hipLaunchKernelGGL((k_batch_zm<float, MODE_RESID, float, K>), g32, blk, 0, st, L, 0.0f);
+      else hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, double, K>), g64, blk, 0, st, L, 0.0);
       break;
     case BK_RESID_F32:
-      hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, float>), g64, blk, 0, st, L, 0.0);
+      hipLaunchKernelGGL((k_batch_zm<double, MODE_RESID, float, K>), g64, blk, 0, st, L, 0.0);
       break;
   }
+}
+void launch_batch_zm(hipStream_t st, int kind, bool f32, int K, const BList *L, double omega) {
+  if (K == MOD_ISO) launch_batch_zm_k<MOD_ISO>(st, kind, f32, L, omega);
+  else launch_batch_zm_k<MOD_ANISO>(st, kind, f32, L, omega);
 }
 
 // Device copy of a plan's work lists (capacity-sized, fixed addresses): the
@@ -1774,7 +1787,7 @@ void launch_plan(const BatchPlan &plan, const BatchDev &dev, hipStream_t st, dou
       continue;
     }
     if (s.zm) {
-      launch_batch_zm(st, s.kind, s.f32, L, omega);
+      launch_batch_zm(st, s.kind, s.f32, s.K, L, omega);
       continue;
     }
     if (s.kind == BK_TAIL) {

@@ -665,11 +665,159 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
   finish(ze - 1, cz);
 }
 
-// z-marching interior workgroups first (nwg of them), then the shell blocks
-// of body_stencil; one launch covers the level.  FP64 needs more than 256
-// registers (one workgroup per CU, which its 95 KB of LDS implies anyway);
-// FP32 fits two workgroups per CU.
+// z-marching pass over an isotropic 3D level.  The workgroup keeps a ring
+// of three planes (z-1, z, z+1) of lambda, mu and the displacement in LDS,
+// each with the one-node x/y halo, and computes plane z with interior_rows
+// itself, addressing the ring by node index plus per-axis offsets (x: 1, y:
+// a row, z: the distance between ring slots), so every row is the tile
+// kernel's arithmetic on the same values, bit for bit.  Per node and plane
+// about 13 global loads (lambda, mu, displacement of the next plane with its
+// halo, right-hand side) instead of about 74.  Norm partials go to the tile
+// kernel's 64 x 4 slots.  LDS slot layout: ((slot * 3 + component) * HP +
+// position), lambda and mu in components 0 and 1 of the moduli ring.
 template <typename R, int MODE, typename TO>
+__device__ __forceinline__ void zm_column_iso(const Geom &g, const Split &sp, const R *__restrict__ C,
+                                              const R *__restrict__ u, const R *__restrict__ f, TO *__restrict__ out,
+                                              R omega, double *__restrict__ partial, int nzc, unsigned w,
+                                              R *__restrict__ sC, R *__restrict__ sU) {
+  constexpr int TX = BX, TY = BY, HX = ZM_HX, HY = ZM_HY, HP = ZM_HP, NH = ZM_NH, PL = 3 * HP;
+  constexpr int HW = (NH + 63) / 64;
+  const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TX + tx;
+  const int wave = __builtin_amdgcn_readfirstlane(ty);
+  const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
+  const unsigned L = nwg % kXCD == 0 ? (w % kXCD) * (nwg / kXCD) + w / kXCD : w;
+  const int chunk = L % nzc, col = L / nzc;
+  const int cx = col % sp.ntx, cy = col / sp.ntx;
+  const int x0 = sp.lo[0] + cx * TX, y0 = sp.lo[1] + cy * TY;
+  const int nz = sp.hi[2] - sp.lo[2] + 1;
+  const int zs = sp.lo[2] + (int)((long long)nz * chunk / nzc);
+  const int ze = sp.lo[2] + (int)((long long)nz * (chunk + 1) / nzc);
+  const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
+  auto fix = [](int c, int m, int per) {
+    if (per) {
+      c %= m;
+      return c < 0 ? c + m : c;
+    }
+    return c < 0 ? 0 : (c > m - 1 ? m - 1 : c);
+  };
+  const bool inbox = x0 + tx <= sp.hi[0] && y0 + ty <= sp.hi[1];
+  const int p0 = (ty + 1) * HX + tx + 1;
+  const unsigned r0 = (unsigned)fix(y0 + ty, m1, g.per[1]) * m0 + fix(x0 + tx, m0, g.per[0]);
+  int p1 = p0;
+  unsigned r1 = r0;
+  if (t < NH) {
+    int hx, hy;
+    if (t < HX) {
+      hy = 0;
+      hx = t;
+    } else if (t < 2 * HX) {
+      hy = HY - 1;
+      hx = t - HX;
+    } else {
+      const int q = t - 2 * HX;
+      hy = 1 + q / 2;
+      hx = (q & 1) ? HX - 1 : 0;
+    }
+    p1 = hy * HX + hx;
+    r1 = (unsigned)fix(y0 + hy - 1, m1, g.per[1]) * m0 + fix(x0 + hx - 1, m0, g.per[0]);
+  }
+  const bool halo = wave < HW;
+  const unsigned P = (unsigned)m0 * m1;
+  const long long N = g.N, SC = g.SC;
+  auto plane = [&](int z) {
+    if (g.per[2]) z = z < 0 ? z + m2 : (z >= m2 ? z - m2 : z);
+    return (unsigned)z * P;
+  };
+  R i2h[3], ih2[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    i2h[a] = R(0.5 / g.h[a]);
+    ih2[a] = R(1.0 / (g.h[a] * g.h[a]));
+  }
+  // a plane in flight: lambda, mu, displacement at the node and the halo position
+  R xc0[2], xc1[2], xu0[3], xu1[3], xf[3];
+  auto issue = [&](int zn) {
+    const unsigned o = plane(zn);
+#pragma unroll
+    for (int c = 0; c < 2; c++) xc0[c] = ld(C + c * SC, o + r0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) xu0[k] = ld(u + k * N, o + r0);
+    if (halo) {
+#pragma unroll
+      for (int c = 0; c < 2; c++) xc1[c] = ld(C + c * SC, o + r1);
+#pragma unroll
+      for (int k = 0; k < 3; k++) xu1[k] = ld(u + k * N, o + r1);
+    }
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int c = 0; c < 2; c++) sC[slot * PL + c * HP + p0] = xc0[c];
+#pragma unroll
+    for (int k = 0; k < 3; k++) sU[slot * PL + k * HP + p0] = xu0[k];
+    if (halo) {
+#pragma unroll
+      for (int c = 0; c < 2; c++) sC[slot * PL + c * HP + p1] = xc1[c];
+#pragma unroll
+      for (int k = 0; k < 3; k++) sU[slot * PL + k * HP + p1] = xu1[k];
+    }
+  };
+  struct RingU {   // displacement accessor on the LDS ring: component k at index i
+    const R *s;
+    __device__ __forceinline__ R operator()(int k, int i) const { return s[k * HP + i]; }
+  };
+  int sm = 0, s0 = 1, sp1 = 2;   // ring slots of planes z-1, z, z+1
+  issue(zs - 1);
+  store(sm);
+  issue(zs);
+  store(s0);
+  issue(zs + 1);
+  store(sp1);
+  __syncthreads();
+  for (int z = zs; z < ze; z++) {
+    if (z + 1 < ze) issue(z + 2);
+    if constexpr (MODE != MODE_APPLY) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) xf[k] = ld(f + k * N, plane(z) + r0);
+    }
+    const int n = s0 * PL + p0;
+    const int om[3] = {-1, -HX, (sm - s0) * PL}, op[3] = {1, HX, (sp1 - s0) * PL};
+    R acc[3], dg[3], uc[3];
+    interior_rows<3, MOD_ISO, R, RingU, int>(sC, HP, RingU{sU}, n, om, op, i2h, ih2, acc, dg, nullptr, 0, nullptr, uc);
+    double nrm = 0.0;
+    const unsigned o = plane(z) + r0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      if (inbox) {
+        TO *__restrict__ oi = (TO *)((char *)(out + i * N) + o * (unsigned)sizeof(TO));
+        if constexpr (MODE == MODE_APPLY) {
+          *oi = TO(acc[i]);
+        } else {
+          const R r = xf[i] - acc[i];
+          *oi = MODE == MODE_RESID ? TO(r) : TO(uc[i] + omega * r / dg[i]);
+          nrm += double(r) * double(r);
+        }
+      }
+    }
+    if (partial)
+      block_sum_256(nrm, partial + sp.sblocks + ((long long)(z - sp.lo[2]) * sp.nty + cy) * sp.ntx + cx);
+    __syncthreads();
+    if (z + 1 < ze) {
+      store(sm);
+      const int t0 = sm;
+      sm = s0;
+      s0 = sp1;
+      sp1 = t0;
+    }
+    __syncthreads();
+  }
+}
+
+// z-marching interior workgroups first (nwg of them), then the shell blocks
+// of body_stencil; one launch covers the level.  Anisotropic FP64 needs more
+// than 256 registers (one workgroup per CU, which its 95 KB of LDS implies
+// anyway); FP32 fits two workgroups per CU.  The isotropic pass (57 KB of
+// LDS in FP64, about 210 registers) fits two per CU, four in FP32.
+template <typename R, int MODE, typename TO, int K = MOD_ANISO>
 __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom g, const R *__restrict__ C,
                                                                            const R *__restrict__ u,
                                                                            const R *__restrict__ f,
@@ -679,16 +827,20 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom
                                                                            float *__restrict__ xz = nullptr,
                                                                            float omegaf = 0.0f) {
   if (skip(ctl)) return;
-  __shared__ R sC[21 * ZM_HP];
+  __shared__ R sC[(K == MOD_ISO ? 9 : 21) * ZM_HP];
   __shared__ R sU[9 * ZM_HP];
   const Split sp = split_of(g);
   const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
   if (blockIdx.x < nwg) {
-    zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU, xz, omegaf);
+    if constexpr (K == MOD_ISO)
+      zm_column_iso<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU);
+    else
+      zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU, xz, omegaf);
   } else {
     const long long t = blockIdx.x - nwg;
-    body_stencil<3, MOD_ANISO, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
-    if constexpr (MODE == MODE_RESID && std::is_same<R, double>::value && std::is_same<TO, float>::value) {
+    body_stencil<3, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
+    if constexpr (K == MOD_ANISO && MODE == MODE_RESID && std::is_same<R, double>::value &&
+                  std::is_same<TO, float>::value) {
       if (xz) {   // first FP32 sweep from zero on the shell nodes of this block (as k_jacobi_zero<float>)
         const long long s = t * 256 + threadIdx.x + BX * threadIdx.y;
         if (s < sp.shell) {
@@ -1801,15 +1953,15 @@ __global__ __launch_bounds__(256) void k_batch(const BList *__restrict__ L, R om
   }
 }
 
-// Batched z-marching stencil pass over 3D anisotropic levels of several
+// Batched z-marching stencil pass over 3D levels (of one moduli kind) of several
 // problems: tasks are the column chunks and shell blocks of each entry
 // (k_stencil_zm's workgroups), taken grid-strided by a fixed grid so one
 // captured graph serves any batch.  A workgroup finishes a task before it
 // takes the next, and no task reads LDS after its last barrier, so tasks
 // can reuse the LDS arrays.
-template <typename R, int MODE, typename TO>
+template <typename R, int MODE, typename TO, int K = MOD_ANISO>
 __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_batch_zm(const BList *__restrict__ L, R omega) {
-  __shared__ R sC[21 * ZM_HP];
+  __shared__ R sC[(K == MOD_ISO ? 9 : 21) * ZM_HP];
   __shared__ R sU[9 * ZM_HP];
   const int n = L->n;
   const long long total = L->total;
@@ -1825,12 +1977,17 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_batch_zm(const 
     const long long local = t - E.tile0;
     const Split sp = split_of(E.g);
     const long long nwg = (long long)sp.ntx * sp.nty * E.nzc;
-    if (local < nwg)
-      zm_column<R, MODE, TO>(E.g, sp, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega, E.partial,
-                             E.nzc, (unsigned)local, sC, sU);
-    else
-      body_stencil<3, MOD_ANISO, R, MODE, TO>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
-                                              E.partial ? E.partial + (local - nwg) : nullptr, local - nwg);
+    if (local < nwg) {
+      if constexpr (K == MOD_ISO)
+        zm_column_iso<R, MODE, TO>(E.g, sp, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
+                                   E.partial, E.nzc, (unsigned)local, sC, sU);
+      else
+        zm_column<R, MODE, TO>(E.g, sp, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
+                               E.partial, E.nzc, (unsigned)local, sC, sU);
+    } else {
+      body_stencil<3, K, R, MODE, TO>(E.g, (const R *)E.C, (const R *)E.a, (const R *)E.b, (TO *)E.out, omega,
+                                      E.partial ? E.partial + (local - nwg) : nullptr, local - nwg);
+    }
   }
 }
 
