@@ -32,6 +32,12 @@ mixed precision, with its variants: V(4,4) smoothing, F-cycles, two FP32
 cycles per step, autotuned stencil passes and a phase-field style coupling
 loop of warm-started re-solves.
 
+inclusion257: the isotropic workload, a spherical inclusion (lambda, mu
+doubled, eigenstrain 1e-3) in an isotropic matrix, 257^3 nodes, z = 0
+clamped and the other faces traction-free, FP64 and mixed precision; its
+finest-level sweep moves 88 B per node (u, lambda, mu, f, out) and runs on
+the isotropic z-marching pass.
+
 serving: a stream of 512 independent solve requests (3D spherical
 inclusions and 8-32-grain polycrystals, 33^3 to 129^3 nodes, log-uniform
 sizes, Poisson arrivals at 200 requests/s, seed 2005), each with an input of
@@ -88,6 +94,10 @@ def parse():
                     help="refinement steps per graph replay of the served batch (admission and retirement "
                          "happen between replays)")
     ap.add_argument("--amr", type=int, default=1, help="run the AMR blocks (0 = skip)")
+    ap.add_argument("--iso", type=int, default=257, help="nodes per axis of the isotropic-inclusion block (0 = skip)")
+    ap.add_argument("--iso-steps", type=int, default=5)
+    ap.add_argument("--headline", type=int, default=1,
+                    help="run the headline polycrystal (0: only the other blocks asked for, e.g. to profile them)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only set up the workload, time the finest-level sweeps and a 512 MiB device copy "
                          "(used for hardware-counter runs)")
@@ -183,10 +193,11 @@ def cpu_baseline(spec, gpu_cycles, u_ref=None):
     return out
 
 
-def polycrystal_block(emg, torch, ctx, args, spec, steps, warmup, with_variants):
+def solve_block(emg, torch, ctx, args, spec, steps, warmup, with_variants):
     """FP64 and mixed-precision timed steps (inputs resident in HBM) of one
-    polycrystal workload, the finest-level sweep timings, and optionally the
-    variants (V(4,4), F-cycles, autotuning, coupling loop)."""
+    3D workload (anisotropic polycrystal or isotropic inclusion), the
+    finest-level sweep timings, and optionally the variants (V(4,4),
+    F-cycles, autotuning, coupling loop)."""
     import numpy as np
     import synth
     dev = "cuda:0"
@@ -232,13 +243,17 @@ def polycrystal_block(emg, torch, ctx, args, spec, steps, warmup, with_variants)
     out["levels"] = prob.num_levels()
     ms = prob.kernel_time(0, level=0, precision="fp64", reps=args.kernel_reps)
     nzc = prob.level_zmarch(0, "fp64")
-    out["sweep"] = {"kernel": ("k_stencil_zm<double,JACOBI> finest level (z-marching pass, %d chunks per column)" % nzc
-                               if nzc else "k_stencil<3,ANISO,double,JACOBI> finest level"),
-                    "fp64_ms": ms, "fp64_bytes": 240 * spec.nodes}
+    # algorithmic bytes per node of a sweep: read u, C, f, write u (FP64)
+    bpn = 240 if spec.kind == "aniso" else 88
+    kind = "ANISO" if spec.kind == "aniso" else "ISO"
+    out["sweep"] = {"kernel": ("k_stencil_zm<double,JACOBI,%s> finest level (z-marching pass, %d chunks per column)"
+                               % (kind, nzc) if nzc else "k_stencil<3,%s,double,JACOBI> finest level" % kind),
+                    "fp64_ms": ms, "fp64_bytes": bpn * spec.nodes}
     sols = {"fp64": u64}
     if not args.no_mixed:
         out["sweep"]["fp32_ms"] = prob.kernel_time(0, level=0, precision="mixed", reps=args.kernel_reps)
-        out["sweep"]["fp32_gbs"] = 120 * spec.nodes / (out["sweep"]["fp32_ms"] * 1e-3) / 1e9
+        out["sweep"]["fp32_bytes"] = bpn // 2 * spec.nodes
+        out["sweep"]["fp32_gbs"] = bpn // 2 * spec.nodes / (out["sweep"]["fp32_ms"] * 1e-3) / 1e9
         dt32, st32 = timed("mixed")
         out["mixed"] = summary(dt32, st32, dofs)
         out["mixed"]["speedup_vs_fp64_step"] = dt64 / dt32
@@ -326,6 +341,20 @@ def polycrystal_block(emg, torch, ctx, args, spec, steps, warmup, with_variants)
     out["coupling_loop"] = loop
     prob.close()
     return out, u_ref
+
+
+def iso_block(emg, torch, ctx, args, synth):
+    """The isotropic workload: a spherical inclusion with eigenstrain in an
+    isotropic matrix, FP64 and mixed precision (finest level on the
+    isotropic z-marching pass)."""
+    spec = synth.inclusion_3d(n=args.iso, seed=2004)
+    blk, _ = solve_block(emg, torch, ctx, args, spec, args.iso_steps, 1, with_variants=False)
+    blk["workload"] = (f"isotropic spherical inclusion {args.iso}^3 nodes (seed 2004): matrix lambda 1.5, mu 1; "
+                       f"inclusion r=0.25 with lambda 3, mu 2 and eigenstrain 1e-3; z=0 clamped, other faces "
+                       f"traction-free; V(2,2) to rel. residual 1e-10")
+    sw = blk["sweep"]
+    blk["roofline_frac"] = sw["fp64_bytes"] / (sw["fp64_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    return blk
 
 
 def serving_pool(torch, count):
@@ -502,6 +531,14 @@ def main():
     import paper_2001_04789_amd as emg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not args.headline:
+        ctx = emg.Context(0)
+        out = {"headline": "skipped"}
+        if args.iso:
+            out[f"inclusion{args.iso}"] = iso_block(emg, torch, ctx, args, synth)
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     t_gen = time.perf_counter()
     spec = synth.polycrystal_3d(n=args.n, grains=args.grains, seed=args.seed,
                                 inclusion=None if args.no_sphere else (3.0, 2e-3))
@@ -525,7 +562,7 @@ def main():
                           "copy_reps": args.kernel_reps}))
         return
 
-    head, u_ref = polycrystal_block(emg, torch, ctx, args, spec, args.steps, args.warmup, with_variants=False)
+    head, u_ref = solve_block(emg, torch, ctx, args, spec, args.steps, args.warmup, with_variants=False)
     print(f"[bench] headline done: FP64 {head['fp64']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     dofs = head["dofs"]
     sw = head["sweep"]
@@ -560,15 +597,18 @@ def main():
         if k in head:
             out[k] = head[k]
     if "fp32_ms" in sw:
-        out["fp32_sweep"] = {"avg_ms": sw["fp32_ms"], "gbs": sw["fp32_gbs"], "bytes_per_launch": 120 * head["nodes"]}
+        out["fp32_sweep"] = {"avg_ms": sw["fp32_ms"], "gbs": sw["fp32_gbs"], "bytes_per_launch": sw["fp32_bytes"]}
     if args.small:
         small = synth.polycrystal_3d(n=129, grains=16, seed=2002)
-        blk, _ = polycrystal_block(emg, torch, ctx, args, small, args.small_steps, 2, with_variants=True)
+        blk, _ = solve_block(emg, torch, ctx, args, small, args.small_steps, 2, with_variants=True)
         blk["workload"] = "polycrystal 129^3 nodes, 16 grains (seed 2002), periodic x/y, uniaxial z 1e-3"
         blk["roofline_frac"] = blk["sweep"]["fp64_bytes"] / (blk["sweep"]["fp64_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
         blk["traffic"] = sweep_traffic("jacobi_sweep_polycrystal129_counters.md")
         out["polycrystal129"] = blk
         print("[bench] 129^3 block done", file=sys.stderr, flush=True)
+    if args.iso:
+        out[f"inclusion{args.iso}"] = iso_block(emg, torch, ctx, args, synth)
+        print("[bench] isotropic block done", file=sys.stderr, flush=True)
     if args.amr:
         out["amr_efficiency"] = amr_efficiency(emg, ctx, synth)
         out["amr_microstructure"] = amr_microstructure(emg, ctx, synth)
