@@ -6,7 +6,8 @@ the output's magnitude), on grids with non-periodic, ragged x and y,
 Neumann and traction faces, and periodic x and z.  Solves (FP64, mixed,
 two FP32 cycles per refinement step, F-cycles) and ragged batches whose
 isotropic finest levels take the z-marching pass give the displacement and
-cycle count of the same solves on the tile kernel."""
+cycle count of the same solves on the tile kernel; so do composite (AMR)
+solves whose base level takes it, isotropic or anisotropic."""
 import json
 
 import numpy as np
@@ -174,3 +175,37 @@ def test_iso_zmarch_in_batches(emg, ctx, tmp_path, monkeypatch, precision):
         emg.autotune_reset()
         for p in probs:
             p.close()
+
+
+@pytest.mark.parametrize("kind", ["iso", "aniso"])
+def test_zmarch_under_amr(emg, ctx, tmp_path, monkeypatch, kind):
+    """A composite (AMR) solve whose 97^3 base level takes the z-marching
+    pass equals, bit for bit and in cycle count, the same solve on the tile
+    kernel, in FP64 and mixed precision (base level and refined box)."""
+    ap = synth.smooth_amr(dim=3, levels=2, n=97, kind=kind)
+    prob = emg.Problem.from_amr(ctx, ap)
+    cache = tmp_path / "tune.json"
+    iso = "/iso" if kind == "iso" else ""
+    shapes = [prob.level_shape(0)[0]] + [tuple(prob.amr_level_shape(k)) for k in range(1, prob.amr_num_levels())]
+
+    def entries(v):
+        return {f"gfx950/{pre}/{m[0]}x{m[1]}x{m[2]}/p0{iso}": v for m in shapes for pre in ("fp64", "fp32")}
+    try:
+        force(emg, monkeypatch, cache, entries(0))
+        ref = {}
+        for prec in ("fp64", "mixed"):
+            st = prob.solve(rtol=1e-10, max_cycles=400, precision=prec)
+            ref[prec] = (st["cycles"], prob.displacement().copy(), prob.amr_displacement(1).copy())
+        for nzc in (1, 3):
+            force(emg, monkeypatch, cache, entries(nzc))
+            for prec in ("fp64", "mixed"):
+                assert prob.level_zmarch(0, prec) == nzc
+                print(f"[gpu] z-march under AMR {kind} chunks {nzc} {prec}", flush=True)
+                st = prob.solve(rtol=1e-10, max_cycles=400, precision=prec)
+                assert st["cycles"] == ref[prec][0], (nzc, prec)
+                np.testing.assert_array_equal(prob.displacement(), ref[prec][1])
+                np.testing.assert_array_equal(prob.amr_displacement(1), ref[prec][2])
+    finally:
+        monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
+        emg.autotune_reset()
+        prob.close()
