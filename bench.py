@@ -94,6 +94,8 @@ def parse():
                     help="refinement steps per graph replay of the served batch (admission and retirement "
                          "happen between replays)")
     ap.add_argument("--amr", type=int, default=1, help="run the AMR blocks (0 = skip)")
+    ap.add_argument("--amr-blocks", default="efficiency,microstructure,penny",
+                    help="which AMR blocks to run (comma list of efficiency, microstructure, penny)")
     ap.add_argument("--iso", type=int, default=257, help="nodes per axis of the isotropic-inclusion block (0 = skip)")
     ap.add_argument("--iso-steps", type=int, default=5)
     ap.add_argument("--headline", type=int, default=1,
@@ -520,6 +522,18 @@ def amr_penny_crack(emg, ctx, synth):
     return out
 
 
+def amr_blocks(emg, ctx, synth, args):
+    pick = set(args.amr_blocks.split(","))
+    out = {}
+    if "efficiency" in pick:
+        out["amr_efficiency"] = amr_efficiency(emg, ctx, synth)
+    if "microstructure" in pick:
+        out["amr_microstructure"] = amr_microstructure(emg, ctx, synth)
+    if "penny" in pick:
+        out["amr_penny_crack"] = amr_penny_crack(emg, ctx, synth)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -536,6 +550,8 @@ def main():
         out = {"headline": "skipped"}
         if args.iso:
             out[f"inclusion{args.iso}"] = iso_block(emg, torch, ctx, args, synth)
+        if args.amr:
+            out.update(amr_blocks(emg, ctx, synth, args))
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -610,9 +626,7 @@ def main():
         out[f"inclusion{args.iso}"] = iso_block(emg, torch, ctx, args, synth)
         print("[bench] isotropic block done", file=sys.stderr, flush=True)
     if args.amr:
-        out["amr_efficiency"] = amr_efficiency(emg, ctx, synth)
-        out["amr_microstructure"] = amr_microstructure(emg, ctx, synth)
-        out["amr_penny_crack"] = amr_penny_crack(emg, ctx, synth)
+        out.update(amr_blocks(emg, ctx, synth, args))
         print("[bench] AMR blocks done", file=sys.stderr, flush=True)
     nserve = max(args.serve_requests, args.serve_light_requests if args.serve_light_rate > 0 else 0)
     if nserve > 0:
