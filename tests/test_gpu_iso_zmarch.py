@@ -209,3 +209,36 @@ def test_zmarch_under_amr(emg, ctx, tmp_path, monkeypatch, kind):
         monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
         emg.autotune_reset()
         prob.close()
+
+
+def test_autotune_isotropic_levels(emg, ctx, tmp_path, monkeypatch):
+    """emg_autotune measures the isotropic z-marching pass beside the tile
+    shapes: on a 97^3 inclusion every level is tuned, the level-0 entries
+    (keyed ".../iso") hold a valid variant that emg_level_zmarch reports, and
+    the tuned solves equal the untuned ones bit for bit."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("EMG_TUNE_CACHE", str(cache))
+    emg.autotune_reset()
+    spec = synth.inclusion_3d(n=97, seed=4)
+    prob = emg.Problem.from_spec(ctx, spec)
+    try:
+        ref = {}
+        for p in ("fp64", "mixed"):
+            st = prob.solve(rtol=1e-10, max_cycles=400, precision=p)
+            ref[p] = (st["cycles"], prob.displacement().copy())
+        print("[gpu] autotune isotropic 97^3", flush=True)
+        for p in ("fp64", "mixed"):
+            assert prob.autotune(p, reps=5) == prob.num_levels()
+        table = json.loads(cache.read_text())
+        for p, pre in (("fp64", "fp64"), ("mixed", "fp32")):
+            v = table[stencil_key(prob, spec, 0, pre)]
+            assert -3 <= v <= 95 // 8, v
+            assert prob.level_zmarch(0, p) == max(v, 0)
+            st = prob.solve(rtol=1e-10, max_cycles=400, precision=p)
+            assert st["cycles"] == ref[p][0]
+            np.testing.assert_array_equal(prob.displacement(), ref[p][1])
+        assert all("/iso" in k for k in table)
+    finally:
+        monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
+        emg.autotune_reset()
+        prob.close()
