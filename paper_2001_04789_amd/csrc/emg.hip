@@ -926,15 +926,20 @@ void record_mixed_iter(emg_problem *p, int nu1, int nu2, float omega, bool fcyc)
   const int eb = mixed_result_buf(p, nu1, nu2);
   hipLaunchKernelGGL(k_add_correction, dim3((unsigned)std::min<long long>((nd0 + 255) / 256, 8192)), dim3(256), 0,
                      p->stream, nd0, L0.u64[0], L0.u32[eb], p->ctl);
-  // on anisotropic z-marching levels the residual pass also writes the FP32
-  // cycle's first sweep from zero (into u32[0]), which the cycle then skips
-  const int nzc = p->K == MOD_ANISO ? zm_plan<double>(p, L0.g) : 0;
+  // on z-marching levels the residual pass also writes the FP32 cycle's
+  // first sweep from zero (into u32[0]), which the cycle then skips
+  const int nzc = zm_plan<double>(p, L0.g);
   if (nzc > 0) {
     const Split sp = split_of(L0.g);
     const unsigned blocks = (unsigned)((long long)sp.ntx * sp.nty * nzc + sp.sblocks);
-    hipLaunchKernelGGL((k_stencil_zm<double, MODE_RESID, float>), dim3(blocks), kBlock, 0, p->stream, L0.g,
-                       (const double *)L0.C64, (const double *)L0.u64[0], (const double *)L0.f64, L0.f32, 0.0,
-                       p->partial, p->ctl, nzc, L0.u32[0], omega);
+    if (p->K == MOD_ISO)
+      hipLaunchKernelGGL((k_stencil_zm<double, MODE_RESID, float, MOD_ISO>), dim3(blocks), kBlock, 0, p->stream,
+                         L0.g, (const double *)L0.C64, (const double *)L0.u64[0], (const double *)L0.f64, L0.f32, 0.0,
+                         p->partial, p->ctl, nzc, L0.u32[0], omega);
+    else
+      hipLaunchKernelGGL((k_stencil_zm<double, MODE_RESID, float>), dim3(blocks), kBlock, 0, p->stream, L0.g,
+                         (const double *)L0.C64, (const double *)L0.u64[0], (const double *)L0.f64, L0.f32, 0.0,
+                         p->partial, p->ctl, nzc, L0.u32[0], omega);
   } else {
     launch_stencil<double, MODE_RESID, float>(p, L0, L0.u64[0], L0.f64, L0.f32, 0.0, p->partial, p->ctl);
   }

@@ -674,12 +674,16 @@ __device__ __forceinline__ void zm_column(const Geom &g, const Split &sp, const 
 // about 13 global loads (lambda, mu, displacement of the next plane with its
 // halo, right-hand side) instead of about 74.  Norm partials go to the tile
 // kernel's 64 x 4 slots.  LDS slot layout: ((slot * 3 + component) * HP +
-// position), lambda and mu in components 0 and 1 of the moduli ring.
+// position), lambda and mu in components 0 and 1 of the moduli ring.  xz
+// (FP64 residual to FP32 only): also the FP32 cycle's first sweep from zero,
+// as in zm_column.
 template <typename R, int MODE, typename TO>
 __device__ __forceinline__ void zm_column_iso(const Geom &g, const Split &sp, const R *__restrict__ C,
                                               const R *__restrict__ u, const R *__restrict__ f, TO *__restrict__ out,
                                               R omega, double *__restrict__ partial, int nzc, unsigned w,
-                                              R *__restrict__ sC, R *__restrict__ sU) {
+                                              R *__restrict__ sC, R *__restrict__ sU, float *__restrict__ xz = nullptr,
+                                              float omegaf = 0.0f) {
+  constexpr bool JZ = MODE == MODE_RESID && std::is_same<R, double>::value && std::is_same<TO, float>::value;
   constexpr int TX = BX, TY = BY, HX = ZM_HX, HY = ZM_HY, HP = ZM_HP, NH = ZM_NH, PL = 3 * HP;
   constexpr int HW = (NH + 63) / 64;
   const int tx = threadIdx.x, ty = threadIdx.y, t = ty * TX + tx;
@@ -785,6 +789,13 @@ __device__ __forceinline__ void zm_column_iso(const Geom &g, const Split &sp, co
     interior_rows<3, MOD_ISO, R, RingU, int>(sC, HP, RingU{sU}, n, om, op, i2h, ih2, acc, dg, nullptr, 0, nullptr, uc);
     double nrm = 0.0;
     const unsigned o = plane(z) + r0;
+    float cdf[3];   // JZ: the interior-row diagonal of k_jacobi_zero<float> (diag_at on the rounded moduli)
+    if constexpr (JZ) {
+      if (xz && inbox) {
+        const int pn[3] = {x0 + tx, y0 + ty, z};
+        diag_at<3, MOD_ISO, float, double>(g, C, (long long)o, pn, ROW_INT, cdf);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       if (inbox) {
@@ -795,6 +806,12 @@ __device__ __forceinline__ void zm_column_iso(const Geom &g, const Split &sp, co
           const R r = xf[i] - acc[i];
           *oi = MODE == MODE_RESID ? TO(r) : TO(uc[i] + omega * r / dg[i]);
           nrm += double(r) * double(r);
+          if constexpr (JZ) {
+            if (xz) {
+              const float r32 = TO(r);
+              *(float *)((char *)(xz + i * N) + o * 4u) = omegaf * r32 / cdf[i];
+            }
+          }
         }
       }
     }
@@ -833,14 +850,13 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom
   const unsigned nwg = (unsigned)sp.ntx * sp.nty * nzc;
   if (blockIdx.x < nwg) {
     if constexpr (K == MOD_ISO)
-      zm_column_iso<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU);
+      zm_column_iso<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU, xz, omegaf);
     else
       zm_column<R, MODE, TO>(g, sp, C, u, f, out, omega, partial, nzc, blockIdx.x, sC, sU, xz, omegaf);
   } else {
     const long long t = blockIdx.x - nwg;
     body_stencil<3, K, R, MODE, TO>(g, C, u, f, out, omega, partial ? partial + t : nullptr, t);
-    if constexpr (K == MOD_ANISO && MODE == MODE_RESID && std::is_same<R, double>::value &&
-                  std::is_same<TO, float>::value) {
+    if constexpr (MODE == MODE_RESID && std::is_same<R, double>::value && std::is_same<TO, float>::value) {
       if (xz) {   // first FP32 sweep from zero on the shell nodes of this block (as k_jacobi_zero<float>)
         const long long s = t * 256 + threadIdx.x + BX * threadIdx.y;
         if (s < sp.shell) {
@@ -849,7 +865,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? 1 : 2) void k_stencil_zm(Geom
           const long long n = ((long long)p[2] * g.m[1] + p[1]) * g.m[0] + p[0];
           const int cls = row_class(g, p);
           float dg[3];
-          diag_at<3, MOD_ANISO, float, double>(g, C, n, p, cls, dg);
+          diag_at<3, K, float, double>(g, C, n, p, cls, dg);
 #pragma unroll
           for (int i = 0; i < 3; i++) {
             const long long q = i * g.N + n;
