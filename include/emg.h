@@ -204,8 +204,9 @@ emg_status emg_num_levels(emg_problem *p, int *levels);
 /* Stencil pass used on a level (introspection, e.g. for tests and profiles):
  * *chunks > 0 if stencil passes of that level in that precision (EMG_FP64
  * for FP64 passes, EMG_MIXED for the FP32 ones) run the z-marching kernel
- * (3D anisotropic levels large enough to give every CU a workgroup), with
- * that many plane runs per column; 0 if they run the tile kernel. */
+ * (3D levels, isotropic or anisotropic, large enough to give every CU its
+ * resident workgroups), with that many plane runs per column; 0 if they run
+ * the tile kernel. */
 emg_status emg_level_zmarch(emg_problem *p, int level, int precision, int *chunks);
 emg_status emg_level_shape(emg_problem *p, int level, int64_t m[3], double h[3]);
 /* moduli of a level (FP64, layout of emg_set_moduli), device pointer out */
@@ -376,7 +377,7 @@ emg_status emg_kernel_time(emg_problem *p, int kernel, int level, int precision,
  * unchanged (launch configurations, not steps of the method).  For every
  * multigrid level, in `precision` (EMG_FP64: FP64 passes, EMG_MIXED: the FP32
  * ones): the Jacobi sweep with the tile kernel in tiles of 64 x 4, 64 x 2,
- * 128 x 2 and 32 x 8 nodes and, on 3D anisotropic levels wide enough (at least
+ * 128 x 2 and 32 x 8 nodes and, on 3D levels wide enough (at least
  * 64 x 4 interior nodes per plane and 8 planes), with the z-marching pass at
  * every chunk count leaving at least 8 planes per chunk; and, on levels with a
  * coarser one, the restriction from the level and the interpolation onto it in
