@@ -3,7 +3,7 @@ node): forced through the EMG_TUNE_CACHE table at several chunk counts, the
 finest-level operator, residual and Jacobi sweep equal the tile kernel's bit
 for bit and the oracle element by element (FP64 to 1e-12, FP32 to 2e-5 of
 the output's magnitude), on grids with non-periodic, ragged x and y,
-Neumann and traction faces, and periodic x and z.  Solves (FP64, mixed,
+Neumann and traction faces, periodic x and z, and periodic x and y.  Solves (FP64, mixed,
 two FP32 cycles per refinement step, F-cycles) and ragged batches whose
 isotropic finest levels take the z-marching pass give the displacement and
 cycle count of the same solves on the tile kernel; so do composite (AMR)
@@ -66,6 +66,8 @@ CASES = {
     "iso_nonperiodic": dict(n=(97, 97, 65), bc=("dirichlet", "traction", "neumann", "traction", "traction", "neumann")),
     # periodic x (96 stored nodes: a ragged second column) and z (64 planes, wrapped), non-periodic y
     "iso_periodic_xz": dict(n=(97, 97, 65), bc=("periodic", "periodic", "dirichlet", "traction", "periodic", "periodic")),
+    # periodic x and y (96 stored nodes each: ragged second column, wrapped halo rows), Dirichlet z
+    "iso_periodic_xy": dict(n=(97, 97, 65), bc=("periodic", "periodic", "periodic", "periodic", "dirichlet", "dirichlet")),
 }
 
 
