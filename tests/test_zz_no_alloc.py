@@ -55,10 +55,10 @@ def test_noalloc_batch_matches_batch_twice(emg, ctx, precision):
 
 
 def test_noalloc_batch_inner_cycles_and_zmarch(emg, ctx):
-    """A member on the z-marching pass (97^3 polycrystal) and two FP32 cycles
-    per refinement step; then a smaller call."""
-    _batch_then_noalloc(emg, ctx, [synth.polycrystal_3d(n=97, grains=16, seed=5), synth.inclusion_2d(n=65)],
-                        "mixed", inner_cycles=2)
+    """Members on the z-marching pass (97^3 polycrystal and isotropic
+    inclusion) and two FP32 cycles per refinement step; then a smaller call."""
+    _batch_then_noalloc(emg, ctx, [synth.polycrystal_3d(n=97, grains=16, seed=5), synth.inclusion_3d(n=97, seed=6),
+                                   synth.inclusion_2d(n=65)], "mixed", inner_cycles=2)
     _batch_then_noalloc(emg, ctx, [synth.inclusion_3d(n=17, seed=1)], "fp64", check_every=1)
 
 
