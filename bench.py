@@ -86,8 +86,9 @@ def parse():
     ap.add_argument("--serve-light-rate", type=float, default=40.0,
                     help="arrival rate of a second, shorter served stream below the GPU's capacity (0 = skip)")
     ap.add_argument("--serve-light-requests", type=int, default=160)
-    ap.add_argument("--serve-nu", type=int, default=4, help="pre/post Jacobi sweeps per level of the served solves "
-                    "(the served stream fixes no sweep count; V(4,4) serves more solves/s than V(2,2))")
+    ap.add_argument("--serve-nu", type=int, default=6, help="pre/post Jacobi sweeps per level of the served solves "
+                    "(the served stream fixes no sweep count; V(6,6) serves the most solves/s of V(3,3) to "
+                    "V(10,10))")
     ap.add_argument("--serve-inner", type=int, default=2, help="FP32 cycles per FP64 refinement step of the "
                     "served solves")
     ap.add_argument("--serve-check-every", type=int, default=1,
