@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--small-steps", type=int, default=10)
     ap.add_argument("--serve-requests", type=int, default=512, help="served stream length (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-slots", type=int, default=16, help="concurrent requests on the GPU")
+    ap.add_argument("--serve-slots", type=int, default=32, help="concurrent requests on the GPU")
     ap.add_argument("--serve-light-rate", type=float, default=40.0,
                     help="arrival rate of a second, shorter served stream below the GPU's capacity (0 = skip)")
     ap.add_argument("--serve-light-requests", type=int, default=160)
