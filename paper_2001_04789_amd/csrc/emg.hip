@@ -333,8 +333,7 @@ bool tune_save_locked(const TuneTable &t) {
 // interior nodes (64 x 4 tiles fully inside the level in x and y) and at
 // least 8 planes per chunk; tile shapes -1..-3; a table value outside that
 // range is ignored.
-bool zm_valid(const Geom &g, int nzc, int kind = MOD_ANISO) {
-  (void)kind;   // both moduli kinds have a z-marching pass
+bool zm_valid(const Geom &g, int nzc) {
   const Split sp = split_of(g);
   if (nzc <= 0) return nzc > -TS_COUNT;
   return g.dim == 3 && sp.inner > 0 && g.m[0] >= BX && g.m[1] >= BY && nzc >= 1 && nzc <= sp.ntz / 8;
@@ -348,7 +347,7 @@ bool tune_find(int device, int rbytes, const Geom &g, int *nzc, int kind = MOD_A
   if (it == t.table.end()) return false;
   const bool ok = strcmp(what, "/tail") == 0 ? it->second >= 0
                  : *what                    ? (it->second >= 0 && it->second < TS_COUNT)
-                                            : zm_valid(g, it->second, kind);
+                                            : zm_valid(g, it->second);
   if (!ok) return false;
   *nzc = it->second;
   return true;
@@ -2828,7 +2827,7 @@ emg_status emg_autotune(emg_problem *p, int precision, int reps, int retune, int
     if (retune || !tune_find(p->ctx->device, rb, g, &have, p->K)) {
       std::vector<int> cands;
       for (int s = 0; s < TS_COUNT; s++) cands.push_back(-s);
-      if (zm_valid(g, 1, p->K))
+      if (zm_valid(g, 1))
         for (int c = 1; c <= sp.ntz / 8; c++) cands.push_back(c);
       double best_ms = 0.0;
       int best = 0;
