@@ -791,9 +791,11 @@ __device__ __forceinline__ void zm_column_iso(const Geom &g, const Split &sp, co
     const unsigned o = plane(z) + r0;
     float cdf[3];   // JZ: the interior-row diagonal of k_jacobi_zero<float> (diag_at on the rounded moduli)
     if constexpr (JZ) {
-      if (xz && inbox) {
+      if (xz && inbox) {   // the same diag_at, reading lambda and mu from the ring (component stride HP)
+        Geom gr = g;
+        gr.SC = HP;
         const int pn[3] = {x0 + tx, y0 + ty, z};
-        diag_at<3, MOD_ISO, float, double>(g, C, (long long)o, pn, ROW_INT, cdf);
+        diag_at<3, MOD_ISO, float, double>(gr, sC, (long long)n, pn, ROW_INT, cdf);
       }
     }
 #pragma unroll
