@@ -18,7 +18,12 @@
  *   - A pointer argument is a host pointer unless the call's `on_device`
  *     flag is set (then it is a device pointer on the problem's GPU, e.g. a
  *     torch tensor's data_ptr()).  The library copies what it is given; the
- *     caller keeps ownership of every buffer it passes.
+ *     caller keeps ownership of every buffer it passes.  A device buffer must
+ *     hold its final contents when the call is made: the problem's stream
+ *     does not wait on the caller's streams (synchronize the producing
+ *     stream first, or hand the library that stream with emg_set_stream).
+ *     Calls that write device buffers have finished writing them when they
+ *     return.
  *   - Each problem owns its device memory and one HIP stream (created at
  *     default priority); all of its work runs on that stream.  Calls on one
  *     problem must not overlap; different problems may be used from

@@ -144,6 +144,15 @@ def check(status: int, where: str = "emg") -> int:
     return status
 
 
+def _ready(t):
+    """Device buffers handed to the library must hold their final contents
+    when the call is made: the problem's stream does not wait on torch's, so
+    torch's work queued on its current stream of the tensor's device (fills,
+    copies, kernels producing the tensor) is finished first."""
+    import torch
+    torch.cuda.current_stream(t.device).synchronize()
+
+
 def _host_or_device(a, dtype=np.float64):
     """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
     if a is None:
@@ -151,6 +160,7 @@ def _host_or_device(a, dtype=np.float64):
     if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
         if a.is_cuda:
             assert a.is_contiguous(), "device tensors must be contiguous"
+            _ready(a)
             return c_void_p(a.data_ptr()), 1, a
         a = a.numpy()
     arr = np.ascontiguousarray(a, dtype=dtype)
@@ -158,8 +168,9 @@ def _host_or_device(a, dtype=np.float64):
 
 
 def _dev(t):
-    """Device pointer of a contiguous torch tensor on the GPU."""
+    """Device pointer of a contiguous torch tensor on the GPU (after _ready)."""
     assert hasattr(t, "is_cuda") and t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    _ready(t)
     return c_void_p(t.data_ptr())
 
 
@@ -261,7 +272,7 @@ class Server:
             if dev:
                 assert a.is_cuda and a.is_contiguous() and str(a.dtype) == "torch.float64"
                 keep.append(a)
-                return c_void_p(a.data_ptr())
+                return _dev(a)
             x = np.ascontiguousarray(a, dtype=np.float64)
             keep.append(x)
             return x.ctypes.data_as(c_void_p)
