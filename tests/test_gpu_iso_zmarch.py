@@ -244,3 +244,36 @@ def test_autotune_isotropic_levels(emg, ctx, tmp_path, monkeypatch):
         monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
         emg.autotune_reset()
         prob.close()
+
+
+def test_iso_zmarch_mixed_periodic(emg, ctx, tmp_path, monkeypatch):
+    """Mixed-precision solves on a grid periodic in x (ragged second column)
+    and z, where the FP64 residual pass of each refinement step also writes
+    the FP32 cycle's zero-start sweep on the z-marching pass: equal, bit for
+    bit and in cycle count, to the solves on the tile kernel (which runs that
+    sweep as a pass of its own)."""
+    c = CASES["iso_periodic_xz"]
+    spec = synth.random_problem(3, c["n"], c["bc"], "iso", seed=23, with_body=True,
+                                lo=(0.0, -0.2, 0.1), hi=(1.0, 0.8, 0.8))
+    prob = emg.Problem.from_spec(ctx, spec)
+    cache = tmp_path / "tune.json"
+    keys = [stencil_key(prob, spec, 0, pre) for pre in ("fp64", "fp32")]
+    variants = [dict(precision="mixed"), dict(precision="mixed", inner_cycles=2)]
+    try:
+        force(emg, monkeypatch, cache, {k: 0 for k in keys})
+        ref = []
+        for v in variants:
+            st = prob.solve(rtol=1e-10, max_cycles=400, **v)
+            ref.append((st["cycles"], prob.displacement().copy()))
+        for nzc in (2, 7):
+            force(emg, monkeypatch, cache, {k: nzc for k in keys})
+            assert prob.level_zmarch(0, "fp64") == nzc
+            for v, (cyc, u) in zip(variants, ref):
+                print(f"[gpu] iso z-march mixed periodic chunks {nzc} {v}", flush=True)
+                st = prob.solve(rtol=1e-10, max_cycles=400, **v)
+                assert st["cycles"] == cyc, (nzc, v)
+                np.testing.assert_array_equal(prob.displacement(), u)
+    finally:
+        monkeypatch.delenv("EMG_TUNE_CACHE", raising=False)
+        emg.autotune_reset()
+        prob.close()
